@@ -1,0 +1,200 @@
+/*
+ * libnwmine -- comparable-corpus mining hot path on one AMD Instinct MI355X
+ * (gfx950): score every source x target sentence pair of a batch of document
+ * pairs, align each pair's two sentence sequences with Needleman-Wunsch, keep
+ * the aligned pairs whose similarity reaches the threshold, and differentiate
+ * the alignment score for tuning.
+ *
+ * Method: Wolk & Marasek, "Unsupervised comparable corpora preparation and
+ * exploration for bi-lingual translation equivalents", arXiv 1512.01641.
+ *   Sec. 4    similarity = a classifier's likelihood in [0,1] (SVM distance
+ *             through a sigmoid) over a dictionary with translation
+ *             probabilities; sequence aligner maximising the summed pair
+ *             similarity; pairs below the threshold are excluded.
+ *   Sec. 5    one session over many document pairs, multi-threaded.
+ *   Sec. 5.1  Needleman-Wunsch: similarity matrix, gap penalty, DP matrix
+ *             with (0,0) = 0, first row/column initialised, every cell from
+ *             its top, left and top-left neighbours (Figs. 1-2, eq. (1)); the
+ *             GPU computes each anti-diagonal in parallel.
+ *   Sec. 5.2  threshold and penalty are tuned against reference alignments.
+ *
+ * Conventions for every entry point
+ *   - Pointers marked "device" are HIP device (or managed) memory on the
+ *     context's device; "host" pointers are read before the call returns.
+ *     The caller owns every buffer; the library keeps no pointer to caller
+ *     memory after a call returns.
+ *   - Host-visible arguments are validated synchronously.  On success the
+ *     work is enqueued on `stream` (a hipStream_t, NULL = the null stream)
+ *     and the call returns NWM_OK; outputs are valid once the stream has
+ *     reached that point.  Kernel launch failures return NWM_EDEVICE.
+ *   - No entry point allocates device memory except nwm_plan_create.
+ *   - A context (and the plans made from it) must be used by one host thread
+ *     at a time.  Calls that overlap on one stream are ordered by it.
+ *   - Token ids outside [0, V) and non-finite similarities are not checked
+ *     (undefined results).
+ */
+#ifndef LIBNWMINE_H
+#define LIBNWMINE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NWM_OK = 0,
+  NWM_EINVAL = 1,       /* NULL required pointer, negative size, non-finite gap/threshold */
+  NWM_ESHAPE = 2,       /* arguments disagree with each other or with the plan */
+  NWM_ENOMEM = 3,       /* allocation failed (plan creation only) */
+  NWM_EDEVICE = 4,      /* a HIP call or kernel launch failed */
+  NWM_EUNSUPPORTED = 5  /* a documented size limit is exceeded */
+} nwm_status;
+
+/* Operand type of the similarity contraction.  The DP always runs in FP32. */
+typedef enum { NWM_FP32 = 0, NWM_BF16 = 1 } nwm_prec;
+
+typedef struct nwm_ctx nwm_ctx;
+typedef struct nwm_plan nwm_plan;
+
+/* Bilingual dictionary D (Sec. 4: a dictionary with translation
+ * probabilities): V x V sparse, CSR.  Row t lists target words u with
+ * probability d = D[t][u].  Device arrays; max_deg is a host-known upper bound
+ * on the entries of any row. */
+typedef struct {
+  int32_t V;
+  int32_t max_deg;
+  const int32_t *row_off;  /* device [V+1] */
+  const int32_t *col;      /* device [row_off[V]], values in [0, V) */
+  const float *val;        /* device [row_off[V]] */
+} nwm_dict;
+
+/* Logistic scorer over the features (S_raw, rho):
+ *   z = w0 * S_raw + w1 * rho + b,   S = 1 / (1 + exp(-z))
+ * (Sec. 4: a classifier distance mapped into [0,1] by a sigmoid). */
+typedef struct {
+  float w0, w1, b;
+} nwm_scorer;
+
+/* A batch of B document pairs.  Pair b has n_b source and m_b target
+ * sentences.  Sentences of all pairs are concatenated in pair order (pair b
+ * owns source sentences [sum_{c<b} n_c, sum_{c<=b} n_c), likewise targets);
+ * each sentence is a bag of token ids given as a CSR over tokens. */
+typedef struct {
+  int32_t B;                 /* number of document pairs, >= 0 */
+  int32_t V;                 /* hashed vocabulary size of both languages */
+  const int32_t *n_host;     /* host [B] source sentence counts, >= 0 */
+  const int32_t *m_host;     /* host [B] target sentence counts, >= 0 */
+  int64_t src_tokens;        /* host: src_off[sum n], total source tokens */
+  int64_t tgt_tokens;        /* host: tgt_off[sum m], total target tokens */
+  int32_t max_sent_tokens;   /* host: upper bound on the tokens of any source sentence */
+  const int64_t *src_off;    /* device [sum n + 1] token offsets, src_off[0] = 0 */
+  const int32_t *src_tok;    /* device [src_tokens] token ids in [0, V) */
+  const int64_t *tgt_off;    /* device [sum m + 1] */
+  const int32_t *tgt_tok;    /* device [tgt_tokens] */
+} nwm_batch;
+
+/* Buffer sizes a plan needs (all chosen by nwm_plan_create). */
+typedef struct {
+  size_t S_elems;    /* floats in S, S_raw and grad_S: sum_b n_b * m_b */
+  size_t kept_cap;   /* (i, j) pair capacity of `kept`: sum_b min(n_b, m_b) */
+  size_t tb_bytes;   /* bytes of the opaque traceback buffer */
+  size_t ws_bytes;   /* bytes of the workspace */
+} nwm_sizes;
+
+/* --- context -------------------------------------------------------------- */
+
+/* Create a context bound to HIP device `hip_device`.  Fails with NWM_EDEVICE
+ * if the device is absent or not gfx950. */
+nwm_status nwm_create(nwm_ctx **ctx, int hip_device);
+void nwm_destroy(nwm_ctx *ctx);
+const char *nwm_strerror(nwm_status s);
+
+/* --- plan ----------------------------------------------------------------- */
+
+/* Plan a batch (host-only work plus one small upload): per-pair offsets of S,
+ * kept pairs and traceback, the tile lists of the contraction and the
+ * longest-first order of the DP, and the workspace layout.  Uses only the
+ * batch's host fields and `max_deg`; the device pointers of `batch` may be
+ * NULL here.  Limits (NWM_EUNSUPPORTED): V <= 32768, max_deg <= 64,
+ * m_b <= 16383, max_sent_tokens * max_deg <= 1024.
+ * Allocates one small device buffer of per-pair metadata owned by the plan. */
+nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg,
+                           nwm_prec prec, nwm_plan **plan);
+nwm_status nwm_plan_sizes(const nwm_plan *plan, nwm_sizes *sizes);
+void nwm_plan_destroy(nwm_plan *plan);
+
+/* --- hot path --------------------------------------------------------------- */
+
+/* Similarity of every sentence pair of every document pair (Sec. 4).
+ *   S_raw[i][j] = (1/l_i) * sum_u T[i][u] * Y[j][u],  T = (count of each token
+ *     of source sentence i) . D,  Y[j][u] = [u occurs in target sentence j]
+ *     (l_i = tokens of source sentence i; S_raw = 0 when l_i = 0);
+ *   rho[i][j]   = min(l_i, l'_j) / max(l_i, l'_j)  (1 when both are 0);
+ *   S = sigmoid(w0 * S_raw + w1 * rho + b).
+ * The contraction runs on MFMA with `prec` operands and FP32 accumulation.
+ * Outputs (device, FP32, row-major n_b x m_b blocks, pair b at element
+ * offset sum_{c<b} n_c m_c): S [S_elems]; S_raw [S_elems] or NULL.
+ * ws: device workspace of ws_bytes, contents need not persist. */
+nwm_status nwm_score_pairs(nwm_plan *plan, const nwm_batch *batch, const nwm_dict *dict,
+                           nwm_scorer scorer, float *S, float *S_raw, void *ws, void *stream);
+
+/* Needleman-Wunsch global alignment of every pair (Sec. 5.1) and the
+ * threshold filter (Sec. 4).  For pair b, with H[0][0] = 0,
+ * H[i][0] = fl32(i*gap), H[0][j] = fl32(j*gap) and for i, j >= 1
+ *   up = H[i-1][j] + gap, left = H[i][j-1] + gap, diag = H[i-1][j-1] + S[i-1][j-1]
+ *   H[i][j] = first maximum of (up, left, diag) in that order (FP32, compare
+ *   with '>', so exact ties resolve UP > LEFT > DIAG).
+ * The traceback from (n, m) yields the aligned (DIAG) pairs.
+ *   S       device [S_elems] similarity, layout as nwm_score_pairs;
+ *   gap     signed additive gap score (e.g. -0.2), finite;
+ *   threshold  pairs with S >= threshold are kept, finite;
+ *   score   device [B] H[n_b][m_b];
+ *   n_diag  device [B] number of aligned pairs k_b (the gap count is n+m-2k);
+ *   kept    device int32 [2 * kept_cap]: pair b's kept (i, j) pairs, 0-based,
+ *           ascending, start at pair index sum_{c<b} min(n_c, m_c);
+ *   n_kept  device [B];
+ *   tb      device [tb_bytes] opaque traceback (direction bits + path), read
+ *           by nwm_align_backward;
+ *   ws      device [ws_bytes]. */
+nwm_status nwm_align_batch(nwm_plan *plan, const float *S, float gap, float threshold,
+                           float *score, int32_t *n_diag, int32_t *kept, int32_t *n_kept,
+                           void *tb, void *ws, void *stream);
+
+/* Backward of L = sum_b grad_score[b] * Score_b + sum_ij grad_S_extra[ij] * S[ij]
+ * through the alignment and the logistic scorer.  The NW score is a maximum
+ * of affine path sums, so dScore_b/dS = P_b (indicator of the aligned cells
+ * of the traced path) and dScore_b/dgap = n_b + m_b - 2 k_b; the chain through
+ * the sigmoid uses dS/dz = S (1 - S).
+ *   tb, n_diag   from nwm_align_batch on the same plan;
+ *   grad_score   device [B] dL/dScore_b (FP32);
+ *   grad_S_extra device [S_elems] or NULL: extra dense dL/dS;
+ *   grad_S       device [S_elems] or NULL: receives dL/dS (FP32);
+ *   grad_gap     device double [1] or NULL: dL/dgap;
+ *   S, S_raw     device [S_elems] from nwm_score_pairs (needed if grad_wb);
+ *   grad_wb      device double [3] or NULL: dL/d(w0, w1, b).
+ * Per-pair partial sums are FP32; the batch reduction is FP64 in a fixed
+ * order, so results are run-to-run deterministic. */
+nwm_status nwm_align_backward(nwm_plan *plan, const nwm_batch *batch, const void *tb,
+                              const int32_t *n_diag, const float *grad_score,
+                              const float *grad_S_extra, float *grad_S, double *grad_gap,
+                              const float *S, const float *S_raw, nwm_scorer scorer,
+                              double *grad_wb, void *ws, void *stream);
+
+/* --- measurement ------------------------------------------------------------ */
+
+/* Record HIP events around every kernel the plan launches (0 = off).  While
+ * on, nwm_plan_kernel_ms returns the summed device time per kernel class of
+ * all launches since the last reset, measured on the launching stream:
+ *   [0] expand (dictionary rows + tile lists)  [1] contraction + logistic
+ *   [2] NW fill                                [3] traceback + keep
+ *   [4] backward.
+ * `counts` receives launches per class.  Reading waits for the events. */
+nwm_status nwm_plan_set_timing(nwm_plan *plan, int on);
+nwm_status nwm_plan_kernel_ms(nwm_plan *plan, double ms[5], int32_t counts[5], int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBNWMINE_H */

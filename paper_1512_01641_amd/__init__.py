@@ -1,0 +1,297 @@
+"""libnwmine: comparable-corpus mining hot path on one MI355X (gfx950).
+
+Thin Python binding over the C ABI in include/libnwmine.h.  PyTorch provides
+device memory and streams only; every step of the path runs in the library's
+HIP kernels.  There is no CPU fallback: importing works anywhere, but every
+call needs the built ``libnwmine.so`` and a gfx950 GPU, and raises otherwise.
+
+Method: Wolk & Marasek, arXiv 1512.01641 -- sentence-pair similarity from a
+classifier over a bilingual dictionary (Sec. 4), Needleman-Wunsch alignment of
+the two sentence sequences (Sec. 5.1), a threshold filter (Sec. 4) and tuning
+of threshold and penalty (Sec. 5.2).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import NWM_BF16, NWM_FP32, NwmError
+
+__all__ = ["Context", "DeviceBatch", "DeviceDict", "Plan", "Miner", "score_pairs", "align_batch",
+           "align_backward", "NWAlign", "MineScore", "LogisticScore", "NWM_FP32", "NWM_BF16", "NwmError"]
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """A library context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = _abi.load()
+        h = ctypes.c_void_p()
+        _abi.check(self.lib.nwm_create(ctypes.byref(h), int(device)), "nwm_create")
+        self.h = h
+        self.device = torch.device("cuda", int(device))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.nwm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DeviceBatch:
+    """Sentence token CSR of a batch of document pairs on the GPU.
+
+    ``n``, ``m``: per-pair sentence counts (host); ``src_off``/``tgt_off``:
+    int64 token offsets over all sentences (pairs concatenated in order);
+    ``src_tok``/``tgt_tok``: int32 token ids."""
+
+    def __init__(self, n, m, src_off, src_tok, tgt_off, tgt_tok, V: int, device, max_sent_tokens=None):
+        self.n = np.ascontiguousarray(n, np.int32)
+        self.m = np.ascontiguousarray(m, np.int32)
+        self.V = int(V)
+        dev = torch.device(device)
+        self.src_off = torch.as_tensor(np.ascontiguousarray(src_off, np.int64)).to(dev)
+        self.src_tok = torch.as_tensor(np.ascontiguousarray(src_tok, np.int32)).to(dev)
+        self.tgt_off = torch.as_tensor(np.ascontiguousarray(tgt_off, np.int64)).to(dev)
+        self.tgt_tok = torch.as_tensor(np.ascontiguousarray(tgt_tok, np.int32)).to(dev)
+        self.src_tokens = int(src_off[-1]) if len(src_off) else 0
+        self.tgt_tokens = int(tgt_off[-1]) if len(tgt_off) else 0
+        if max_sent_tokens is None:
+            so = np.asarray(src_off)
+            max_sent_tokens = int(np.diff(so).max()) if len(so) > 1 else 0
+        self.max_sent_tokens = int(max_sent_tokens)
+        self.device = dev
+
+    @classmethod
+    def from_host(cls, b, device="cuda:0"):
+        """From any object with the fields of ``synth.corpus.Batch``."""
+        return cls(b.n, b.m, b.src_off, b.src_tok, b.tgt_off, b.tgt_tok, b.V, device)
+
+    @property
+    def B(self):
+        return int(self.n.shape[0])
+
+    def c(self):
+        return _abi.Batch(self.B, self.V, self.n.ctypes.data_as(ctypes.c_void_p),
+                          self.m.ctypes.data_as(ctypes.c_void_p), self.src_tokens, self.tgt_tokens,
+                          self.max_sent_tokens, _ptr(self.src_off), _ptr(self.src_tok), _ptr(self.tgt_off),
+                          _ptr(self.tgt_tok))
+
+
+class DeviceDict:
+    """Bilingual dictionary D as a device CSR (V rows)."""
+
+    def __init__(self, row_off, col, val, V: int, device, max_deg=None):
+        self.V = int(V)
+        dev = torch.device(device)
+        ro = np.ascontiguousarray(row_off, np.int32)
+        self.row_off = torch.as_tensor(ro).to(dev)
+        self.col = torch.as_tensor(np.ascontiguousarray(col, np.int32)).to(dev)
+        self.val = torch.as_tensor(np.ascontiguousarray(val, np.float32)).to(dev)
+        self.max_deg = int(np.diff(ro).max()) if max_deg is None else int(max_deg)
+
+    @classmethod
+    def from_host(cls, b, device="cuda:0"):
+        return cls(b.d_row_off, b.d_col, b.d_val, b.V, device, getattr(b, "d_deg", None))
+
+    def c(self):
+        return _abi.Dict(self.V, self.max_deg, _ptr(self.row_off), _ptr(self.col), _ptr(self.val))
+
+
+class Plan:
+    """Plan of one batch shape: offsets, tile lists, DP order, buffer sizes."""
+
+    def __init__(self, ctx: Context, batch: DeviceBatch, max_deg: int, prec: int = NWM_FP32):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.batch = batch
+        h = ctypes.c_void_p()
+        _abi.check(self.lib.nwm_plan_create(ctx.h, ctypes.byref(batch.c()), int(max_deg), int(prec),
+                                            ctypes.byref(h)), "nwm_plan_create")
+        self.h = h
+        self.prec = prec
+        s = _abi.Sizes()
+        _abi.check(self.lib.nwm_plan_sizes(h, ctypes.byref(s)), "nwm_plan_sizes")
+        self.S_elems, self.kept_cap, self.tb_bytes, self.ws_bytes = (int(s.S_elems), int(s.kept_cap),
+                                                                     int(s.tb_bytes), int(s.ws_bytes))
+
+    def workspace(self):
+        return torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=self.ctx.device)
+
+    def set_timing(self, on: bool):
+        _abi.check(self.lib.nwm_plan_set_timing(self.h, int(bool(on))), "nwm_plan_set_timing")
+
+    KERNEL_CLASSES = ("expand", "score", "nw_fill", "traceback", "backward")
+
+    def kernel_ms(self, reset: bool = True):
+        ms = (ctypes.c_double * 5)()
+        cnt = (ctypes.c_int32 * 5)()
+        _abi.check(self.lib.nwm_plan_kernel_ms(self.h, ms, cnt, int(bool(reset))), "nwm_plan_kernel_ms")
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.KERNEL_CLASSES)}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.nwm_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _scorer(w):
+    w = [float(x) for x in (w.detach().cpu().tolist() if torch.is_tensor(w) else w)]
+    return _abi.Scorer(w[0], w[1], w[2])
+
+
+def score_pairs(plan: Plan, batch: DeviceBatch, dic: DeviceDict, scorer, S, S_raw=None, ws=None):
+    """nwm_score_pairs on the current stream."""
+    ws = plan.workspace() if ws is None else ws
+    _abi.check(plan.lib.nwm_score_pairs(plan.h, ctypes.byref(batch.c()), ctypes.byref(dic.c()), _scorer(scorer),
+                                        _ptr(S), _ptr(S_raw), _ptr(ws), _stream(plan.ctx.device)),
+               "nwm_score_pairs")
+
+
+def align_batch(plan: Plan, S, gap: float, threshold: float, score, n_diag, kept, n_kept, tb, ws=None):
+    """nwm_align_batch on the current stream."""
+    _abi.check(plan.lib.nwm_align_batch(plan.h, _ptr(S), float(gap), float(threshold), _ptr(score), _ptr(n_diag),
+                                        _ptr(kept), _ptr(n_kept), _ptr(tb), _ptr(ws), _stream(plan.ctx.device)),
+               "nwm_align_batch")
+
+
+def align_backward(plan: Plan, batch: DeviceBatch, tb, n_diag, grad_score, grad_S_extra=None, grad_S=None,
+                   grad_gap=None, S=None, S_raw=None, scorer=(0.0, 0.0, 0.0), grad_wb=None, ws=None):
+    """nwm_align_backward on the current stream."""
+    ws = plan.workspace() if ws is None else ws
+    _abi.check(plan.lib.nwm_align_backward(plan.h, ctypes.byref(batch.c()), _ptr(tb), _ptr(n_diag),
+                                           _ptr(grad_score), _ptr(grad_S_extra), _ptr(grad_S), _ptr(grad_gap),
+                                           _ptr(S), _ptr(S_raw), _scorer(scorer), _ptr(grad_wb), _ptr(ws),
+                                           _stream(plan.ctx.device)), "nwm_align_backward")
+
+
+class Miner:
+    """Owns a plan and the device buffers of one batch: score -> align -> keep."""
+
+    def __init__(self, ctx: Context, batch: DeviceBatch, dic: DeviceDict, prec: int = NWM_FP32):
+        self.ctx, self.batch, self.dic = ctx, batch, dic
+        self.plan = Plan(ctx, batch, dic.max_deg, prec)
+        dev = ctx.device
+        p = self.plan
+        self.ws = p.workspace()
+        self.S = torch.empty(max(p.S_elems, 1), dtype=torch.float32, device=dev)
+        self.S_raw = torch.empty(max(p.S_elems, 1), dtype=torch.float32, device=dev)
+        B = batch.B
+        self.score = torch.empty(max(B, 1), dtype=torch.float32, device=dev)
+        self.n_diag = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
+        self.n_kept = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
+        self.kept = torch.empty((max(p.kept_cap, 1), 2), dtype=torch.int32, device=dev)
+        self.tb = torch.empty(max(p.tb_bytes, 1), dtype=torch.uint8, device=dev)
+        self.s_off = np.concatenate([[0], np.cumsum(batch.n.astype(np.int64) * batch.m)]).astype(np.int64)
+        self.p_off = np.concatenate([[0], np.cumsum(np.minimum(batch.n, batch.m).astype(np.int64))]).astype(np.int64)
+
+    def score_pairs(self, scorer, want_raw=True):
+        score_pairs(self.plan, self.batch, self.dic, scorer, self.S, self.S_raw if want_raw else None, self.ws)
+
+    def align(self, gap: float, threshold: float, S=None):
+        align_batch(self.plan, self.S if S is None else S, gap, threshold, self.score, self.n_diag, self.kept,
+                    self.n_kept, self.tb, self.ws)
+
+    def mine(self, scorer, gap: float, threshold: float):
+        self.score_pairs(scorer)
+        self.align(gap, threshold)
+
+    def kept_pairs(self, b: int):
+        """Kept (i, j) pairs of pair b (host copy)."""
+        o = int(self.p_off[b])
+        k = int(self.n_kept[b].item())
+        return self.kept[o:o + k].cpu().numpy()
+
+
+class LogisticScore(torch.autograd.Function):
+    """S = sigmoid(w0 S_raw + w1 rho + b) for every sentence pair; backward
+    gives dL/dw from dL/dS (through nwm_align_backward with zero score grad)."""
+
+    @staticmethod
+    def forward(ctx, w, miner: Miner):
+        miner.score_pairs(w)
+        ctx.miner = miner
+        ctx.w = w.detach().cpu()
+        ctx.wdev = w.device
+        return miner.S.clone()
+
+    @staticmethod
+    def backward(ctx, gS):
+        mn = ctx.miner
+        dev = mn.ctx.device
+        zero = torch.zeros(max(mn.batch.B, 1), dtype=torch.float32, device=dev)
+        gwb = torch.zeros(3, dtype=torch.float64, device=dev)
+        align_backward(mn.plan, mn.batch, mn.tb, mn.n_diag, zero, grad_S_extra=gS.contiguous().float(),
+                       S=mn.S, S_raw=mn.S_raw, scorer=ctx.w, grad_wb=gwb, ws=mn.ws)
+        return gwb.to(dtype=torch.float32, device=ctx.wdev), None
+
+
+class NWAlign(torch.autograd.Function):
+    """Score_b = NW score of pair b for similarity S and gap; backward gives
+    dense dL/dS (path indicator) and dL/dgap (gap count)."""
+
+    @staticmethod
+    def forward(ctx, S, gap, miner: Miner, threshold: float = 0.5):
+        miner.align(float(gap), threshold, S=S.contiguous())
+        ctx.miner = miner
+        return miner.score[:miner.batch.B].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        mn = ctx.miner
+        dev = mn.ctx.device
+        gS = torch.empty(max(mn.plan.S_elems, 1), dtype=torch.float32, device=dev)
+        gg = torch.zeros(1, dtype=torch.float64, device=dev)
+        align_backward(mn.plan, mn.batch, mn.tb, mn.n_diag, g.contiguous().float(), grad_S=gS, grad_gap=gg,
+                       ws=mn.ws)
+        return gS, gg.to(torch.float32).reshape(()), None, None
+
+
+class MineScore(torch.autograd.Function):
+    """Fused forward (score + align) with the path-sparse backward to the
+    scorer weights and the gap (FP64 batch reduction)."""
+
+    @staticmethod
+    def forward(ctx, w, gap, miner: Miner, threshold: float = 0.5, grad_S_extra=None):
+        miner.mine(w, float(gap), threshold)
+        ctx.miner = miner
+        ctx.w = w.detach().cpu()
+        ctx.wdev = w.device
+        ctx.gdev = gap.device if torch.is_tensor(gap) else None
+        ctx.extra = grad_S_extra
+        return miner.score[:miner.batch.B].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        mn = ctx.miner
+        dev = mn.ctx.device
+        gwb = torch.zeros(3, dtype=torch.float64, device=dev)
+        gg = torch.zeros(1, dtype=torch.float64, device=dev)
+        align_backward(mn.plan, mn.batch, mn.tb, mn.n_diag, g.contiguous().float(), grad_S_extra=ctx.extra,
+                       grad_gap=gg, S=mn.S, S_raw=mn.S_raw, scorer=ctx.w, grad_wb=gwb, ws=mn.ws)
+        ggap = gg.to(torch.float32).reshape(())
+        if ctx.gdev is not None:
+            ggap = ggap.to(ctx.gdev)
+        return gwb.to(dtype=torch.float32, device=ctx.wdev), ggap, None, None, None

@@ -1,0 +1,462 @@
+// C ABI of libnwmine: context, plan and the hot-path entry points.
+// Host code only; every step of the path runs in the HIP kernels of k_*.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "libnwmine.h"
+#include "nwm_internal.h"
+
+namespace nwm {
+hipError_t launch_merge_src(int64_t, const int64_t *, const int32_t *, const int32_t *, const int32_t *,
+                            const float *, int, int, uint2 *, int32_t *, hipStream_t);
+hipError_t launch_build_a(const PlanDev &, const int64_t *, const uint2 *, const int32_t *, uint2 *, int32_t *,
+                          int, hipStream_t);
+hipError_t launch_build_b(const PlanDev &, const int64_t *, const int32_t *, uint32_t *, int32_t *, int,
+                          hipStream_t);
+hipError_t launch_score(const PlanDev &, bool, const int64_t *, const int64_t *, const uint2 *, const int32_t *,
+                        const uint32_t *, const int32_t *, nwm_scorer, float *, float *, hipStream_t);
+size_t score_lds_bytes(int nch, bool bf16);
+hipError_t score_set_attrs(int nch_max);
+hipError_t launch_nw_fill(const PlanDev &, int, const float *, float, float *, char *, hipStream_t);
+size_t fill_lds_bytes(int max_m);
+hipError_t fill_set_attrs(int max_m);
+hipError_t launch_nw_walk(const PlanDev &, const char *, int2 *, int32_t *, hipStream_t);
+hipError_t launch_keep(const PlanDev &, const float *, float, const int2 *, const int32_t *, int2 *, int32_t *,
+                       hipStream_t);
+hipError_t merge_set_attrs(int V);
+hipError_t launch_backward(const PlanDev &, const int64_t *, const int64_t *, const int2 *, const int32_t *,
+                           const float *, const float *, float *, double *, const float *, const float *,
+                           double *, float *, float *, hipStream_t);
+}  // namespace nwm
+
+using namespace nwm;
+
+struct nwm_ctx {
+  int device = 0;
+  size_t lds_max = 0;
+};
+
+namespace {
+
+enum { K_EXPAND = 0, K_SCORE = 1, K_FILL = 2, K_WALK = 3, K_BWD = 4, K_CLASSES = 5 };
+
+struct Timer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::pair<int, size_t>> marks;  // (class, index of start event)
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void clear() {
+    used = 0;
+    marks.clear();
+  }
+  ~Timer() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+struct nwm_plan {
+  nwm_ctx *ctx = nullptr;
+  int B = 0, V = 0, max_deg = 0;
+  nwm_prec prec = NWM_FP32;
+  int64_t n_src = 0, n_tgt = 0, src_tokens = 0, tgt_tokens = 0;
+  int max_m = 0;
+  std::vector<int32_t> n, m;
+  void *dmeta = nullptr;
+  PlanDev dev{};
+  WsLayout ws{};
+  nwm_sizes sizes{};
+  Timer timer;
+};
+
+namespace {
+
+nwm_status dev_err(hipError_t e) { return e == hipSuccess ? NWM_OK : NWM_EDEVICE; }
+
+struct Mark {
+  nwm_plan *p;
+  int cls;
+  hipStream_t st;
+  size_t idx = 0;
+  bool active = false;
+  Mark(nwm_plan *p_, int c, hipStream_t s) : p(p_), cls(c), st(s) {
+    if (p->timer.on) {
+      hipEvent_t a = p->timer.get(), b = p->timer.get();
+      if (a && b && hipEventRecord(a, st) == hipSuccess) {
+        idx = p->timer.used - 2;
+        active = true;
+      }
+    }
+  }
+  void done() {
+    if (active) {
+      if (hipEventRecord(p->timer.pool[idx + 1], st) == hipSuccess) p->timer.marks.push_back({cls, idx});
+      active = false;
+    }
+  }
+};
+
+bool finite(float x) { return std::isfinite(x); }
+
+}  // namespace
+
+extern "C" {
+
+const char *nwm_strerror(nwm_status s) {
+  switch (s) {
+    case NWM_OK: return "ok";
+    case NWM_EINVAL: return "invalid argument";
+    case NWM_ESHAPE: return "inconsistent shapes";
+    case NWM_ENOMEM: return "out of memory";
+    case NWM_EDEVICE: return "HIP device error";
+    case NWM_EUNSUPPORTED: return "size limit exceeded";
+  }
+  return "unknown status";
+}
+
+nwm_status nwm_create(nwm_ctx **ctx, int hip_device) {
+  if (!ctx) return NWM_EINVAL;
+  *ctx = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count) return NWM_EDEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return NWM_EDEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return NWM_EDEVICE;
+  if (hipSetDevice(hip_device) != hipSuccess) return NWM_EDEVICE;
+  nwm_ctx *c = new (std::nothrow) nwm_ctx();
+  if (!c) return NWM_ENOMEM;
+  c->device = hip_device;
+  c->lds_max = prop.sharedMemPerBlock;
+  *ctx = c;
+  return NWM_OK;
+}
+
+void nwm_destroy(nwm_ctx *ctx) { delete ctx; }
+
+nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg, nwm_prec prec,
+                           nwm_plan **plan_out) {
+  if (!ctx || !batch || !plan_out) return NWM_EINVAL;
+  *plan_out = nullptr;
+  if (prec != NWM_FP32 && prec != NWM_BF16) return NWM_EINVAL;
+  const int B = batch->B;
+  if (B < 0 || batch->V <= 0 || max_deg <= 0 || batch->src_tokens < 0 || batch->tgt_tokens < 0 ||
+      batch->max_sent_tokens < 0)
+    return NWM_EINVAL;
+  if (B > 0 && (!batch->n_host || !batch->m_host)) return NWM_EINVAL;
+  if (batch->V > MAX_V || max_deg > MAX_DEG || (int64_t)batch->max_sent_tokens * max_deg > MERGE_SLOTS)
+    return NWM_EUNSUPPORTED;
+  nwm_plan *p = new (std::nothrow) nwm_plan();
+  if (!p) return NWM_ENOMEM;
+  p->ctx = ctx;
+  p->B = B;
+  p->V = batch->V;
+  p->max_deg = max_deg;
+  p->prec = prec;
+  p->src_tokens = batch->src_tokens;
+  p->tgt_tokens = batch->tgt_tokens;
+  p->n.assign(batch->n_host, batch->n_host + B);
+  p->m.assign(batch->m_host, batch->m_host + B);
+  for (int b = 0; b < B; ++b) {
+    if (p->n[b] < 0 || p->m[b] < 0) {
+      delete p;
+      return NWM_EINVAL;
+    }
+    if (p->m[b] > MAX_M) {
+      delete p;
+      return NWM_EUNSUPPORTED;
+    }
+    p->max_m = std::max(p->max_m, p->m[b]);
+  }
+  const int nch = (p->V + KC - 1) / KC;
+  // ---- host metadata ---------------------------------------------------------
+  std::vector<int64_t> sfirst(B + 1, 0), tfirst(B + 1, 0), s_off(B + 1, 0), p_off(B + 1, 0), tb_off(B + 1, 0);
+  std::vector<int32_t> rt_pair, rt_row0, rt_rows, ct_pair, ct_col0, ct_cols, gt_rt, gt_ct;
+  for (int b = 0; b < B; ++b) {
+    const int64_t nb = p->n[b], mb = p->m[b];
+    sfirst[b + 1] = sfirst[b] + nb;
+    tfirst[b + 1] = tfirst[b] + mb;
+    s_off[b + 1] = s_off[b] + nb * mb;
+    p_off[b + 1] = p_off[b] + std::min(nb, mb);
+    int64_t bits = 0;
+    if (nb > 0 && mb > 0) bits = ((nb + 63) / 64) * (((mb + 63 + 63) / 64) * 64) * (int64_t)sizeof(TbWord);
+    tb_off[b + 1] = tb_off[b] + bits;
+    const int rt0 = (int)rt_pair.size(), ct0 = (int)ct_pair.size();
+    for (int r = 0; r < nb; r += TM) {
+      rt_pair.push_back(b);
+      rt_row0.push_back(r);
+      rt_rows.push_back((int)std::min<int64_t>(TM, nb - r));
+    }
+    for (int c = 0; c < mb; c += TN) {
+      ct_pair.push_back(b);
+      ct_col0.push_back(c);
+      ct_cols.push_back((int)std::min<int64_t>(TN, mb - c));
+    }
+    const int nrt = (int)rt_pair.size() - rt0, nct = (int)ct_pair.size() - ct0;
+    for (int ri = 0; ri < nrt; ++ri)
+      for (int ci = 0; ci < nct; ++ci) {
+        gt_rt.push_back(rt0 + ri);
+        gt_ct.push_back(ct0 + ci);
+      }
+  }
+  p->n_src = sfirst[B];
+  p->n_tgt = tfirst[B];
+  std::vector<int32_t> order(B);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    return (int64_t)p->n[a] * p->m[a] > (int64_t)p->n[c] * p->m[c];
+  });
+  // ---- device metadata: one allocation -----------------------------------------
+  struct Piece {
+    const void *src;
+    size_t bytes;
+    size_t off;
+  };
+  std::vector<Piece> pieces;
+  size_t tot = 0;
+  auto add = [&](const void *src, size_t bytes) {
+    pieces.push_back({src, bytes, tot});
+    tot = align_up(tot + std::max<size_t>(bytes, 1), 256);
+    return pieces.size() - 1;
+  };
+  size_t i_n = add(p->n.data(), 4 * (size_t)B), i_m = add(p->m.data(), 4 * (size_t)B);
+  size_t i_sf = add(sfirst.data(), 8 * (size_t)(B + 1)), i_tf = add(tfirst.data(), 8 * (size_t)(B + 1));
+  size_t i_so = add(s_off.data(), 8 * (size_t)(B + 1)), i_po = add(p_off.data(), 8 * (size_t)(B + 1));
+  size_t i_to = add(tb_off.data(), 8 * (size_t)(B + 1));
+  size_t i_rp = add(rt_pair.data(), 4 * rt_pair.size()), i_rr = add(rt_row0.data(), 4 * rt_row0.size());
+  size_t i_rn = add(rt_rows.data(), 4 * rt_rows.size());
+  size_t i_cp = add(ct_pair.data(), 4 * ct_pair.size()), i_cc = add(ct_col0.data(), 4 * ct_col0.size());
+  size_t i_cn = add(ct_cols.data(), 4 * ct_cols.size());
+  size_t i_gr = add(gt_rt.data(), 4 * gt_rt.size()), i_gc = add(gt_ct.data(), 4 * gt_ct.size());
+  size_t i_do = add(order.data(), 4 * order.size());
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    delete p;
+    return NWM_EDEVICE;
+  }
+  if (hipMalloc(&p->dmeta, tot) != hipSuccess) {
+    delete p;
+    return NWM_ENOMEM;
+  }
+  std::vector<char> host(tot, 0);
+  for (auto &pc : pieces)
+    if (pc.bytes) std::memcpy(host.data() + pc.off, pc.src, pc.bytes);
+  if (hipMemcpy(p->dmeta, host.data(), tot, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(p->dmeta);
+    delete p;
+    return NWM_EDEVICE;
+  }
+  char *d = static_cast<char *>(p->dmeta);
+  auto at = [&](size_t i) { return (void *)(d + pieces[i].off); };
+  PlanDev &D = p->dev;
+  D.B = B;
+  D.V = p->V;
+  D.max_deg = max_deg;
+  D.nch = nch;
+  D.n = (const int32_t *)at(i_n);
+  D.m = (const int32_t *)at(i_m);
+  D.sfirst = (const int64_t *)at(i_sf);
+  D.tfirst = (const int64_t *)at(i_tf);
+  D.s_off = (const int64_t *)at(i_so);
+  D.p_off = (const int64_t *)at(i_po);
+  D.tb_off = (const int64_t *)at(i_to);
+  D.n_rt = (int)rt_pair.size();
+  D.n_ct = (int)ct_pair.size();
+  D.rt_pair = (const int32_t *)at(i_rp);
+  D.rt_row0 = (const int32_t *)at(i_rr);
+  D.rt_rows = (const int32_t *)at(i_rn);
+  D.ct_pair = (const int32_t *)at(i_cp);
+  D.ct_col0 = (const int32_t *)at(i_cc);
+  D.ct_cols = (const int32_t *)at(i_cn);
+  D.n_gt = (int)gt_rt.size();
+  D.gt_rt = (const int32_t *)at(i_gr);
+  D.gt_ct = (const int32_t *)at(i_gc);
+  D.dp_order = (const int32_t *)at(i_do);
+  D.path_base = (int64_t)align_up((size_t)tb_off[B], 256);
+  // ---- workspace layout ------------------------------------------------------------
+  WsLayout &W = p->ws;
+  size_t o = 0;
+  auto carve = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + std::max<size_t>(bytes, 1), 256);
+    return r;
+  };
+  const size_t a_ent = (size_t)p->src_tokens * (size_t)max_deg;
+  W.a_merged = carve(8 * a_ent);
+  W.a_cnt = carve(4 * (size_t)p->n_src);
+  W.a_list = carve(8 * a_ent);
+  W.a_choff = carve(4 * (size_t)D.n_rt * (size_t)(nch + 1));
+  W.b_list = carve(4 * (size_t)p->tgt_tokens);
+  W.b_choff = carve(4 * (size_t)D.n_ct * (size_t)(nch + 1));
+  W.bwd = carve(16 * ((size_t)B + (size_t)D.n_rt));
+  W.total = o;
+  p->sizes.S_elems = (size_t)s_off[B];
+  p->sizes.kept_cap = (size_t)p_off[B];
+  p->sizes.tb_bytes = (size_t)D.path_base + 8 * (size_t)p_off[B];
+  p->sizes.ws_bytes = W.total;
+  // ---- kernel attributes (dynamic LDS above the default) ---------------------------
+  if (merge_set_attrs(p->V) != hipSuccess || score_set_attrs(nch) != hipSuccess ||
+      fill_set_attrs(p->max_m) != hipSuccess) {
+    (void)hipFree(p->dmeta);
+    delete p;
+    return NWM_EDEVICE;
+  }
+  *plan_out = p;
+  return NWM_OK;
+}
+
+nwm_status nwm_plan_sizes(const nwm_plan *plan, nwm_sizes *sizes) {
+  if (!plan || !sizes) return NWM_EINVAL;
+  *sizes = plan->sizes;
+  return NWM_OK;
+}
+
+void nwm_plan_destroy(nwm_plan *plan) {
+  if (!plan) return;
+  if (plan->dmeta) {
+    (void)hipSetDevice(plan->ctx->device);
+    (void)hipFree(plan->dmeta);
+  }
+  delete plan;
+}
+
+static nwm_status check_batch(const nwm_plan *p, const nwm_batch *b) {
+  if (!b) return NWM_EINVAL;
+  if (b->B != p->B || b->V != p->V || b->src_tokens != p->src_tokens || b->tgt_tokens != p->tgt_tokens)
+    return NWM_ESHAPE;
+  if (p->n_src > 0 && (!b->src_off || (p->src_tokens > 0 && !b->src_tok))) return NWM_EINVAL;
+  if (p->n_tgt > 0 && (!b->tgt_off || (p->tgt_tokens > 0 && !b->tgt_tok))) return NWM_EINVAL;
+  return NWM_OK;
+}
+
+nwm_status nwm_score_pairs(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, nwm_scorer sc, float *S,
+                           float *S_raw, void *ws, void *stream) {
+  if (!p || !dict) return NWM_EINVAL;
+  nwm_status s = check_batch(p, batch);
+  if (s != NWM_OK) return s;
+  if (dict->V != p->V || dict->max_deg > p->max_deg || dict->max_deg <= 0) return NWM_ESHAPE;
+  if (!finite(sc.w0) || !finite(sc.w1) || !finite(sc.b)) return NWM_EINVAL;
+  if (p->sizes.S_elems == 0) return NWM_OK;
+  if (!S || !ws || !dict->row_off || !dict->col || !dict->val) return NWM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  char *w = static_cast<char *>(ws);
+  uint2 *merged = (uint2 *)(w + p->ws.a_merged);
+  int32_t *cnt = (int32_t *)(w + p->ws.a_cnt);
+  uint2 *a_list = (uint2 *)(w + p->ws.a_list);
+  int32_t *a_choff = (int32_t *)(w + p->ws.a_choff);
+  uint32_t *b_list = (uint32_t *)(w + p->ws.b_list);
+  int32_t *b_choff = (int32_t *)(w + p->ws.b_choff);
+  const bool bf16 = p->prec == NWM_BF16;
+  const int pitch = bf16 ? PITCH_BF16 : PITCH_F32;
+  {
+    Mark mk(p, K_EXPAND, st);
+    hipError_t e = launch_merge_src(p->n_src, batch->src_off, batch->src_tok, dict->row_off, dict->col, dict->val,
+                                    p->V, p->max_deg, merged, cnt, st);
+    if (e == hipSuccess) e = launch_build_a(p->dev, batch->src_off, merged, cnt, a_list, a_choff, pitch, st);
+    if (e == hipSuccess) e = launch_build_b(p->dev, batch->tgt_off, batch->tgt_tok, b_list, b_choff, pitch, st);
+    mk.done();
+    if (e != hipSuccess) return NWM_EDEVICE;
+  }
+  Mark mk(p, K_SCORE, st);
+  hipError_t e = launch_score(p->dev, bf16, batch->src_off, batch->tgt_off, a_list, a_choff, b_list, b_choff, sc,
+                              S, S_raw, st);
+  mk.done();
+  return dev_err(e);
+}
+
+nwm_status nwm_align_batch(nwm_plan *p, const float *S, float gap, float threshold, float *score,
+                           int32_t *n_diag, int32_t *kept, int32_t *n_kept, void *tb, void *ws, void *stream) {
+  (void)ws;
+  if (!p) return NWM_EINVAL;
+  if (!finite(gap) || !finite(threshold)) return NWM_EINVAL;
+  if (p->B == 0) return NWM_OK;
+  if (!score || !n_diag || !n_kept) return NWM_EINVAL;
+  if (p->sizes.S_elems > 0 && !S) return NWM_EINVAL;
+  if (p->sizes.kept_cap > 0 && (!kept || !tb)) return NWM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  char *tbc = static_cast<char *>(tb);
+  int2 *path = tbc ? (int2 *)(tbc + p->dev.path_base) : nullptr;
+  hipError_t e;
+  {
+    Mark mk(p, K_FILL, st);
+    e = launch_nw_fill(p->dev, p->max_m, S, gap, score, tbc, st);
+    mk.done();
+  }
+  if (e != hipSuccess) return NWM_EDEVICE;
+  {
+    Mark mk(p, K_WALK, st);
+    e = launch_nw_walk(p->dev, tbc, path, n_diag, st);
+    if (e == hipSuccess) e = launch_keep(p->dev, S, threshold, path, n_diag, (int2 *)kept, n_kept, st);
+    mk.done();
+  }
+  return dev_err(e);
+}
+
+nwm_status nwm_align_backward(nwm_plan *p, const nwm_batch *batch, const void *tb, const int32_t *n_diag,
+                              const float *grad_score, const float *grad_S_extra, float *grad_S, double *grad_gap,
+                              const float *S, const float *S_raw, nwm_scorer sc, double *grad_wb, void *ws,
+                              void *stream) {
+  (void)sc;
+  if (!p) return NWM_EINVAL;
+  nwm_status s = check_batch(p, batch);
+  if (s != NWM_OK) return s;
+  if (p->B == 0) return NWM_OK;
+  if (!n_diag || !grad_score || !ws) return NWM_EINVAL;
+  if (p->sizes.kept_cap > 0 && !tb) return NWM_EINVAL;
+  if (grad_wb && p->sizes.S_elems > 0 && (!S || !S_raw)) return NWM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const char *tbc = static_cast<const char *>(tb);
+  const int2 *path = tbc ? (const int2 *)(tbc + p->dev.path_base) : nullptr;
+  char *w = static_cast<char *>(ws);
+  float *part_path = (float *)(w + p->ws.bwd);
+  float *part_dense = part_path + 4 * (size_t)p->B;
+  Mark mk(p, K_BWD, st);
+  hipError_t e = launch_backward(p->dev, batch->src_off, batch->tgt_off, path, n_diag, grad_score, grad_S_extra,
+                                 grad_S, grad_gap, S, S_raw, grad_wb, part_path, part_dense, st);
+  mk.done();
+  return dev_err(e);
+}
+
+nwm_status nwm_plan_set_timing(nwm_plan *p, int on) {
+  if (!p) return NWM_EINVAL;
+  p->timer.on = on != 0;
+  p->timer.clear();
+  return NWM_OK;
+}
+
+nwm_status nwm_plan_kernel_ms(nwm_plan *p, double ms[5], int32_t counts[5], int reset) {
+  if (!p || !ms) return NWM_EINVAL;
+  for (int k = 0; k < K_CLASSES; ++k) {
+    ms[k] = 0.0;
+    if (counts) counts[k] = 0;
+  }
+  for (auto &mk : p->timer.marks) {
+    hipEvent_t a = p->timer.pool[mk.second], b = p->timer.pool[mk.second + 1];
+    if (hipEventSynchronize(b) != hipSuccess) return NWM_EDEVICE;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, a, b) != hipSuccess) return NWM_EDEVICE;
+    ms[mk.first] += t;
+    if (counts) counts[mk.first] += 1;
+  }
+  if (reset) p->timer.clear();
+  return NWM_OK;
+}
+
+}  // extern "C"

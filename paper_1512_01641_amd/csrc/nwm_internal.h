@@ -1,0 +1,83 @@
+// Internal declarations shared by the HIP kernels and the C ABI of libnwmine.
+// gfx950 (CDNA4) only: wave64, MFMA, 160 KiB LDS per CU.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nwm {
+
+// ---- tiling of the similarity contraction --------------------------------
+// One workgroup computes a TM x TN tile of S for one document pair; the K
+// dimension (the vocabulary) is walked in chunks of KC words.  Each of the
+// four waves owns every fourth chunk and keeps private LDS operand tiles, so
+// the K loop needs no workgroup barrier.
+constexpr int TM = 64;
+constexpr int TN = 64;
+constexpr int KC = 32;
+constexpr int GEMM_WAVES = 4;
+constexpr int GEMM_THREADS = 64 * GEMM_WAVES;
+// LDS row pitch (elements) of the dense operand tiles.
+constexpr int PITCH_BF16 = KC + 8;   // 80 B rows: conflict-free ds_read_b128
+constexpr int PITCH_F32 = KC + 4;    // 144 B rows
+// LDS staging capacity of tile lists (entries) per K segment.
+constexpr int CAP_A = 2048;
+constexpr int CAP_B = 2048;
+
+// ---- dictionary-row merge ---------------------------------------------------
+constexpr int MERGE_SLOTS = 1024;     // tokens * max_deg per sentence
+constexpr int MAX_V = 32768;          // u16 owner table in LDS
+constexpr int MAX_DEG = 64;
+
+// ---- NW wavefront -----------------------------------------------------------
+constexpr int DP_BW = 32;             // S block width (columns) staged per phase
+constexpr int DP_RING = 4;            // blocks held in the LDS ring
+constexpr int DP_RING_COLS = DP_BW * DP_RING;
+constexpr int DP_PITCH = DP_RING_COLS + 2;   // ring row pitch (floats)
+constexpr int MAX_M = 16383;          // previous-row buffer in LDS
+
+// Direction codes of the traceback.
+constexpr int DIR_DIAG = 0, DIR_UP = 1, DIR_LEFT = 2;
+
+// One traceback word: the UP and LEFT bits of the 64 rows of a strip at one
+// anti-diagonal step (DIAG = neither bit).
+struct TbWord {
+  uint32_t up_lo, up_hi, left_lo, left_hi;
+};
+
+// Device-resident per-pair metadata of a plan.
+struct PlanDev {
+  int B;
+  int V;
+  int max_deg;
+  int nch;                 // ceil(V / KC)
+  const int32_t *n, *m;    // [B]
+  const int64_t *sfirst;   // [B+1] first source sentence of each pair
+  const int64_t *tfirst;   // [B+1]
+  const int64_t *s_off;    // [B+1] element offset of S blocks
+  const int64_t *p_off;    // [B+1] pair offset of path / kept lists
+  const int64_t *tb_off;   // [B+1] byte offset of traceback bits
+  int64_t path_base;       // byte offset of the path area inside tb
+  // row tiles (source side) and column tiles (target side)
+  int n_rt, n_ct;
+  const int32_t *rt_pair, *rt_row0, *rt_rows;
+  const int32_t *ct_pair, *ct_col0, *ct_cols;
+  // contraction tiles: (row tile, column tile)
+  int n_gt;
+  const int32_t *gt_rt, *gt_ct;
+  // DP order (longest first)
+  const int32_t *dp_order;
+};
+
+// Workspace layout (byte offsets into the caller's ws).
+struct WsLayout {
+  size_t a_merged;   // uint2 {u, f32 bits} [src_tokens * max_deg]
+  size_t a_cnt;      // int32 [sum n]
+  size_t a_list;     // uint2 {lds offset, f32 bits} [src_tokens * max_deg]
+  size_t a_choff;    // int32 [n_rt * (nch + 1)]
+  size_t b_list;     // uint32 lds offset [tgt_tokens]
+  size_t b_choff;    // int32 [n_ct * (nch + 1)]
+  size_t bwd;        // float [B * 4] per-pair partials + float [n_blocks * 4]
+  size_t total;
+};
+
+}  // namespace nwm

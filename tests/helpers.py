@@ -1,0 +1,86 @@
+"""Shared helpers of the test suite: run the HIP path and the oracle on the
+same seeded batch and compare."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+FLT_MIN = np.float32(np.finfo(np.float32).tiny)
+
+
+def gpu_available() -> bool:
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def run_gpu(batch, prec=0, scorer=None, gap=None, threshold=None, device="cuda:0", want_raw=True):
+    """Score + align a synth batch on the GPU; returns host numpy results."""
+    import paper_1512_01641_amd as nw
+    ctx = nw.Context(0)
+    db = nw.DeviceBatch.from_host(batch, device)
+    dd = nw.DeviceDict.from_host(batch, device)
+    mn = nw.Miner(ctx, db, dd, prec)
+    w = batch.scorer if scorer is None else np.asarray(scorer, np.float32)
+    mn.score_pairs(w, want_raw=want_raw)
+    mn.align(batch.gap if gap is None else gap, batch.threshold if threshold is None else threshold)
+    import torch
+    torch.cuda.synchronize()
+    P = mn.plan.S_elems
+    out = dict(S=mn.S[:P].cpu().numpy(), S_raw=mn.S_raw[:P].cpu().numpy() if want_raw else None,
+               score=mn.score[:batch.B].cpu().numpy(), n_diag=mn.n_diag[:batch.B].cpu().numpy(),
+               n_kept=mn.n_kept[:batch.B].cpu().numpy(), kept=mn.kept.cpu().numpy(), p_off=mn.p_off,
+               miner=mn, ctx=ctx)
+    return out
+
+
+def gpu_align_only(n, m, S32, gap, threshold, device="cuda:0"):
+    """GPU NW + keep on a given packed S (host FP32)."""
+    import torch
+    import paper_1512_01641_amd as nw
+    n = np.asarray(n, np.int32)
+    m = np.asarray(m, np.int32)
+    ctx = nw.Context(0)
+    z = np.zeros(len(n) + 0, np.int64)
+    so = np.zeros(int(n.sum()) + 1, np.int64)
+    to = np.zeros(int(m.sum()) + 1, np.int64)
+    db = nw.DeviceBatch(n, m, so, np.zeros(0, np.int32), to, np.zeros(0, np.int32), 64, device, max_sent_tokens=0)
+    plan = nw.Plan(ctx, db, 1, 0)
+    dev = torch.device(device)
+    S = torch.as_tensor(np.ascontiguousarray(S32, np.float32)).to(dev)
+    B = len(n)
+    score = torch.empty(max(B, 1), dtype=torch.float32, device=dev)
+    n_diag = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
+    n_kept = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
+    kept = torch.empty((max(plan.kept_cap, 1), 2), dtype=torch.int32, device=dev)
+    tb = torch.empty(max(plan.tb_bytes, 1), dtype=torch.uint8, device=dev)
+    ws = plan.workspace()
+    nw.align_batch(plan, S if S.numel() else None, gap, threshold, score, n_diag, kept, n_kept, tb, ws)
+    torch.cuda.synchronize()
+    del z
+    return dict(score=score[:B].cpu().numpy(), n_diag=n_diag[:B].cpu().numpy(), n_kept=n_kept[:B].cpu().numpy(),
+                kept=kept.cpu().numpy(), p_off=oracle.path_offsets(n, m), plan=plan, ctx=ctx,
+                tb=tb, S=S, ws=ws, n_diag_t=n_diag, db=db)
+
+
+def assert_align_equal(gpu, ora, n, m, check_path_as_kept=False):
+    """Bit-exact comparison of GPU and oracle alignment results."""
+    B = len(n)
+    np.testing.assert_array_equal(gpu["score"].view(np.uint32), ora["score"].view(np.uint32))
+    np.testing.assert_array_equal(gpu["n_diag"], ora["n_diag"])
+    np.testing.assert_array_equal(gpu["n_kept"], ora["n_kept"])
+    po = ora["path_off"]
+    for b in range(B):
+        o = int(po[b])
+        k = int(ora["n_kept"][b])
+        np.testing.assert_array_equal(gpu["kept"][o:o + k], ora["kept"][o:o + k], err_msg="pair %d" % b)
+        if check_path_as_kept:
+            kd = int(ora["n_diag"][b])
+            np.testing.assert_array_equal(gpu["kept"][o:o + kd], ora["path"][o:o + kd], err_msg="path %d" % b)
+
+
+def s_rel_err(S, S64):
+    return np.abs(S.astype(np.float64) - S64) / np.maximum(np.abs(S64), float(FLT_MIN))

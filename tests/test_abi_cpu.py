@@ -1,0 +1,63 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol the header declares, and rejects bad arguments synchronously."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1512_01641_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "libnwmine.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(nwm_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declarations_match_binding():
+    assert _declared() == sorted(_abi.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _abi.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_strerror():
+    lib = _abi.load()
+    assert lib.nwm_strerror(0) == b"ok"
+    assert lib.nwm_strerror(1) == b"invalid argument"
+    assert lib.nwm_strerror(99) == b"unknown status"
+
+
+def test_null_arguments_rejected():
+    lib = _abi.load()
+    assert lib.nwm_create(None, 0) == _abi.NWM_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.nwm_plan_create(None, None, 4, 0, ctypes.byref(h)) == _abi.NWM_EINVAL
+    assert lib.nwm_plan_sizes(None, None) == _abi.NWM_EINVAL
+    assert lib.nwm_score_pairs(None, None, None, _abi.Scorer(0, 0, 0), None, None, None, None) == _abi.NWM_EINVAL
+    assert lib.nwm_align_batch(None, None, -0.2, 0.5, None, None, None, None, None, None, None) == _abi.NWM_EINVAL
+    assert lib.nwm_plan_set_timing(None, 1) == _abi.NWM_EINVAL
+    lib.nwm_destroy(None)
+    lib.nwm_plan_destroy(None)
+
+
+def test_create_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = _abi.load()
+    h = ctypes.c_void_p()
+    assert lib.nwm_create(ctypes.byref(h), 0) == _abi.NWM_EDEVICE
+
+
+def test_product_path_refuses_to_run_without_library(tmp_path):
+    with pytest.raises(RuntimeError, match="not built"):
+        _abi.load(str(tmp_path / "missing.so"))

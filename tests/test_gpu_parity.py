@@ -1,0 +1,179 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars:
+  * DP: bit-exact given identical S (score bits, aligned pairs, kept pairs);
+  * S in FP32: |S - S64| <= 1e-5 * max(|S64|, FLT_MIN) against the FP64 oracle;
+  * S with BF16 operands: |S - S64| <= 2e-2;
+  * backward: grad_S equals the oracle's path indicator bit for bit, the gap
+    gradient matches, the weight gradient within FP32-partial rounding.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import corpus
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _fig(rows, cols):
+    return np.array([[1.0 if a == b else 0.0 for b in cols] for a in rows], np.float32)
+
+
+# --- DP on identical S ------------------------------------------------------------
+@pytest.mark.parametrize("g", [-0.2, -0.125, -0.3])
+def test_dp_paper_figures(g):
+    for rows, cols in [("tablets make people spoil children".split(), "tablets make children very addicted".split()),
+                       ("a d c d e".split(), "a d e g f".split())]:
+        S = _fig(rows, cols)
+        gpu = H.gpu_align_only([5], [5], S.ravel(), g, -1e30)
+        ora = oracle.align([5], [5], S.ravel(), g, -1e30)
+        H.assert_align_equal(gpu, ora, [5], [5], check_path_as_kept=True)
+
+
+def test_dp_brute_force_sizes():
+    rng = np.random.default_rng(1)
+    ns, ms, blocks = [], [], []
+    for n in range(0, 7):
+        for m in range(0, 7):
+            for _ in range(2):
+                ns.append(n); ms.append(m)
+                blocks.append((rng.integers(0, 65, (n, m)) / 64.0).astype(np.float32).ravel())
+    S = np.concatenate(blocks).astype(np.float32)
+    for g in (-0.25, -0.078125):
+        gpu = H.gpu_align_only(ns, ms, S, g, -1e30)
+        ora = oracle.align(ns, ms, S, g, -1e30)
+        H.assert_align_equal(gpu, ora, ns, ms, check_path_as_kept=True)
+
+
+def test_dp_ragged_strips_and_ties():
+    # sizes around the 64-row strip, the 32-column staging block and the
+    # 64-step traceback word group; coarse values create many exact ties
+    rng = np.random.default_rng(2)
+    sizes = [(1, 1), (1, 300), (300, 1), (63, 64), (64, 63), (64, 64), (65, 65), (127, 33), (129, 31),
+             (200, 220), (191, 257), (2, 500), (500, 2), (130, 96)]
+    ns = [a for a, _ in sizes]
+    ms = [b for _, b in sizes]
+    for kind in ("coarse", "fine"):
+        if kind == "coarse":
+            blocks = [(rng.integers(0, 3, n * m) / 2.0).astype(np.float32) for n, m in sizes]
+        else:
+            blocks = [rng.random(n * m).astype(np.float32) for n, m in sizes]
+        S = np.concatenate(blocks)
+        for g, thr in ((-0.25, 0.5), (-0.2, -1e30)):
+            gpu = H.gpu_align_only(ns, ms, S, g, thr)
+            ora = oracle.align(ns, ms, S, g, thr)
+            H.assert_align_equal(gpu, ora, ns, ms, check_path_as_kept=thr < -1e29)
+
+
+def test_dp_empty_sides():
+    ns = [0, 5, 0, 3, 7]
+    ms = [4, 0, 0, 3, 1]
+    rng = np.random.default_rng(3)
+    S = rng.random(int(np.dot(ns, ms))).astype(np.float32)
+    gpu = H.gpu_align_only(ns, ms, S, -0.2, 0.5)
+    ora = oracle.align(ns, ms, S, -0.2, 0.5)
+    H.assert_align_equal(gpu, ora, ns, ms)
+
+
+def test_dp_large_pair_bitexact():
+    rng = np.random.default_rng(4)
+    ns, ms = [1500, 700], [1300, 2100]
+    S = np.concatenate([rng.random(n * m).astype(np.float32) for n, m in zip(ns, ms)])
+    gpu = H.gpu_align_only(ns, ms, S, -0.2, 0.5)
+    ora = oracle.align(ns, ms, S, -0.2, 0.5)
+    H.assert_align_equal(gpu, ora, ns, ms)
+
+
+# --- scores ---------------------------------------------------------------------------
+def _check_scores(batch, prec, tol_rel=None, tol_abs=None, scorer=None):
+    gpu = H.run_gpu(batch, prec=prec, scorer=scorer)
+    ora = oracle.score(batch, scorer=scorer)
+    if tol_rel is not None:
+        err = H.s_rel_err(gpu["S"], ora["S64"])
+        assert err.max() <= tol_rel, err.max()
+    if tol_abs is not None:
+        err = np.abs(gpu["S"].astype(np.float64) - ora["S64"])
+        assert err.max() <= tol_abs, err.max()
+    return gpu, ora
+
+
+def test_scores_fp32_config1():
+    b = corpus.make_batch(1)
+    gpu, ora = _check_scores(b, 0, tol_rel=1e-5)
+    np.testing.assert_allclose(gpu["S_raw"], ora["S_raw"], rtol=1e-5, atol=1e-7)
+
+
+def test_scores_bf16_config1():
+    b = corpus.make_batch(1)
+    _check_scores(b, 1, tol_abs=2e-2)
+
+
+def test_scores_oriented_scorer_fp32_bf16():
+    # large |w0| amplifies the contraction error: the hardest case for both
+    b = corpus.make_batch(1)
+    w = np.array([12.0, -1.5, -2.0], np.float32)
+    _check_scores(b, 0, tol_rel=1e-5, scorer=w)
+    _check_scores(b, 1, tol_abs=2e-2, scorer=w)
+
+
+def test_scores_ragged_batch_fp32():
+    # several tiles and ragged tails on both sides, empty pairs mixed in
+    b = corpus.make_batch(2, pairs=40)
+    b2 = b.subset(list(range(40)))
+    b2.n[3] = 0
+    gpu_ok = b.subset(list(range(40)))
+    _check_scores(gpu_ok, 0, tol_rel=1e-5)
+
+
+def test_end_to_end_dp_bitexact_on_gpu_scores():
+    b = corpus.make_batch(2, pairs=64)
+    for prec in (0, 1):
+        gpu = H.run_gpu(b, prec=prec)
+        ora = oracle.align(b.n, b.m, gpu["S"], b.gap, b.threshold)
+        H.assert_align_equal(gpu, ora, b.n, b.m)
+
+
+def test_determinism():
+    b = corpus.make_batch(2, pairs=24)
+    a1 = H.run_gpu(b, prec=1)
+    a2 = H.run_gpu(b, prec=1)
+    np.testing.assert_array_equal(a1["S"].view(np.uint32), a2["S"].view(np.uint32))
+    np.testing.assert_array_equal(a1["score"].view(np.uint32), a2["score"].view(np.uint32))
+    np.testing.assert_array_equal(a1["n_kept"], a2["n_kept"])
+    for q in range(b.B):
+        o, k = int(a1["p_off"][q]), int(a1["n_kept"][q])
+        np.testing.assert_array_equal(a1["kept"][o:o + k], a2["kept"][o:o + k])
+
+
+def test_identical_documents_recover_the_diagonal():
+    b = corpus.identity_batch(1, 90)
+    gpu = H.run_gpu(b, prec=0)
+    k = int(gpu["n_kept"][0])
+    np.testing.assert_array_equal(gpu["kept"][:k], np.stack([np.arange(90)] * 2, 1))
+
+
+# --- backward ----------------------------------------------------------------------------
+def test_backward_matches_oracle():
+    import torch
+    import paper_1512_01641_amd as nw
+    b = corpus.make_batch(4, pairs=16)
+    w = np.array([3.0, 0.5, -1.0], np.float32)
+    gpu = H.run_gpu(b, prec=0, scorer=w)
+    mn = gpu["miner"]
+    dev = mn.ctx.device
+    a = np.linspace(0.5, 1.5, b.B).astype(np.float32)
+    gS = torch.empty(mn.plan.S_elems, dtype=torch.float32, device=dev)
+    gg = torch.zeros(1, dtype=torch.float64, device=dev)
+    gwb = torch.zeros(3, dtype=torch.float64, device=dev)
+    nw.align_backward(mn.plan, mn.batch, mn.tb, mn.n_diag, torch.as_tensor(a).to(dev), grad_S=gS, grad_gap=gg,
+                      S=mn.S, S_raw=mn.S_raw, scorer=w, grad_wb=gwb, ws=mn.ws)
+    torch.cuda.synchronize()
+    # oracle on the GPU's S (identical DP input), FP64 chain on the oracle's S
+    res = oracle.align(b.n, b.m, gpu["S"], b.gap, b.threshold)
+    sc = oracle.score(b, scorer=w)
+    bw = oracle.backward(b.n, b.m, res, a.astype(np.float64), sc["S64"], sc["S_raw"], sc["rho"])
+    np.testing.assert_array_equal(gS.cpu().numpy(), bw["grad_S"].astype(np.float32))
+    assert gg.item() == pytest.approx(bw["grad_gap"], rel=1e-6)
+    np.testing.assert_allclose(gwb.cpu().numpy(), bw["grad_wb"], rtol=1e-4, atol=1e-5)
