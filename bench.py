@@ -1,0 +1,187 @@
+"""Benchmark of the mining hot path on one MI355X.
+
+One step = one pass of the whole hot path over the batch: similarity of every
+sentence pair (dictionary expansion, contraction + logistic scorer), NW fill,
+traceback and threshold filter.  Inputs are resident in HBM before timing.
+
+Workload (default): 4096 seeded synthetic document pairs, sentence counts
+lognormal (median 60, clipped 20..2000, +-30 % target skew), V = 4096,
+contraction operands BF16 with FP32 accumulation, DP in FP32.  Also measured
+on the same pairs: the batched path with FP32 operands and the plain path
+(the same library called once per pair, FP32, no batching).
+
+Prints ONE JSON line.  Only one GPU is used; --gpus N > 1 exits with a
+message.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
+
+
+def _log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def _time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1000.0 / max(steps, 1)
+
+
+def cpu_baseline(batch, seconds_hint=30.0):
+    """The CPU oracle (FP64 scores, FP32 DP) on the host cores, timed on a
+    bounded sample of the same workload."""
+    import oracle
+    cores = min(os.cpu_count() or 1, 16)
+    # sample: leading pairs whose cells fit the hint at a conservative
+    # 100 M cells/s aggregate oracle rate
+    budget = seconds_hint * 1.0e8
+    cells = np.cumsum(batch.n.astype(np.int64) * batch.m)
+    k = int(np.searchsorted(cells, budget)) + 1
+    k = max(1, min(k, batch.B))
+    sub = batch.subset(range(k)) if k < batch.B else batch
+    t0 = time.perf_counter()
+    sc = oracle.score(sub, nthreads=cores)
+    oracle.align(sub.n, sub.m, sc["S32"], sub.gap, sub.threshold, nthreads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": round(sub.B / dt, 3), "unit": "doc-pairs/s", "cores": cores, "kind": "oracle",
+            "sample": "first %d of %d pairs (%d cells), score FP64 + NW FP32 + keep, %.1f s" % (
+                sub.B, batch.B, sub.cells(), dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--pairs", type=int, default=None, help="fewer pairs of the same workload (testing)")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py measures one GPU only: the document pairs are independent, so N GPUs would each run "
+              "the one-GPU path on a shard of the batch (see the design notes); no multi-GPU figure is made.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1512_01641_amd as nw
+    from synth import corpus
+
+    cfg = 2
+    _log("generating workload")
+    batch = corpus.make_batch(cfg, pairs=args.pairs)
+    B = batch.B
+    cells = batch.cells()
+    V = batch.V
+    ctx = nw.Context(0)
+    db = nw.DeviceBatch.from_host(batch)
+    dd = nw.DeviceDict.from_host(batch)
+    w, gap, thr = batch.scorer, batch.gap, batch.threshold
+    torch.cuda.synchronize()
+
+    results = {}
+    kernel = {}
+    for prec_name, prec in (("bf16", nw.NWM_BF16), ("f32", nw.NWM_FP32)):
+        _log("batched %s" % prec_name)
+        mn = nw.Miner(ctx, db, dd, prec)
+        step = lambda mn=mn: mn.mine(w, gap, thr)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        mn.plan.set_timing(True)
+        ms = _time_steps(step, args.steps, 0, torch)
+        km = mn.plan.kernel_ms(reset=True)
+        mn.plan.set_timing(False)
+        results[prec_name] = ms
+        kernel[prec_name] = {k: (v[0] / max(v[1], 1)) for k, v in km.items() if v[1]}
+        kernel[prec_name + "_launches_per_step"] = {k: v[1] / args.steps for k, v in km.items() if v[1]}
+        del mn
+
+    plain = None
+    if not args.no_plain:
+        _log("plain per-pair FP32")
+        # the same library called once per document pair, FP32, no batching
+        so = np.concatenate([[0], np.cumsum(batch.n, dtype=np.int64)])
+        to = np.concatenate([[0], np.cumsum(batch.m, dtype=np.int64)])
+        miners = []
+        for b in range(B):
+            sub = batch.subset([b])
+            miners.append(nw.Miner(ctx, nw.DeviceBatch.from_host(sub), dd, nw.NWM_FP32))
+            if (b + 1) % 512 == 0:
+                _log("plain setup %d/%d" % (b + 1, B))
+        del so, to
+
+        def plain_pass():
+            for mnb in miners:
+                mnb.mine(w, gap, thr)
+        plain = _time_steps(plain_pass, 1, 1, torch)
+        del miners
+
+    bf_ms = results["bf16"]
+    value = B / (bf_ms / 1000.0)
+    kb = kernel["bf16"]
+    score_ms = kb.get("score", float("nan"))
+    fill_ms = kb.get("nw_fill", float("nan"))
+    flops = 2.0 * V * cells
+    achieved = flops / (score_ms / 1000.0) / 1e12
+    gcups = cells / (fill_ms / 1000.0) / 1e9
+    dp_bytes = cells * 4.25
+    out = {
+        "metric": "NW GCUPS + aligned doc-pairs/s, batched BF16 vs plain FP32, same GPU",
+        "value": round(value, 2),
+        "unit": "doc-pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(bf_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic (seeded comparable-corpus generator with planted alignments)",
+        "config": {"workload": "%d document pairs, sentence counts lognormal median 60 clipped 20-2000 "
+                               "(+-30%% skew), V=%d hashed vocab, Zipf(1.1) tokens, BF16 contraction operands, "
+                               "FP32 DP, gap -0.2, threshold 0.5" % (B, V),
+                   "pairs": B, "cells": cells, "V": V},
+        "gcups": round(gcups, 3),
+        "pairs_per_s_batched_fp32": round(B / (results["f32"] / 1000.0), 2),
+        "pairs_per_s_plain_fp32": round(B / (plain / 1000.0), 2) if plain else None,
+        "ratio_batched_bf16_vs_plain_fp32": round(plain / bf_ms, 2) if plain else None,
+        "kernel_ms_per_step": {p: {k: round(v, 4) for k, v in kernel[p].items()} for p in ("bf16", "f32")},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": MFMA_PEAK_TFLOPS["bf16"],
+                     "unit": "TFLOP/s", "frac": round(achieved / MFMA_PEAK_TFLOPS["bf16"], 4), "traffic": None,
+                     "kernel": "k_score<bf16> (contraction + logistic epilogue)",
+                     "algorithmic": "2*V*sum(n*m) = %.4g flop per launch" % flops},
+        "dp_roofline": {"bound": "hbm", "achieved": round(dp_bytes / (fill_ms / 1000.0) / 1e9, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(dp_bytes / (fill_ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
+                        "kernel": "k_nw_fill", "algorithmic": "4.25 B/cell (S read + 2-bit traceback)"},
+    }
+    if not args.no_cpu:
+        _log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(batch)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

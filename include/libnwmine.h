@@ -118,7 +118,7 @@ const char *nwm_strerror(nwm_status s);
  * longest-first order of the DP, and the workspace layout.  Uses only the
  * batch's host fields and `max_deg`; the device pointers of `batch` may be
  * NULL here.  Limits (NWM_EUNSUPPORTED): V <= 32768, max_deg <= 64,
- * m_b <= 16383, max_sent_tokens * max_deg <= 1024.
+ * m_b <= 2^22, max_sent_tokens * max_deg <= 1024.
  * Allocates one small device buffer of per-pair metadata owned by the plan. */
 nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg,
                            nwm_prec prec, nwm_plan **plan);

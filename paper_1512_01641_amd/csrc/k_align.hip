@@ -2,151 +2,305 @@
 // document pair (Sec. 5.1, Figs. 1-2, eq. (1)) and the threshold filter
 // (Sec. 4).
 //
-// k_nw_fill  anti-diagonal wavefront, one wave per pair (longest pairs
-//            first).  The DP lattice is cut into strips of 64 rows; lane r
-//            owns row r of the strip and at step t computes column
-//            j = t - r + 1, so each step is one anti-diagonal of the strip
-//            (the paper's "diagonal in parallel threads").  The value from the
-//            row above arrives from lane r-1 by a DPP wave shift; lane 0
-//            reads the previous strip's last row from LDS, which the strip's
-//            last row overwrites in place behind it.  S is staged into an LDS
-//            ring of 32-column blocks with a one-block register prefetch.
-//            Per cell, in FP32 without contraction:
-//               up = H[i-1][j] + g, left = H[i][j-1] + g, diag = H[i-1][j-1] + S
-//               first maximum of (up, left, diag) with '>' (ties UP > LEFT > DIAG)
-//            The directions of a step are packed with two ballots into one
-//            16-byte word (UP bits, LEFT bits); 64 words are written per
-//            64 steps by one coalesced store.  H itself never reaches HBM.
-// k_nw_walk  traceback from (n, m): one wave per pair walks the direction
-//            words, holding a 64-step window in registers (one word per lane)
-//            and reading it with uniform-index readlane.  Aligned pairs are
-//            written right-aligned (ascending) into the path area.
-// k_keep     keeps the aligned pairs with S >= threshold, ascending.
+// k_nw_fill   persistent work-queue kernel, one wave per workgroup.  A work
+//             item is one 64-row strip of one pair's DP lattice; items are
+//             ordered longest pair first, strips top to bottom.  Lane r owns
+//             row r of the strip and at step t computes column j = t - r + 1,
+//             so each step is one anti-diagonal of the strip -- the paper's
+//             "diagonal in parallel threads".  Per cell, in FP32 without
+//             contraction:
+//                up = H[i-1][j] + g, left = H[i][j-1] + g, diag = H[i-1][j-1] + S
+//                first maximum of (up, left, diag) with '>' (UP > LEFT > DIAG)
+//             The value from the row above moves one lane per step by a DPP
+//             wave shift.  The strip's top boundary (the previous strip's last
+//             row) enters lane 0 through a 64-lane register window shifted one
+//             lane per step; the strip's own last row leaves through a second
+//             shifted window and is published every 16 steps behind a progress
+//             counter (agent-coherent stores, no cache flushes), so the next
+//             strip runs concurrently on another wave about 100 steps behind
+//             (bounded poll).
+//             S is staged through an LDS ring whose slot index equals the step
+//             index (row r of column c lands in slot c + r), so every lane reads
+//             the same slot and one ds_read_b128 serves four steps; the ring is
+//             fed one 32-step group ahead through registers.  Each lane packs
+//             its 2-bit directions, 16 steps per word, and every 64 steps the
+//             wave writes one coalesced 1 KiB block.  H never reaches HBM.
+// k_nw_reset  zeroes the queue and progress counters; scores of empty pairs.
+// k_nw_walk   traceback from (n, m): one wave per pair holds one 64-step block
+//             of its strip (one 16-byte word per lane) and reads it with
+//             uniform-index readlane.  Aligned pairs are written right-aligned
+//             (ascending) into the path area.
+// k_keep      keeps the aligned pairs with S >= threshold, ascending.
 #include "nwm_internal.h"
 
 namespace nwm {
 
-static __device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+constexpr int RING = 64;              // ring slots (steps) per row
+constexpr int RPITCH = RING + 4;      // floats per ring row
+constexpr int GROUP = 32;             // steps per S staging group
+constexpr int SPIN_LIMIT = 1 << 22;   // polls before a wave gives up (error flag)
+
+static __device__ __forceinline__ float dpp_shr1(float old, float src) {
+  // lane l <- src of lane l-1; lane 0 keeps `old`
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src), 0x138, 0xF, 0xF, false));
+}
+static __device__ __forceinline__ float dpp_shl1(float old, float src) {
+  // lane l <- src of lane l+1; lane 63 keeps `old`
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src), 0x130, 0xF, 0xF, false));
 }
 
-static __device__ __forceinline__ float shr1(float x) {
-  // lane l receives lane l-1's value (lane 0 receives 0 and is overwritten)
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xF, 0xF, false));
+static __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// A pointer every lane holds the same value of, moved to scalar registers.
+template <typename T>
+static __device__ __forceinline__ T *uniform_ptr(T *p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return reinterpret_cast<T *>(((uint64_t)hi << 32) | lo);
 }
 
-static __device__ __forceinline__ int steps_padded(int m) { return ((m + 63 + 63) / 64) * 64; }
+// Load the parallelogram of S used by steps [GROUP*q, GROUP*q + GROUP):
+// row r, columns GROUP*q - r + [0, GROUP); cells outside the strip read 0.
+// `rs` is a raw buffer over the strip's rows of S.
+struct StripSrc {
+  __amdgpu_buffer_rsrc_t rs;
+  int m, rows;
+  int lane_off;   // bytes: row (lane >> 5), column (lane & 31) - (lane >> 5)
+};
 
-// Load block q (64 rows x DP_BW columns of S, rows >= nrows / cols >= m read as 0).
-static __device__ __forceinline__ void dp_load_block(float (&R)[DP_BW], const float *__restrict__ Sb, int i0,
-                                                     int nrows, int m, int q, int lane) {
-  const int col = DP_BW * q + (lane & (DP_BW - 1));
-  const bool vc = col < m;
+static __device__ __forceinline__ bool group_interior(const StripSrc &src, int q) {
+  // every cell of the group lies inside the strip
+  return src.rows == 64 && q >= 2 && GROUP * q + GROUP <= src.m;
+}
+
+static __device__ __forceinline__ void load_group(float (&R)[GROUP], const StripSrc &src, int q, int lane) {
+  if (group_interior(src, q)) {
+    int soff = GROUP * q * 4;
+    const int step = (2 * src.m - 2) * 4;
 #pragma unroll
-  for (int k = 0; k < DP_BW; ++k) {
-    const int row = 2 * k + (lane >> 5);
-    R[k] = (vc && row < nrows) ? Sb[(int64_t)(i0 + row) * m + col] : 0.0f;
+    for (int k = 0; k < GROUP; ++k) {
+      R[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(src.rs, src.lane_off, soff, 0));
+      soff += step;
+      asm volatile("" : "+s"(soff));   // keep one running offset, not 32 live ones
+    }
+  } else {
+    // boundary group: load from a clamped in-range cell, then zero the
+    // cells outside the strip
+    const int h = lane >> 5, cl = lane & (GROUP - 1);
+#pragma unroll
+    for (int k = 0; k < GROUP; ++k) {
+      const int row = 2 * k + h;
+      const int c = GROUP * q + cl - row;
+      const bool ok = row < src.rows && (unsigned)c < (unsigned)src.m;
+      const int rc = min(row, src.rows - 1);
+      const int cc = min(max(c, 0), src.m - 1);
+      const float v =
+          __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(src.rs, (rc * src.m + cc) * 4, 0, 0));
+      R[k] = ok ? v : 0.0f;
+      if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);   // bound the live offsets
+    }
   }
 }
 
-static __device__ __forceinline__ void dp_store_block(const float (&R)[DP_BW], float *ring, int q, int lane) {
-  const int rc = (DP_BW * q + (lane & (DP_BW - 1))) & (DP_RING_COLS - 1);
+static __device__ __forceinline__ void store_group(const float (&R)[GROUP], float *ring, int q, int lane) {
+  const int slot = (GROUP * q + (lane & (GROUP - 1))) & (RING - 1);
 #pragma unroll
-  for (int k = 0; k < DP_BW; ++k) {
-    const int row = 2 * k + (lane >> 5);
-    ring[row * DP_PITCH + rc] = R[k];
-  }
+  for (int k = 0; k < GROUP; ++k) ring[(2 * k + (lane >> 5)) * RPITCH + slot] = R[k];
 }
 
-__global__ __launch_bounds__(64) void k_nw_fill(PlanDev P, const float *__restrict__ S, float g,
-                                                float *__restrict__ score, char *__restrict__ tb) {
-  extern __shared__ __align__(16) float lds[];
-  float *ring = lds;                       // [64][DP_PITCH]
-  float *prev = lds + 64 * DP_PITCH;       // [m+1]
-  const int b = P.dp_order[blockIdx.x];
-  const int n = P.n[b], m = P.m[b];
-  const int lane = threadIdx.x;
-  if (n == 0 || m == 0) {
+struct StripState {
+  float H, diag, pw, col;
+  uint32_t bits;
+};
+
+// 16 steps starting at t0 (a multiple of 16).  MASKED chunks (the first 64
+// steps and the steps past column m) update H only where 1 <= j <= m, so a
+// lane keeps H[i][0] until its column starts and keeps H[i][m] after it ends;
+// in between every lane is active.  Every step also shifts the last-row
+// collector (lane 63 enters), used by strips that have a successor.
+template <bool MASKED>
+static __device__ __forceinline__ void run16(StripState &st, const float *ring, int t0, int m, float g,
+                                             int lane) {
+  float4 sv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    sv[q] = *reinterpret_cast<const float4 *>(ring + lane * RPITCH + ((t0 + 4 * q) & (RING - 1)));
+  float H = st.H, diag = st.diag, pw = st.pw, col = st.col;
+  uint32_t bits = 0;
+  int d = t0 - lane;   // column - 1 of this lane at the current step
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const float4 v4 = sv[u >> 2];
+    const float s = (u & 3) == 0 ? v4.x : (u & 3) == 1 ? v4.y : (u & 3) == 2 ? v4.z : v4.w;
+    const float x = dpp_shr1(pw, H);   // H[i-1][j]: lane r-1, or the boundary row for lane 0
+    const float up = x + g;
+    const float left = H + g;
+    const float dg = diag + s;
+    const bool c1 = left > up;
+    const float b1 = c1 ? left : up;
+    const bool c2 = dg > b1;
+    const float best = c2 ? dg : b1;
+    const uint32_t code = c2 ? (uint32_t)DIR_DIAG : (c1 ? (uint32_t)DIR_LEFT : (uint32_t)DIR_UP);
+    if (MASKED) {
+      H = ((unsigned)d < (unsigned)m) ? best : H;
+      ++d;
+    } else {
+      H = best;
+    }
+    diag = x;
+    bits = (bits << 2) | code;
+    asm volatile("" : "+v"(bits));   // pack now: do not keep 16 steps of compare masks alive
+    pw = dpp_shl1(pw, pw);
+    col = dpp_shl1(H, col);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  st.H = H;
+  st.diag = diag;
+  st.pw = pw;
+  st.col = col;
+  st.bits = bits;
+}
+
+struct FillArgs {
+  int n_items, n_prog, B;
+  const int32_t *it_pair, *it_strip, *n, *m;
+  const int64_t *s_off, *tb_off, *bnd_off, *prog_off;
+};
+
+__global__ __launch_bounds__(64) void k_nw_reset(FillArgs A, int32_t *__restrict__ prog, int32_t *__restrict__ ctl,
+                                                 float g, float *__restrict__ score) {
+  const int tid = blockIdx.x * 64 + threadIdx.x;
+  for (int k = tid; k < A.n_prog; k += gridDim.x * 64) prog[k] = 0;
+  if (tid < 2) ctl[tid] = 0;   // [0] queue head, [1] error flag
+  for (int b = tid; b < A.B; b += gridDim.x * 64) {
+    const int n = A.n[b], m = A.m[b];
     // H[n][0] = fl32(n*g), H[0][m] = fl32(m*g), H[0][0] = +0
-    if (lane == 0) score[b] = (n + m == 0) ? 0.0f : (float)(n + m) * g;
-    return;
+    if (n == 0 || m == 0) score[b] = (n + m == 0) ? 0.0f : (float)(n + m) * g;
   }
-  const float *Sb = S + P.s_off[b];
-  TbWord *tbb = reinterpret_cast<TbWord *>(tb + P.tb_off[b]);
-  const int spad = steps_padded(m);
-  for (int j = lane; j <= m; j += 64) prev[j] = (float)j * g;   // first row H[0][j]
-  wave_sync();
-  const int nstrips = (n + 63) / 64;
-  for (int s = 0; s < nstrips; ++s) {
+}
+
+__global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restrict__ S, float g,
+                                                float *__restrict__ score, char *__restrict__ tb,
+                                                float *__restrict__ bnd, int32_t *__restrict__ prog,
+                                                int32_t *__restrict__ ctl) {
+  __shared__ __align__(16) float ring[64 * RPITCH];
+  const int lane = threadIdx.x;
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = atomicAdd(&ctl[0], 1);
+    item = uniform(item);
+    if (item >= A.n_items) break;
+    const int b = uniform(A.it_pair[item]);
+    const int s = uniform(A.it_strip[item]);
+    const int n = uniform(A.n[b]), m = uniform(A.m[b]);
+    const int nstrips = (n + 63) >> 6;
+    const bool last = s == nstrips - 1;
     const int i0 = 64 * s;
     const int rows = min(64, n - i0);
-    const int i = i0 + 1 + lane;
-    const bool vrow = lane < rows;
-    float H = (float)i * g;                 // first column H[i][0]
-    float diag = (float)i0 * g;             // lane 0: H[i0][0]
-    if (lane == 0) prev[0] = diag;
-    TbWord *tbs = tbb + (int64_t)s * spad;
+    const float *Sb = S + A.s_off[b];
+    const int64_t mstride = (int64_t)m + BND_PAD;
+    const float *in_row = bnd + A.bnd_off[b] + (int64_t)(s - 1) * mstride;   // used when s > 0
+    const int32_t *in_prog = prog + A.prog_off[b] + (s - 1);
+    float *out_row = bnd + A.bnd_off[b] + (int64_t)s * mstride;                     // used when !last
+    int32_t *out_prog = prog + A.prog_off[b] + s;
+    const int nG = (m + 63 + 63) >> 6;
+    uint4 *tbs = reinterpret_cast<uint4 *>(tb + A.tb_off[b]) + (int64_t)s * nG * 64;
     const int T_end = m + rows - 1;
-    // stage block 0, prefetch block 1
-    float R[DP_BW];
-    dp_load_block(R, Sb, i0, rows, m, 0, lane);
-    dp_store_block(R, ring, 0, lane);
-    dp_load_block(R, Sb, i0, rows, m, 1, lane);
-    wave_sync();
-    uint32_t w_up_lo = 0, w_up_hi = 0, w_lf_lo = 0, w_lf_hi = 0;
-    for (int t0 = 0; t0 < T_end; t0 += DP_BW) {
-      const int tq = t0 / DP_BW;
-      const int t1 = min(t0 + DP_BW, T_end);
-      for (int t = t0; t < t1; ++t) {
-        const int j = t - lane + 1;
-        const bool act = vrow && j >= 1 && j <= m;
-        const float from_above = shr1(H);
-        const float pv = prev[min(t + 1, m)];
-        const float up_in = (lane == 0) ? pv : from_above;
-        const float sv = ring[lane * DP_PITCH + ((t - lane) & (DP_RING_COLS - 1))];
-        const float up = up_in + g;
-        const float left = H + g;
-        const float dg = diag + sv;
-        float best = up;
-        int dir = DIR_UP;
-        if (left > best) {
-          best = left;
-          dir = DIR_LEFT;
+    const int T_pad = (T_end + 15) & ~15;
+    const int r_last = n - 1 - i0;   // lane of row n in the last strip
+    bool failed = false;
+
+    StripSrc src;
+    src.rs = __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(Sb + (int64_t)i0 * m), (short)0,
+                                               uniform(rows * m * 4), 0x00020000);
+    src.m = m;
+    src.rows = rows;
+    src.lane_off = ((lane >> 5) * m + (lane & (GROUP - 1)) - (lane >> 5)) * 4;
+
+    StripState st;
+    const int i = i0 + 1 + lane;
+    st.H = (float)i * g;                                    // H[i][0]
+    st.diag = (i0 == 0) ? 0.0f : (float)i0 * g;             // lane 0: H[i0][0]
+    st.col = 0.0f;
+    st.bits = 0u;
+    st.pw = 0.0f;
+    uint32_t w0 = 0u, w1 = 0u, w2 = 0u;
+
+    // S ring prologue: group 0 in the ring, group 1 in flight
+    float R[GROUP];
+#pragma nounroll
+    for (int q = 0; q < 2; ++q) {
+      load_group(R, src, q, lane);
+      if (q == 0) store_group(R, ring, 0, lane);
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    // Boundary window prev[tw + 1 + lane]: the first row, or the previous
+    // strip's last row published by another wave.  Published rows and their
+    // counters are agent-coherent (sc1) relaxed atomics: the producer drains
+    // its row stores before it bumps the counter, the consumer reads the row
+    // only after it has seen the counter.  No cache flushes are involved.
+    auto fetch_window = [&](int tw) -> float {
+      if (s == 0) return (float)(tw + 1 + lane) * g;
+      const int need = min(tw + 16, m);
+      int spins = 0;
+      while (uniform(__hip_atomic_load(in_prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < need) {
+        if (++spins > SPIN_LIMIT) {
+          failed = true;
+          break;
         }
-        if (dg > best) {
-          best = dg;
-          dir = DIR_DIAG;
-        }
-        if (act) H = best;
-        diag = up_in;
-        if (act && lane == rows - 1) prev[j] = H;
-        if (act && i == n && j == m) score[b] = H;
-        const uint64_t um = __ballot(act && dir == DIR_UP);
-        const uint64_t lm = __ballot(act && dir == DIR_LEFT);
-        const int tl = t & 63;
-        const bool mine = lane == tl;   // lane tl keeps step t's word
-        w_up_lo = mine ? (uint32_t)um : w_up_lo;
-        w_up_hi = mine ? (uint32_t)(um >> 32) : w_up_hi;
-        w_lf_lo = mine ? (uint32_t)lm : w_lf_lo;
-        w_lf_hi = mine ? (uint32_t)(lm >> 32) : w_lf_hi;
-        if (tl == 63 || t == T_end - 1) {
-          if (lane <= tl) {
-            TbWord w;
-            w.up_lo = w_up_lo;
-            w.up_hi = w_up_hi;
-            w.left_lo = w_lf_lo;
-            w.left_hi = w_lf_hi;
-            tbs[t - tl + lane] = w;
-          }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      return __hip_atomic_load(in_row + tw + 1 + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    float pw_next = fetch_window(0);
+    for (int t0 = 0; t0 < T_pad; t0 += 16) {
+      // window for this chunk was fetched one chunk ago; fetch the next one now
+      st.pw = pw_next;
+      if (t0 + 16 < T_pad) pw_next = fetch_window(t0 + 16);
+      if (failed) break;
+
+      if (t0 < 64 || t0 + 16 > m) run16<true>(st, ring, t0, m, g, lane);
+      else run16<false>(st, ring, t0, m, g, lane);
+
+      const int t_last = t0 + 15;
+      // direction words: 4 per 64-step block, one coalesced store per block
+      const int kword = (t0 >> 4) & 3;
+      if (kword == 0) w0 = st.bits;
+      else if (kword == 1) w1 = st.bits;
+      else if (kword == 2) w2 = st.bits;
+      if (kword == 3 || t0 + 16 >= T_pad) tbs[(int64_t)(t0 >> 6) * 64 + lane] = make_uint4(w0, w1, w2, st.bits);
+      // publish the strip's last row: lane l of the collector holds H of row
+      // 64 at step t_last - 63 + l, i.e. column t_last - 125 + l
+      if (!last) {
+        const int j = t_last - 125 + lane;
+        if (lane >= 48 && j >= 1 && j <= m)
+          __hip_atomic_store(out_row + j, st.col, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int done = min(t_last - 62, m);
+        if (done >= 1) {
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
+          __builtin_amdgcn_s_waitcnt(0);   // row stores complete before the counter moves
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
+          if (lane == 0) __hip_atomic_store(out_prog, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
-      // block tq+1 (prefetched) enters the ring; prefetch block tq+2
-      dp_store_block(R, ring, tq + 1, lane);
-      dp_load_block(R, Sb, i0, rows, m, tq + 2, lane);
-      wave_sync();
+      // S ring: after the second chunk of group q, group q+1 (loaded one
+      // group ago) enters the ring and the registers start loading group q+2
+      if ((t0 & (GROUP - 1)) == 16 && t0 + 16 < T_pad) {
+        const int q = t0 / GROUP;
+        store_group(R, ring, q + 1, lane);
+        load_group(R, src, q + 2, lane);
+        __builtin_amdgcn_wave_barrier();
+      }
     }
-    wave_sync();
+    if (last) {
+      // lane r_last stopped updating after column m: it holds H[n][m]
+      const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(st.H), r_last));
+      if (lane == 0 && !failed) score[b] = v;
+    }
+    if (failed && lane == 0) __hip_atomic_store(&ctl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -157,27 +311,28 @@ __global__ __launch_bounds__(64) void k_nw_walk(PlanDev P, const char *__restric
   const int lane = threadIdx.x;
   const int cap = min(n, m);
   int2 *pa = path + P.p_off[b];
-  const TbWord *tbb = reinterpret_cast<const TbWord *>(tb_bits + P.tb_off[b]);
-  const int spad = steps_padded(m);
+  const uint4 *tbw = reinterpret_cast<const uint4 *>(tb_bits + P.tb_off[b]);
+  const int nG = (m + 63 + 63) >> 6;
   int i = n, j = m, k = 0;
-  int ws = -1, wt0 = 0;
-  TbWord w = {0u, 0u, 0u, 0u};
+  int cs = -1, cG = -1;
+  uint4 w = make_uint4(0u, 0u, 0u, 0u);
   while (i > 0 && j > 0) {
     const int s = (i - 1) >> 6;
     const int r = (i - 1) & 63;
     const int t = j - 1 + r;
-    if (s != ws || t < wt0) {
-      ws = s;
-      wt0 = t & ~63;
-      w = tbb[(int64_t)s * spad + wt0 + lane];
+    const int G = t >> 6;
+    if (s != cs || G != cG) {
+      cs = s;
+      cG = G;
+      w = tbw[((int64_t)s * nG + G) * 64 + lane];
     }
-    const int idx = t - wt0;
-    const uint32_t uw = (uint32_t)__builtin_amdgcn_readlane((int)(r < 32 ? w.up_lo : w.up_hi), idx);
-    const uint32_t lw = (uint32_t)__builtin_amdgcn_readlane((int)(r < 32 ? w.left_lo : w.left_hi), idx);
-    const uint32_t bit = 1u << (r & 31);
-    if (uw & bit) {
+    const int kk = (t >> 4) & 3;
+    const uint32_t word = kk == 0 ? w.x : kk == 1 ? w.y : kk == 2 ? w.z : w.w;
+    const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)word, r);
+    const uint32_t code = (v >> (2 * (15 - (t & 15)))) & 3u;
+    if (code == DIR_UP) {
       --i;
-    } else if (lw & bit) {
+    } else if (code == DIR_LEFT) {
       --j;
     } else {
       ++k;
@@ -216,12 +371,44 @@ __global__ __launch_bounds__(64) void k_keep(PlanDev P, const float *__restrict_
   if (lane == 0) n_kept[b] = nk;
 }
 
-size_t fill_lds_bytes(int max_m) { return sizeof(float) * (64 * DP_PITCH + (size_t)max_m + 1); }
+static int g_fill_grid = 0;
 
-hipError_t launch_nw_fill(const PlanDev &P, int max_m, const float *S, float g, float *score, char *tb,
-                          hipStream_t st) {
+hipError_t fill_set_attrs(int) {
+  if (g_fill_grid == 0) {
+    int dev = 0, cus = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_nw_fill, 64, 0);
+    if (e != hipSuccess) return e;
+    g_fill_grid = cus * (per > 0 ? per : 1);
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *score, char *tb, float *bnd,
+                          int32_t *prog, int32_t *ctl, hipStream_t st) {
   if (P.B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_nw_fill, dim3(P.B), dim3(64), fill_lds_bytes(max_m), st, P, S, g, score, tb);
+  FillArgs A;
+  A.n_items = P.n_items;
+  A.n_prog = P.n_prog;
+  A.B = P.B;
+  A.it_pair = P.it_pair;
+  A.it_strip = P.it_strip;
+  A.n = P.n;
+  A.m = P.m;
+  A.s_off = P.s_off;
+  A.tb_off = P.tb_off;
+  A.bnd_off = P.bnd_off;
+  A.prog_off = P.prog_off;
+  hipLaunchKernelGGL(k_nw_reset, dim3(64), dim3(64), 0, st, A, prog, ctl, g, score);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || P.n_items <= 0) return e;
+  if (g_fill_grid == 0) {
+    e = fill_set_attrs(0);
+    if (e != hipSuccess) return e;
+  }
+  const int grid = P.n_items < g_fill_grid ? P.n_items : g_fill_grid;
+  hipLaunchKernelGGL(k_nw_fill, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, prog, ctl);
   return hipGetLastError();
 }
 
@@ -236,11 +423,6 @@ hipError_t launch_keep(const PlanDev &P, const float *S, float thr, const int2 *
   if (P.B <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_keep, dim3(P.B), dim3(64), 0, st, P, S, thr, path, n_diag, kept, n_kept);
   return hipGetLastError();
-}
-
-hipError_t fill_set_attrs(int max_m) {
-  return hipFuncSetAttribute((const void *)k_nw_fill, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)fill_lds_bytes(max_m));
 }
 
 }  // namespace nwm

@@ -25,9 +25,9 @@ hipError_t launch_score(const PlanDev &, bool, const int64_t *, const int64_t *,
                         const uint32_t *, const int32_t *, nwm_scorer, float *, float *, hipStream_t);
 size_t score_lds_bytes(int nch, bool bf16);
 hipError_t score_set_attrs(int nch_max);
-hipError_t launch_nw_fill(const PlanDev &, int, const float *, float, float *, char *, hipStream_t);
-size_t fill_lds_bytes(int max_m);
-hipError_t fill_set_attrs(int max_m);
+hipError_t launch_nw_fill(const PlanDev &, const float *, float, float *, char *, float *, int32_t *, int32_t *,
+                          hipStream_t);
+hipError_t fill_set_attrs(int);
 hipError_t launch_nw_walk(const PlanDev &, const char *, int2 *, int32_t *, hipStream_t);
 hipError_t launch_keep(const PlanDev &, const float *, float, const int2 *, const int32_t *, int2 *, int32_t *,
                        hipStream_t);
@@ -197,7 +197,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
     s_off[b + 1] = s_off[b] + nb * mb;
     p_off[b + 1] = p_off[b] + std::min(nb, mb);
     int64_t bits = 0;
-    if (nb > 0 && mb > 0) bits = ((nb + 63) / 64) * (((mb + 63 + 63) / 64) * 64) * (int64_t)sizeof(TbWord);
+    if (nb > 0 && mb > 0) bits = ((nb + 63) / 64) * ((mb + 63 + 63) / 64) * 1024;
     tb_off[b + 1] = tb_off[b] + bits;
     const int rt0 = (int)rt_pair.size(), ct0 = (int)ct_pair.size();
     for (int r = 0; r < nb; r += TM) {
@@ -224,6 +224,24 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
     return (int64_t)p->n[a] * p->m[a] > (int64_t)p->n[c] * p->m[c];
   });
+  // DP work items: every strip of every non-empty pair, longest pair first;
+  // boundary rows and progress counters between consecutive strips
+  std::vector<int32_t> it_pair, it_strip;
+  std::vector<int64_t> bnd_off(B + 1, 0), prog_off(B + 1, 0);
+  for (int b = 0; b < B; ++b) {
+    const int64_t ns = (p->n[b] > 0 && p->m[b] > 0) ? (p->n[b] + 63) / 64 : 0;
+    const int64_t links = ns > 0 ? ns - 1 : 0;
+    bnd_off[b + 1] = bnd_off[b] + links * ((int64_t)p->m[b] + BND_PAD);
+    prog_off[b + 1] = prog_off[b] + links;
+  }
+  for (int q = 0; q < B; ++q) {
+    const int b = order[q];
+    if (p->n[b] <= 0 || p->m[b] <= 0) continue;
+    for (int s = 0; s < (p->n[b] + 63) / 64; ++s) {
+      it_pair.push_back(b);
+      it_strip.push_back(s);
+    }
+  }
   // ---- device metadata: one allocation -----------------------------------------
   struct Piece {
     const void *src;
@@ -247,6 +265,8 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   size_t i_cn = add(ct_cols.data(), 4 * ct_cols.size());
   size_t i_gr = add(gt_rt.data(), 4 * gt_rt.size()), i_gc = add(gt_ct.data(), 4 * gt_ct.size());
   size_t i_do = add(order.data(), 4 * order.size());
+  size_t i_ip = add(it_pair.data(), 4 * it_pair.size()), i_is = add(it_strip.data(), 4 * it_strip.size());
+  size_t i_bo = add(bnd_off.data(), 8 * (size_t)(B + 1)), i_pg = add(prog_off.data(), 8 * (size_t)(B + 1));
   if (hipSetDevice(ctx->device) != hipSuccess) {
     delete p;
     return NWM_EDEVICE;
@@ -289,6 +309,12 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   D.gt_rt = (const int32_t *)at(i_gr);
   D.gt_ct = (const int32_t *)at(i_gc);
   D.dp_order = (const int32_t *)at(i_do);
+  D.n_items = (int)it_pair.size();
+  D.it_pair = (const int32_t *)at(i_ip);
+  D.it_strip = (const int32_t *)at(i_is);
+  D.bnd_off = (const int64_t *)at(i_bo);
+  D.prog_off = (const int64_t *)at(i_pg);
+  D.n_prog = (int)prog_off[B];
   D.path_base = (int64_t)align_up((size_t)tb_off[B], 256);
   // ---- workspace layout ------------------------------------------------------------
   WsLayout &W = p->ws;
@@ -306,14 +332,16 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   W.b_list = carve(4 * (size_t)p->tgt_tokens);
   W.b_choff = carve(4 * (size_t)D.n_ct * (size_t)(nch + 1));
   W.bwd = carve(16 * ((size_t)B + (size_t)D.n_rt));
+  W.bnd = carve(4 * (size_t)bnd_off[B]);
+  W.prog = carve(4 * (size_t)prog_off[B]);
+  W.ctl = carve(8);
   W.total = o;
   p->sizes.S_elems = (size_t)s_off[B];
   p->sizes.kept_cap = (size_t)p_off[B];
   p->sizes.tb_bytes = (size_t)D.path_base + 8 * (size_t)p_off[B];
   p->sizes.ws_bytes = W.total;
   // ---- kernel attributes (dynamic LDS above the default) ---------------------------
-  if (merge_set_attrs(p->V) != hipSuccess || score_set_attrs(nch) != hipSuccess ||
-      fill_set_attrs(p->max_m) != hipSuccess) {
+  if (merge_set_attrs(p->V) != hipSuccess || score_set_attrs(nch) != hipSuccess || fill_set_attrs(0) != hipSuccess) {
     (void)hipFree(p->dmeta);
     delete p;
     return NWM_EDEVICE;
@@ -383,20 +411,22 @@ nwm_status nwm_score_pairs(nwm_plan *p, const nwm_batch *batch, const nwm_dict *
 
 nwm_status nwm_align_batch(nwm_plan *p, const float *S, float gap, float threshold, float *score,
                            int32_t *n_diag, int32_t *kept, int32_t *n_kept, void *tb, void *ws, void *stream) {
-  (void)ws;
   if (!p) return NWM_EINVAL;
   if (!finite(gap) || !finite(threshold)) return NWM_EINVAL;
   if (p->B == 0) return NWM_OK;
   if (!score || !n_diag || !n_kept) return NWM_EINVAL;
   if (p->sizes.S_elems > 0 && !S) return NWM_EINVAL;
   if (p->sizes.kept_cap > 0 && (!kept || !tb)) return NWM_EINVAL;
+  if (!ws) return NWM_EINVAL;
   hipStream_t st = (hipStream_t)stream;
+  char *w = static_cast<char *>(ws);
   char *tbc = static_cast<char *>(tb);
   int2 *path = tbc ? (int2 *)(tbc + p->dev.path_base) : nullptr;
   hipError_t e;
   {
     Mark mk(p, K_FILL, st);
-    e = launch_nw_fill(p->dev, p->max_m, S, gap, score, tbc, st);
+    e = launch_nw_fill(p->dev, S, gap, score, tbc, (float *)(w + p->ws.bnd), (int32_t *)(w + p->ws.prog),
+                       (int32_t *)(w + p->ws.ctl), st);
     mk.done();
   }
   if (e != hipSuccess) return NWM_EDEVICE;

@@ -29,20 +29,15 @@ constexpr int MAX_V = 32768;          // u16 owner table in LDS
 constexpr int MAX_DEG = 64;
 
 // ---- NW wavefront -----------------------------------------------------------
-constexpr int DP_BW = 32;             // S block width (columns) staged per phase
-constexpr int DP_RING = 4;            // blocks held in the LDS ring
-constexpr int DP_RING_COLS = DP_BW * DP_RING;
-constexpr int DP_PITCH = DP_RING_COLS + 2;   // ring row pitch (floats)
-constexpr int MAX_M = 16383;          // previous-row buffer in LDS
+constexpr int BND_PAD = 192;          // slack floats after each published boundary row
+constexpr int MAX_M = 1 << 22;        // per-pair target sentences (64-row strip of S < 1 GiB)
 
 // Direction codes of the traceback.
 constexpr int DIR_DIAG = 0, DIR_UP = 1, DIR_LEFT = 2;
 
-// One traceback word: the UP and LEFT bits of the 64 rows of a strip at one
-// anti-diagonal step (DIAG = neither bit).
-struct TbWord {
-  uint32_t up_lo, up_hi, left_lo, left_hi;
-};
+// Traceback bits: per pair, per 64-row strip, per 64-step block, per lane
+// (row) one uint4 = four 32-bit words of 16 steps x 2 bits (first step in the
+// high bits).  ceil((m + 63) / 64) blocks per strip, 1 KiB per block.
 
 // Device-resident per-pair metadata of a plan.
 struct PlanDev {
@@ -64,8 +59,13 @@ struct PlanDev {
   // contraction tiles: (row tile, column tile)
   int n_gt;
   const int32_t *gt_rt, *gt_ct;
-  // DP order (longest first)
+  // DP order (longest first) and DP work items (pair, strip), longest pair first
   const int32_t *dp_order;
+  int n_items;
+  const int32_t *it_pair, *it_strip;
+  const int64_t *bnd_off;   // [B+1] float offset of a pair's published boundary rows
+  const int64_t *prog_off;  // [B+1] offset of a pair's progress counters
+  int n_prog;               // total progress counters (sum over pairs of strips - 1)
 };
 
 // Workspace layout (byte offsets into the caller's ws).
@@ -77,6 +77,9 @@ struct WsLayout {
   size_t b_list;     // uint32 lds offset [tgt_tokens]
   size_t b_choff;    // int32 [n_ct * (nch + 1)]
   size_t bwd;        // float [B * 4] per-pair partials + float [n_blocks * 4]
+  size_t bnd;        // float boundary rows between strips
+  size_t prog;       // int32 [n_prog] progress counters
+  size_t ctl;        // int32 [2]: DP queue head, error flag
   size_t total;
 };
 
