@@ -15,17 +15,17 @@
 //             wave shift.  The strip's top boundary (the previous strip's last
 //             row) enters lane 0 through a 64-lane register window shifted one
 //             lane per step; the strip's own last row leaves through a second
-//             shifted window and is published every 16 steps behind a progress
-//             counter (agent-coherent stores, no cache flushes), so the next
-//             strip runs concurrently on another wave about 100 steps behind
-//             (bounded poll).
+//             shifted window and is published every 16 steps as epoch-tagged
+//             64-bit agent-coherent stores (no counters, no cache flushes), so
+//             the next strip runs concurrently on another wave about 100 steps
+//             behind (bounded re-read).
 //             S is staged through an LDS ring whose slot index equals the step
 //             index (row r of column c lands in slot c + r), so every lane reads
 //             the same slot and one ds_read_b128 serves four steps; the ring is
 //             fed one 32-step group ahead through registers.  Each lane packs
 //             its 2-bit directions, 16 steps per word, and every 64 steps the
 //             wave writes one coalesced 1 KiB block.  H never reaches HBM.
-// k_nw_reset  zeroes the queue and progress counters; scores of empty pairs.
+// k_nw_reset  zeroes the queue; scores of empty pairs.
 // k_nw_walk   traceback from (n, m): one wave per pair holds one 64-step block
 //             of its strip (one 16-byte word per lane) and reads it with
 //             uniform-index readlane.  Aligned pairs are written right-aligned
@@ -163,15 +163,14 @@ static __device__ __forceinline__ void run16(StripState &st, const float *ring, 
 }
 
 struct FillArgs {
-  int n_items, n_prog, B;
+  int n_items, B;
   const int32_t *it_pair, *it_strip, *n, *m;
-  const int64_t *s_off, *tb_off, *bnd_off, *prog_off;
+  const int64_t *s_off, *tb_off, *bnd_off;
 };
 
-__global__ __launch_bounds__(64) void k_nw_reset(FillArgs A, int32_t *__restrict__ prog, int32_t *__restrict__ ctl,
-                                                 float g, float *__restrict__ score) {
+__global__ __launch_bounds__(64) void k_nw_reset(FillArgs A, int32_t *__restrict__ ctl, float g,
+                                                 float *__restrict__ score) {
   const int tid = blockIdx.x * 64 + threadIdx.x;
-  for (int k = tid; k < A.n_prog; k += gridDim.x * 64) prog[k] = 0;
   if (tid < 2) ctl[tid] = 0;   // [0] queue head, [1] error flag
   for (int b = tid; b < A.B; b += gridDim.x * 64) {
     const int n = A.n[b], m = A.m[b];
@@ -182,7 +181,7 @@ __global__ __launch_bounds__(64) void k_nw_reset(FillArgs A, int32_t *__restrict
 
 __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restrict__ S, float g,
                                                 float *__restrict__ score, char *__restrict__ tb,
-                                                float *__restrict__ bnd, int32_t *__restrict__ prog,
+                                                uint64_t *__restrict__ bnd, uint32_t epoch,
                                                 int32_t *__restrict__ ctl) {
   __shared__ __align__(16) float ring[64 * RPITCH];
   const int lane = threadIdx.x;
@@ -200,10 +199,8 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     const int rows = min(64, n - i0);
     const float *Sb = S + A.s_off[b];
     const int64_t mstride = (int64_t)m + BND_PAD;
-    const float *in_row = bnd + A.bnd_off[b] + (int64_t)(s - 1) * mstride;   // used when s > 0
-    const int32_t *in_prog = prog + A.prog_off[b] + (s - 1);
-    float *out_row = bnd + A.bnd_off[b] + (int64_t)s * mstride;                     // used when !last
-    int32_t *out_prog = prog + A.prog_off[b] + s;
+    const uint64_t *in_row = bnd + A.bnd_off[b] + (int64_t)(s - 1) * mstride;   // used when s > 0
+    uint64_t *out_row = bnd + A.bnd_off[b] + (int64_t)s * mstride;               // used when !last
     const int nG = (m + 63 + 63) >> 6;
     uint4 *tbs = reinterpret_cast<uint4 *>(tb + A.tb_off[b]) + (int64_t)s * nG * 64;
     const int T_end = m + rows - 1;
@@ -237,29 +234,36 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     __builtin_amdgcn_wave_barrier();
 
     // Boundary window prev[tw + 1 + lane]: the first row, or the previous
-    // strip's last row published by another wave.  Published rows and their
-    // counters are agent-coherent (sc1) relaxed atomics: the producer drains
-    // its row stores before it bumps the counter, the consumer reads the row
-    // only after it has seen the counter.  No cache flushes are involved.
-    auto fetch_window = [&](int tw) -> float {
-      if (s == 0) return (float)(tw + 1 + lane) * g;
-      const int need = min(tw + 16, m);
-      int spins = 0;
-      while (uniform(__hip_atomic_load(in_prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < need) {
-        if (++spins > SPIN_LIMIT) {
-          failed = true;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    // strip's last row published by another wave.  Every published value is
+    // one 64-bit agent-coherent (sc1) store of (value, launch epoch), so a
+    // consumer knows a value is there when its tag matches: no counters, no
+    // store drains and no cache flushes.  The window of the next chunk is
+    // loaded one chunk ahead and re-read (bounded) only if incomplete.
+    auto load_window = [&](int tw) -> uint64_t {
       return __hip_atomic_load(in_row + tw + 1 + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
-    float pw_next = fetch_window(0);
+    auto window_ready = [&](uint64_t v, int tw) -> bool {
+      // lanes 0..15 feed the next 16 steps; columns beyond m are never used
+      const bool need = lane < 16 && tw + 1 + lane <= m;
+      return __ballot(need && (uint32_t)(v >> 32) != epoch) == 0;
+    };
+    uint64_t wv = (s > 0) ? load_window(0) : 0ull;
     for (int t0 = 0; t0 < T_pad; t0 += 16) {
-      // window for this chunk was fetched one chunk ago; fetch the next one now
-      st.pw = pw_next;
-      if (t0 + 16 < T_pad) pw_next = fetch_window(t0 + 16);
+      if (s > 0) {
+        int spins = 0;
+        while (!window_ready(wv, t0)) {
+          if (++spins > SPIN_LIMIT) {
+            failed = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          wv = load_window(t0);
+        }
+        st.pw = __uint_as_float((uint32_t)wv);
+        if (t0 + 16 < T_pad) wv = load_window(t0 + 16);
+      } else {
+        st.pw = (float)(t0 + 1 + lane) * g;
+      }
       if (failed) break;
 
       if (t0 < 64 || t0 + 16 > m) run16<true>(st, ring, t0, m, g, lane);
@@ -277,14 +281,8 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
       if (!last) {
         const int j = t_last - 125 + lane;
         if (lane >= 48 && j >= 1 && j <= m)
-          __hip_atomic_store(out_row + j, st.col, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int done = min(t_last - 62, m);
-        if (done >= 1) {
-          __atomic_signal_fence(__ATOMIC_SEQ_CST);
-          __builtin_amdgcn_s_waitcnt(0);   // row stores complete before the counter moves
-          __atomic_signal_fence(__ATOMIC_SEQ_CST);
-          if (lane == 0) __hip_atomic_store(out_prog, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+          __hip_atomic_store(out_row + j, ((uint64_t)epoch << 32) | __float_as_uint(st.col), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
       }
       // S ring: after the second chunk of group q, group q+1 (loaded one
       // group ago) enters the ring and the registers start loading group q+2
@@ -385,12 +383,11 @@ hipError_t fill_set_attrs(int) {
   return hipSuccess;
 }
 
-hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *score, char *tb, float *bnd,
-                          int32_t *prog, int32_t *ctl, hipStream_t st) {
+hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *score, char *tb, uint64_t *bnd,
+                          uint32_t epoch, int32_t *ctl, hipStream_t st) {
   if (P.B <= 0) return hipSuccess;
   FillArgs A;
   A.n_items = P.n_items;
-  A.n_prog = P.n_prog;
   A.B = P.B;
   A.it_pair = P.it_pair;
   A.it_strip = P.it_strip;
@@ -399,8 +396,7 @@ hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *scor
   A.s_off = P.s_off;
   A.tb_off = P.tb_off;
   A.bnd_off = P.bnd_off;
-  A.prog_off = P.prog_off;
-  hipLaunchKernelGGL(k_nw_reset, dim3(64), dim3(64), 0, st, A, prog, ctl, g, score);
+  hipLaunchKernelGGL(k_nw_reset, dim3(64), dim3(64), 0, st, A, ctl, g, score);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || P.n_items <= 0) return e;
   if (g_fill_grid == 0) {
@@ -408,7 +404,7 @@ hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *scor
     if (e != hipSuccess) return e;
   }
   const int grid = P.n_items < g_fill_grid ? P.n_items : g_fill_grid;
-  hipLaunchKernelGGL(k_nw_fill, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, prog, ctl);
+  hipLaunchKernelGGL(k_nw_fill, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, epoch, ctl);
   return hipGetLastError();
 }
 

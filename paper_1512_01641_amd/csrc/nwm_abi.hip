@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -25,7 +26,7 @@ hipError_t launch_score(const PlanDev &, bool, const int64_t *, const int64_t *,
                         const uint32_t *, const int32_t *, nwm_scorer, float *, float *, hipStream_t);
 size_t score_lds_bytes(int nch, bool bf16);
 hipError_t score_set_attrs(int nch_max);
-hipError_t launch_nw_fill(const PlanDev &, const float *, float, float *, char *, float *, int32_t *, int32_t *,
+hipError_t launch_nw_fill(const PlanDev &, const float *, float, float *, char *, uint64_t *, uint32_t, int32_t *,
                           hipStream_t);
 hipError_t fill_set_attrs(int);
 hipError_t launch_nw_walk(const PlanDev &, const char *, int2 *, int32_t *, hipStream_t);
@@ -116,6 +117,14 @@ struct Mark {
 };
 
 bool finite(float x) { return std::isfinite(x); }
+
+// Tag of one NW launch: boundary rows published between strips carry it, so
+// values left in the workspace by earlier launches are never taken as ready.
+uint32_t next_epoch() {
+  static std::atomic<uint32_t> epoch{0x9E3779B9u};
+  uint32_t e = epoch.fetch_add(1, std::memory_order_relaxed) + 1;
+  return e == 0 ? next_epoch() : e;
+}
 
 }  // namespace
 
@@ -225,14 +234,13 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
     return (int64_t)p->n[a] * p->m[a] > (int64_t)p->n[c] * p->m[c];
   });
   // DP work items: every strip of every non-empty pair, longest pair first;
-  // boundary rows and progress counters between consecutive strips
+  // boundary rows between consecutive strips
   std::vector<int32_t> it_pair, it_strip;
-  std::vector<int64_t> bnd_off(B + 1, 0), prog_off(B + 1, 0);
+  std::vector<int64_t> bnd_off(B + 1, 0);
   for (int b = 0; b < B; ++b) {
     const int64_t ns = (p->n[b] > 0 && p->m[b] > 0) ? (p->n[b] + 63) / 64 : 0;
     const int64_t links = ns > 0 ? ns - 1 : 0;
     bnd_off[b + 1] = bnd_off[b] + links * ((int64_t)p->m[b] + BND_PAD);
-    prog_off[b + 1] = prog_off[b] + links;
   }
   for (int q = 0; q < B; ++q) {
     const int b = order[q];
@@ -266,7 +274,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   size_t i_gr = add(gt_rt.data(), 4 * gt_rt.size()), i_gc = add(gt_ct.data(), 4 * gt_ct.size());
   size_t i_do = add(order.data(), 4 * order.size());
   size_t i_ip = add(it_pair.data(), 4 * it_pair.size()), i_is = add(it_strip.data(), 4 * it_strip.size());
-  size_t i_bo = add(bnd_off.data(), 8 * (size_t)(B + 1)), i_pg = add(prog_off.data(), 8 * (size_t)(B + 1));
+  size_t i_bo = add(bnd_off.data(), 8 * (size_t)(B + 1));
   if (hipSetDevice(ctx->device) != hipSuccess) {
     delete p;
     return NWM_EDEVICE;
@@ -313,8 +321,6 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   D.it_pair = (const int32_t *)at(i_ip);
   D.it_strip = (const int32_t *)at(i_is);
   D.bnd_off = (const int64_t *)at(i_bo);
-  D.prog_off = (const int64_t *)at(i_pg);
-  D.n_prog = (int)prog_off[B];
   D.path_base = (int64_t)align_up((size_t)tb_off[B], 256);
   // ---- workspace layout ------------------------------------------------------------
   WsLayout &W = p->ws;
@@ -332,8 +338,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   W.b_list = carve(4 * (size_t)p->tgt_tokens);
   W.b_choff = carve(4 * (size_t)D.n_ct * (size_t)(nch + 1));
   W.bwd = carve(16 * ((size_t)B + (size_t)D.n_rt));
-  W.bnd = carve(4 * (size_t)bnd_off[B]);
-  W.prog = carve(4 * (size_t)prog_off[B]);
+  W.bnd = carve(8 * (size_t)bnd_off[B]);
   W.ctl = carve(8);
   W.total = o;
   p->sizes.S_elems = (size_t)s_off[B];
@@ -425,7 +430,7 @@ nwm_status nwm_align_batch(nwm_plan *p, const float *S, float gap, float thresho
   hipError_t e;
   {
     Mark mk(p, K_FILL, st);
-    e = launch_nw_fill(p->dev, S, gap, score, tbc, (float *)(w + p->ws.bnd), (int32_t *)(w + p->ws.prog),
+    e = launch_nw_fill(p->dev, S, gap, score, tbc, (uint64_t *)(w + p->ws.bnd), next_epoch(),
                        (int32_t *)(w + p->ws.ctl), st);
     mk.done();
   }

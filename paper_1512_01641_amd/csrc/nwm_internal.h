@@ -63,9 +63,7 @@ struct PlanDev {
   const int32_t *dp_order;
   int n_items;
   const int32_t *it_pair, *it_strip;
-  const int64_t *bnd_off;   // [B+1] float offset of a pair's published boundary rows
-  const int64_t *prog_off;  // [B+1] offset of a pair's progress counters
-  int n_prog;               // total progress counters (sum over pairs of strips - 1)
+  const int64_t *bnd_off;   // [B+1] offset of a pair's published boundary rows (uint64 units)
 };
 
 // Workspace layout (byte offsets into the caller's ws).
@@ -77,8 +75,7 @@ struct WsLayout {
   size_t b_list;     // uint32 lds offset [tgt_tokens]
   size_t b_choff;    // int32 [n_ct * (nch + 1)]
   size_t bwd;        // float [B * 4] per-pair partials + float [n_blocks * 4]
-  size_t bnd;        // float boundary rows between strips
-  size_t prog;       // int32 [n_prog] progress counters
+  size_t bnd;        // uint64 (value, epoch) boundary rows between strips
   size_t ctl;        // int32 [2]: DP queue head, error flag
   size_t total;
 };
