@@ -75,6 +75,10 @@ def main():
     ap.add_argument("--pairs", type=int, default=None, help="fewer pairs of the same workload (testing)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
+    ap.add_argument("--prec", choices=("both", "bf16", "f32"), default="both")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="run a plain device copy of MIB MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
@@ -99,22 +103,45 @@ def main():
     w, gap, thr = batch.scorer, batch.gap, batch.threshold
     torch.cuda.synchronize()
 
+    if args.copy_probe:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # give the factor that turns counter readings into bytes
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        _log("copy probe: %d bytes read, %d bytes written per copy" % (nbytes, nbytes))
+        del src, dst
+
+    precs = [p for p in (("bf16", nw.NWM_BF16), ("f32", nw.NWM_FP32)) if args.prec in ("both", p[0])]
     results = {}
+    eager = {}
     kernel = {}
-    for prec_name, prec in (("bf16", nw.NWM_BF16), ("f32", nw.NWM_FP32)):
+    for prec_name, prec in precs:
         _log("batched %s" % prec_name)
         mn = nw.Miner(ctx, db, dd, prec)
         step = lambda mn=mn: mn.mine(w, gap, thr)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
+        # timed region 1: eager launches, every kernel bracketed by HIP events
+        # on the stream it runs on
         mn.plan.set_timing(True)
         ms = _time_steps(step, args.steps, 0, torch)
         km = mn.plan.kernel_ms(reset=True)
         mn.plan.set_timing(False)
-        results[prec_name] = ms
+        eager[prec_name] = ms
         kernel[prec_name] = {k: (v[0] / max(v[1], 1)) for k, v in km.items() if v[1]}
         kernel[prec_name + "_launches_per_step"] = {k: v[1] / args.steps for k, v in km.items() if v[1]}
+        results[prec_name] = ms
+        if not args.no_graph:
+            # timed region 2: the whole path as one captured HIP graph per step
+            gstep = lambda mn=mn: mn.mine(w, gap, thr, graph=True)
+            results[prec_name] = _time_steps(gstep, args.steps, max(args.warmup, 1), torch)
+        _log("%s: eager %.4f ms/step, %s %.4f ms/step" % (prec_name, ms, "eager" if args.no_graph else "graph",
+                                                          results[prec_name]))
         del mn
 
     plain = None
@@ -137,9 +164,10 @@ def main():
         plain = _time_steps(plain_pass, 1, 1, torch)
         del miners
 
-    bf_ms = results["bf16"]
+    head = precs[0][0]
+    bf_ms = results[head]
     value = B / (bf_ms / 1000.0)
-    kb = kernel["bf16"]
+    kb = kernel[head]
     score_ms = kb.get("score", float("nan"))
     fill_ms = kb.get("nw_fill", float("nan"))
     flops = 2.0 * V * cells
@@ -157,20 +185,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": head,
         "data": "synthetic (seeded comparable-corpus generator with planted alignments)",
         "config": {"workload": "%d document pairs, sentence counts lognormal median 60 clipped 20-2000 "
                                "(+-30%% skew), V=%d hashed vocab, Zipf(1.1) tokens, BF16 contraction operands, "
                                "FP32 DP, gap -0.2, threshold 0.5" % (B, V),
                    "pairs": B, "cells": cells, "V": V},
         "gcups": round(gcups, 3),
-        "pairs_per_s_batched_fp32": round(B / (results["f32"] / 1000.0), 2),
+        "launch": "eager" if args.no_graph else "hipGraph replay of the whole path per step",
+        "ms_per_step_eager": {p: round(v, 4) for p, v in eager.items()},
+        "pairs_per_s_batched_fp32": round(B / (results["f32"] / 1000.0), 2) if "f32" in results else None,
         "pairs_per_s_plain_fp32": round(B / (plain / 1000.0), 2) if plain else None,
         "ratio_batched_bf16_vs_plain_fp32": round(plain / bf_ms, 2) if plain else None,
-        "kernel_ms_per_step": {p: {k: round(v, 4) for k, v in kernel[p].items()} for p in ("bf16", "f32")},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": MFMA_PEAK_TFLOPS["bf16"],
-                     "unit": "TFLOP/s", "frac": round(achieved / MFMA_PEAK_TFLOPS["bf16"], 4), "traffic": None,
-                     "kernel": "k_score<bf16> (contraction + logistic epilogue)",
+        "kernel_ms_per_step": {p: {k: round(v, 4) for k, v in kernel[p].items()} for p, _ in precs},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": MFMA_PEAK_TFLOPS[head],
+                     "unit": "TFLOP/s", "frac": round(achieved / MFMA_PEAK_TFLOPS[head], 4), "traffic": None,
+                     "kernel": "k_score<%s> (contraction + logistic epilogue)" % head,
                      "algorithmic": "2*V*sum(n*m) = %.4g flop per launch" % flops},
         "dp_roofline": {"bound": "hbm", "achieved": round(dp_bytes / (fill_ms / 1000.0) / 1e9, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -182,6 +182,19 @@ nwm_status nwm_align_backward(nwm_plan *plan, const nwm_batch *batch, const void
                               const float *S, const float *S_raw, nwm_scorer scorer,
                               double *grad_wb, void *ws, void *stream);
 
+/* Score then align (nwm_score_pairs followed by nwm_align_batch, same
+ * arguments and layouts) in one call.  With graphs enabled on the plan
+ * (nwm_plan_set_graph), the first call for a given set of arguments captures
+ * the plan's kernels into a HIP graph on a stream of the library's own and
+ * every later call with the same arguments replays the whole path with one
+ * graph launch on `stream` (Sec. 5: one session over many document pairs).
+ * Changing any argument recaptures.  Per-kernel timing is not recorded for
+ * graph replays. */
+nwm_status nwm_mine(nwm_plan *plan, const nwm_batch *batch, const nwm_dict *dict, nwm_scorer scorer, float gap,
+                    float threshold, float *S, float *S_raw, float *score, int32_t *n_diag, int32_t *kept,
+                    int32_t *n_kept, void *tb, void *ws, void *stream);
+nwm_status nwm_plan_set_graph(nwm_plan *plan, int on);
+
 /* --- measurement ------------------------------------------------------------ */
 
 /* Record HIP events around every kernel the plan launches (0 = off).  While

@@ -134,6 +134,9 @@ class Plan:
     def workspace(self):
         return torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=self.ctx.device)
 
+    def set_graph(self, on: bool):
+        _abi.check(self.lib.nwm_plan_set_graph(self.h, int(bool(on))), "nwm_plan_set_graph")
+
     def set_timing(self, on: bool):
         _abi.check(self.lib.nwm_plan_set_timing(self.h, int(bool(on))), "nwm_plan_set_timing")
 
@@ -187,6 +190,14 @@ def align_backward(plan: Plan, batch: DeviceBatch, tb, n_diag, grad_score, grad_
                                            _stream(plan.ctx.device)), "nwm_align_backward")
 
 
+def mine(plan: Plan, batch: DeviceBatch, dic: DeviceDict, scorer, gap: float, threshold: float, S, S_raw, score,
+         n_diag, kept, n_kept, tb, ws=None):
+    ws = plan.workspace() if ws is None else ws
+    _abi.check(plan.lib.nwm_mine(plan.h, ctypes.byref(batch.c()), ctypes.byref(dic.c()), _scorer(scorer), float(gap),
+                                 float(threshold), _ptr(S), _ptr(S_raw), _ptr(score), _ptr(n_diag), _ptr(kept),
+                                 _ptr(n_kept), _ptr(tb), _ptr(ws), _stream(plan.ctx.device)), "nwm_mine")
+
+
 class Miner:
     """Owns a plan and the device buffers of one batch: score -> align -> keep."""
 
@@ -214,9 +225,19 @@ class Miner:
         align_batch(self.plan, self.S if S is None else S, gap, threshold, self.score, self.n_diag, self.kept,
                     self.n_kept, self.tb, self.ws)
 
-    def mine(self, scorer, gap: float, threshold: float):
-        self.score_pairs(scorer)
-        self.align(gap, threshold)
+    def mine(self, scorer, gap: float, threshold: float, graph: bool = False, want_raw: bool = False):
+        """Score then align.  graph=True replays one captured HIP graph of the
+        whole path (captured on the first call with these arguments).  S_raw
+        is written only with want_raw (the backward needs it, mining does not)."""
+        if not graph:
+            self.score_pairs(scorer, want_raw=want_raw)
+            self.align(gap, threshold)
+            return
+        if not getattr(self, "_graph_on", False):
+            self.plan.set_graph(True)
+            self._graph_on = True
+        mine(self.plan, self.batch, self.dic, scorer, gap, threshold, self.S, self.S_raw if want_raw else None,
+             self.score, self.n_diag, self.kept, self.n_kept, self.tb, self.ws)
 
     def kept_pairs(self, b: int):
         """Kept (i, j) pairs of pair b (host copy)."""
@@ -275,7 +296,7 @@ class MineScore(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, w, gap, miner: Miner, threshold: float = 0.5, grad_S_extra=None):
-        miner.mine(w, float(gap), threshold)
+        miner.mine(w, float(gap), threshold, want_raw=True)
         ctx.miner = miner
         ctx.w = w.detach().cpu()
         ctx.wdev = w.device

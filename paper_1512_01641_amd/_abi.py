@@ -14,8 +14,8 @@ STATUS_NAMES = {0: "NWM_OK", 1: "NWM_EINVAL", 2: "NWM_ESHAPE", 3: "NWM_ENOMEM", 
 
 # exported symbols declared by include/libnwmine.h
 SYMBOLS = ["nwm_create", "nwm_destroy", "nwm_strerror", "nwm_plan_create", "nwm_plan_sizes",
-           "nwm_plan_destroy", "nwm_score_pairs", "nwm_align_batch", "nwm_align_backward",
-           "nwm_plan_set_timing", "nwm_plan_kernel_ms"]
+           "nwm_plan_destroy", "nwm_score_pairs", "nwm_align_batch", "nwm_align_backward", "nwm_mine",
+           "nwm_plan_set_graph", "nwm_plan_set_timing", "nwm_plan_kernel_ms"]
 
 P = ctypes.c_void_p
 
@@ -78,6 +78,11 @@ def load(path: str | None = None):
     lib.nwm_align_batch.restype = I
     lib.nwm_align_backward.argtypes = [P, ctypes.POINTER(Batch), P, P, P, P, P, P, P, P, Scorer, P, P, P]
     lib.nwm_align_backward.restype = I
+    lib.nwm_mine.argtypes = [P, ctypes.POINTER(Batch), ctypes.POINTER(Dict), Scorer, ctypes.c_float, ctypes.c_float,
+                             P, P, P, P, P, P, P, P, P]
+    lib.nwm_mine.restype = I
+    lib.nwm_plan_set_graph.argtypes = [P, I]
+    lib.nwm_plan_set_graph.restype = I
     lib.nwm_plan_set_timing.argtypes = [P, I]
     lib.nwm_plan_set_timing.restype = I
     lib.nwm_plan_kernel_ms.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), I]

@@ -24,6 +24,9 @@ FLAGS = [
     # no packed-FP32 instructions anywhere
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
+    # MFMA accumulators in ordinary VGPRs: no accumulator copies between the
+    # unrolled K chunks of the contraction
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 

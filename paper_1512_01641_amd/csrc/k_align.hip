@@ -15,9 +15,9 @@
 //             wave shift.  The strip's top boundary (the previous strip's last
 //             row) enters lane 0 through a 64-lane register window shifted one
 //             lane per step; the strip's own last row leaves through a second
-//             shifted window and is published every 16 steps as epoch-tagged
-//             64-bit agent-coherent stores (no counters, no cache flushes), so
-//             the next strip runs concurrently on another wave about 100 steps
+//             shifted window and is published every 16 steps as tagged 64-bit
+//             agent-coherent stores (no counters, no cache flushes), so the
+//             next strip runs concurrently on another wave about 100 steps
 //             behind (bounded re-read).
 //             S is staged through an LDS ring whose slot index equals the step
 //             index (row r of column c lands in slot c + r), so every lane reads
@@ -25,11 +25,13 @@
 //             fed one 32-step group ahead through registers.  Each lane packs
 //             its 2-bit directions, 16 steps per word, and every 64 steps the
 //             wave writes one coalesced 1 KiB block.  H never reaches HBM.
-// k_nw_reset  zeroes the queue; scores of empty pairs.
-// k_nw_walk   traceback from (n, m): one wave per pair holds one 64-step block
-//             of its strip (one 16-byte word per lane) and reads it with
-//             uniform-index readlane.  Aligned pairs are written right-aligned
-//             (ascending) into the path area.
+// k_nw_reset  clears the published-row region and the queue; scores of
+//             empty pairs.
+// k_nw_walk   traceback from (n, m): one wave per pair holds one 64-step
+//             block of its strip (one 16-byte word per lane) and reads it with
+//             uniform-index readlane, with the previous block prefetched.
+//             Aligned pairs are written right-aligned (ascending) into the
+//             path area.
 // k_keep      keeps the aligned pairs with S >= threshold, ascending.
 #include "nwm_internal.h"
 
@@ -168,11 +170,15 @@ struct FillArgs {
   const int64_t *s_off, *tb_off, *bnd_off;
 };
 
-__global__ __launch_bounds__(64) void k_nw_reset(FillArgs A, int32_t *__restrict__ ctl, float g,
-                                                 float *__restrict__ score) {
-  const int tid = blockIdx.x * 64 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_nw_reset(FillArgs A, uint4 *__restrict__ bnd16, int64_t n_bnd16,
+                                                  int32_t *__restrict__ ctl, float g, float *__restrict__ score) {
+  const int64_t tid = blockIdx.x * (int64_t)256 + threadIdx.x;
+  const int64_t nthr = (int64_t)gridDim.x * 256;
+  // published boundary values carry tag 1; clearing them every launch means a
+  // value left by an earlier launch is never taken as ready
+  for (int64_t k = tid; k < n_bnd16; k += nthr) bnd16[k] = make_uint4(0u, 0u, 0u, 0u);
   if (tid < 2) ctl[tid] = 0;   // [0] queue head, [1] error flag
-  for (int b = tid; b < A.B; b += gridDim.x * 64) {
+  for (int64_t b = tid; b < A.B; b += nthr) {
     const int n = A.n[b], m = A.m[b];
     // H[n][0] = fl32(n*g), H[0][m] = fl32(m*g), H[0][0] = +0
     if (n == 0 || m == 0) score[b] = (n + m == 0) ? 0.0f : (float)(n + m) * g;
@@ -181,8 +187,8 @@ __global__ __launch_bounds__(64) void k_nw_reset(FillArgs A, int32_t *__restrict
 
 __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restrict__ S, float g,
                                                 float *__restrict__ score, char *__restrict__ tb,
-                                                uint64_t *__restrict__ bnd, uint32_t epoch,
-                                                int32_t *__restrict__ ctl) {
+                                                uint64_t *__restrict__ bnd, int32_t *__restrict__ ctl) {
+  constexpr uint32_t epoch = 1u;   // tag of a published value (the reset clears to 0)
   __shared__ __align__(16) float ring[64 * RPITCH];
   const int lane = threadIdx.x;
   for (;;) {
@@ -191,7 +197,10 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     item = uniform(item);
     if (item >= A.n_items) break;
     const int b = uniform(A.it_pair[item]);
-    const int s = uniform(A.it_strip[item]);
+    const int s_tag = uniform(A.it_strip[item]);
+    const int s = s_tag & ~ITEM_HOT;
+    const bool hot = (s_tag & ITEM_HOT) != 0;
+    if (hot) __builtin_amdgcn_s_setprio(2);
     const int n = uniform(A.n[b]), m = uniform(A.m[b]);
     const int nstrips = (n + 63) >> 6;
     const bool last = s == nstrips - 1;
@@ -235,9 +244,9 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
 
     // Boundary window prev[tw + 1 + lane]: the first row, or the previous
     // strip's last row published by another wave.  Every published value is
-    // one 64-bit agent-coherent (sc1) store of (value, launch epoch), so a
-    // consumer knows a value is there when its tag matches: no counters, no
-    // store drains and no cache flushes.  The window of the next chunk is
+    // one 64-bit agent-coherent (sc1) store of (value, tag 1) into memory the
+    // reset kernel cleared, so a consumer knows a value is there when its tag
+    // is set: no counters, no store drains and no cache flushes.  The window of the next chunk is
     // loaded one chunk ahead and re-read (bounded) only if incomplete.
     auto load_window = [&](int tw) -> uint64_t {
       return __hip_atomic_load(in_row + tw + 1 + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -299,45 +308,138 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
       if (lane == 0 && !failed) score[b] = v;
     }
     if (failed && lane == 0) __hip_atomic_store(&ctl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (hot) __builtin_amdgcn_s_setprio(0);
   }
 }
 
+constexpr int WALK_LDS = 4096;   // path cells buffered in LDS per pair before a flush
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// A block load the compiler does not track: the walk waits for it itself
+// (below), at the next block change, and keeps the destination live until
+// then, so no step between two block changes waits on memory.
+static __device__ __forceinline__ u32x4 load_block_async(const uint4 *p) {
+  u32x4 v;
+  asm volatile("global_load_dwordx4 %0, %1, off" : "=v"(v) : "v"(p) : "memory");
+  return v;
+}
+
+// Traceback (Sec. 5.1): from (n, m) back to the first row or column,
+// following the stored directions; every DIAG step emits the aligned pair.
+// One wave per pair (longest pair first).  The walk reads one 64-step block
+// of one strip at a time (lane l: row l's four code words).  On entering a
+// block it prefetches the three blocks the walk can enter next -- the
+// previous block of the strip, or the block above or above-right in the
+// strip above -- so a block change waits only for loads issued one block
+// earlier.  Path cells collect in registers (one per lane) and LDS and reach
+// memory in coalesced stores at the end.
 __global__ __launch_bounds__(64) void k_nw_walk(PlanDev P, const char *__restrict__ tb_bits,
                                                 int2 *__restrict__ path, int32_t *__restrict__ n_diag) {
+  __shared__ int2 lbuf[WALK_LDS];
   const int b = P.dp_order[blockIdx.x];
   const int n = P.n[b], m = P.m[b];
   const int lane = threadIdx.x;
   const int cap = min(n, m);
-  int2 *pa = path + P.p_off[b];
+  int2 *pa = path + P.p_off[b];   // entry q of the walk (descending) at cap - 1 - q
+  if (n <= 0 || m <= 0) {
+    if (lane == 0) n_diag[b] = 0;
+    return;
+  }
   const uint4 *tbw = reinterpret_cast<const uint4 *>(tb_bits + P.tb_off[b]);
+  const int nS = (n + 63) >> 6;
   const int nG = (m + 63 + 63) >> 6;
-  int i = n, j = m, k = 0;
-  int cs = -1, cG = -1;
-  uint4 w = make_uint4(0u, 0u, 0u, 0u);
+  auto blk_ptr = [&](int s, int G) {
+    // out-of-range candidates read block (0, 0), which always exists
+    const bool ok = s >= 0 && s < nS && G >= 0 && G < nG;
+    return tbw + (ok ? ((int64_t)s * nG + G) * 64 : 0) + lane;
+  };
+  int i = n, j = m, k = 0, flushed = 0;
+  int cs = (n - 1) >> 6, cG = (m - 1 + ((n - 1) & 63)) >> 6;
+  u32x4 cur = load_block_async(blk_ptr(cs, cG));
+  u32x4 pA = load_block_async(blk_ptr(cs, cG - 1));
+  u32x4 pB = load_block_async(blk_ptr(cs - 1, cG));
+  u32x4 pC = load_block_async(blk_ptr(cs - 1, cG + 1));
+  asm volatile("s_waitcnt vmcnt(3)" : "+v"(cur));
+  int ckk = -1;
+  uint32_t cw = 0u;   // the current block's code word for 16 steps
+  int ri = 0, rj = 0;   // lane l: cell l of the current batch of 64
   while (i > 0 && j > 0) {
     const int s = (i - 1) >> 6;
     const int r = (i - 1) & 63;
     const int t = j - 1 + r;
     const int G = t >> 6;
     if (s != cs || G != cG) {
+      // The three prefetches (issued one block ago) must all have landed
+      // before any of their registers can be reused: the compiler does not
+      // know they are in flight, so a register it reuses (say, for the next
+      // load's address) could otherwise be overwritten by a late load.
+      asm volatile("s_waitcnt vmcnt(0)" : "+v"(pA), "+v"(pB), "+v"(pC));
+      if (s == cs && G == cG - 1) {
+        cur = pA;
+      } else if (s == cs - 1 && G == cG) {
+        cur = pB;
+      } else if (s == cs - 1 && G == cG + 1) {
+        cur = pC;
+      } else {
+        cur = load_block_async(blk_ptr(s, G));
+        asm volatile("s_waitcnt vmcnt(0)" : "+v"(cur));
+      }
       cs = s;
       cG = G;
-      w = tbw[((int64_t)s * nG + G) * 64 + lane];
+      ckk = -1;
+      pA = load_block_async(blk_ptr(cs, cG - 1));
+      pB = load_block_async(blk_ptr(cs - 1, cG));
+      pC = load_block_async(blk_ptr(cs - 1, cG + 1));
     }
     const int kk = (t >> 4) & 3;
-    const uint32_t word = kk == 0 ? w.x : kk == 1 ? w.y : kk == 2 ? w.z : w.w;
-    const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)word, r);
+    if (kk != ckk) {
+      cw = kk == 0 ? cur.x : kk == 1 ? cur.y : kk == 2 ? cur.z : cur.w;
+      ckk = kk;
+    }
+    const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)cw, r);
     const uint32_t code = (v >> (2 * (15 - (t & 15)))) & 3u;
     if (code == DIR_UP) {
       --i;
     } else if (code == DIR_LEFT) {
       --j;
     } else {
+      const int slot = k & 63;
+      if (lane == slot) {
+        ri = i - 1;
+        rj = j - 1;
+      }
       ++k;
-      if (lane == 0 && k <= cap) pa[cap - k] = make_int2(i - 1, j - 1);
+      if (slot == 63) {   // a full batch: to LDS, and LDS to memory when full
+        const int q0 = k - 64 - flushed;
+        lbuf[q0 + lane] = make_int2(ri, rj);
+        if (q0 + 64 == WALK_LDS) {
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          for (int e = lane; e < WALK_LDS; e += 64) {
+            const int q = flushed + e;
+            if (q < cap) pa[cap - 1 - q] = lbuf[e];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          flushed += WALK_LDS;
+        }
+      }
       --i;
       --j;
     }
+  }
+  // drain the prefetches before the wave ends
+  asm volatile("s_waitcnt vmcnt(0)" : "+v"(pA), "+v"(pB), "+v"(pC));
+  // the last partial batch, then everything buffered since the last flush
+  const int rem = k - flushed;
+  const int q0 = (k & ~63) - flushed;
+  if (lane < (k & 63)) lbuf[q0 + lane] = make_int2(ri, rj);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int e = lane; e < rem; e += 64) {
+    const int q = flushed + e;
+    if (q < cap) pa[cap - 1 - q] = lbuf[e];
   }
   if (lane == 0) n_diag[b] = k;
 }
@@ -384,7 +486,7 @@ hipError_t fill_set_attrs(int) {
 }
 
 hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *score, char *tb, uint64_t *bnd,
-                          uint32_t epoch, int32_t *ctl, hipStream_t st) {
+                          int64_t n_bnd, int32_t *ctl, hipStream_t st) {
   if (P.B <= 0) return hipSuccess;
   FillArgs A;
   A.n_items = P.n_items;
@@ -396,7 +498,10 @@ hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *scor
   A.s_off = P.s_off;
   A.tb_off = P.tb_off;
   A.bnd_off = P.bnd_off;
-  hipLaunchKernelGGL(k_nw_reset, dim3(64), dim3(64), 0, st, A, ctl, g, score);
+  const int64_t n16 = (n_bnd + 1) / 2;   // the region is 256-byte aligned and padded
+  const int64_t rb = (n16 + 255) / 256;
+  hipLaunchKernelGGL(k_nw_reset, dim3((unsigned)(rb < 2048 ? (rb > 0 ? rb : 1) : 2048)), dim3(256), 0, st, A,
+                     reinterpret_cast<uint4 *>(bnd), n16, ctl, g, score);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || P.n_items <= 0) return e;
   if (g_fill_grid == 0) {
@@ -404,7 +509,7 @@ hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *scor
     if (e != hipSuccess) return e;
   }
   const int grid = P.n_items < g_fill_grid ? P.n_items : g_fill_grid;
-  hipLaunchKernelGGL(k_nw_fill, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, epoch, ctl);
+  hipLaunchKernelGGL(k_nw_fill, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, ctl);
   return hipGetLastError();
 }
 

@@ -40,21 +40,19 @@ struct Op<false> {
   static constexpr int PITCH = PITCH_F32;
 };
 
-constexpr int REG_A = 2;   // A entries per lane held in registers per chunk (128)
-constexpr int REG_B = 4;   // B entries per lane (256; frequent target words crowd the first chunks)
-
 static __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
 
 // List entries of one K chunk of one tile, as loaded: lane l holds entries
-// l, 64 + l, ... of the chunk; entries at or past the chunk's count are junk
-// and are recognised from the count at scatter time (so the loaded values are
-// not touched before they are needed, and the loads stay in flight).
+// l, 64 + l, ... counted from the chunk start.  Entries at or past the
+// chunk's count belong to later chunks (or to the lists' slack) and are
+// masked out by the count when the chunk is scattered, so the loads are
+// unconditional and stay in flight until then.
 struct Chunk {
-  uint2 a[REG_A];     // {LDS element offset in the A tile, FP32 value bits}
-  uint32_t b[REG_B];  // LDS element offset in the B tile
+  uint2 a[REG_A];     // {LDS byte offset in the A tile, FP32 value bits}
+  uint32_t b[REG_B];  // LDS byte offset in the B tile
   int a0, na, b0, nb; // list start and count (uniform)
 };
 
@@ -77,15 +75,10 @@ static __device__ __forceinline__ void load_window(int &w, int &sh, const int32_
   sh = load_off(ch, first + 1 + lane, nch);
 }
 
-// Raw buffers over a tile's two lists.  Lanes past a chunk's end read with
-// an offset beyond the buffer and get 0, so every load is issued
-// unconditionally (exact wait counts, no branches).
 struct Lists {
-  __amdgpu_buffer_rsrc_t a, b;
-  const uint2 *pa;
-  const uint32_t *pb;
+  const uint2 *pa;      // the tile's A list (chunk-major)
+  const uint32_t *pb;   // the tile's B list
 };
-constexpr uint32_t OOB = 0xFFFFFFF0u;
 
 static __device__ __forceinline__ void load_chunk(Chunk &C, const Lists &L, OffWin &W,
                                                   const int32_t *__restrict__ chA, const int32_t *__restrict__ chB,
@@ -104,69 +97,68 @@ static __device__ __forceinline__ void load_chunk(Chunk &C, const Lists &L, OffW
   C.na = __builtin_amdgcn_readlane(W.sa0, k) - C.a0;
   C.b0 = __builtin_amdgcn_readlane(W.wb0, k);
   C.nb = __builtin_amdgcn_readlane(W.sb0, k) - C.b0;
+  // uniform chunk base + constant lane offset: no per-entry address math;
+  // reads past the last list stay inside its slack
+  const uint2 *pa = L.pa + C.a0;
+  const uint32_t *pb = L.pb + C.b0;
 #pragma unroll
-  for (int q = 0; q < REG_A; ++q) {
-    const int e = q * 64 + lane;
-    const uint32_t off = e < C.na ? (uint32_t)(C.a0 + e) * 8u : OOB;
-    const uint64_t v = (uint64_t)__builtin_amdgcn_raw_buffer_load_b64(L.a, off, 0, 0);
-    C.a[q] = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
-  }
+  for (int q = 0; q < REG_A; ++q) C.a[q] = pa[q * 64 + lane];
 #pragma unroll
-  for (int q = 0; q < REG_B; ++q) {
-    const int e = q * 64 + lane;
-    const uint32_t off = e < C.nb ? (uint32_t)(C.b0 + e) * 4u : OOB;
-    C.b[q] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(L.b, off, 0, 0);
-  }
+  for (int q = 0; q < REG_B; ++q) C.b[q] = pb[q * 64 + lane];
 }
 
-// Set the chunk's entries in the tiles.  Junk register entries write to a
-// padding element of row 0 (column KC), which no MFMA fragment reads; entries
-// beyond the register capacity (rare) come straight from the lists, after the
-// register entries so that their loads do not delay those.
+template <typename T>
+static __device__ __forceinline__ void lds_put(char *tile, uint32_t byte_off, T v) {
+  *reinterpret_cast<T *>(tile + byte_off) = v;
+}
+
+// Set the chunk's entries in the tiles.  Lanes past the count write to their
+// own padding word (distinct banks, never read as a fragment), and the
+// address each lane used is kept in the chunk for the clear; groups of 64 entries wholly past the count are skipped by a uniform
+// branch.  Entries beyond the register capacity (rare) come from the lists.
 template <bool BF16>
-static __device__ __forceinline__ void scatter_set(const Chunk &C, typename Op<BF16>::T *At,
-                                                   typename Op<BF16>::T *Bt, const Lists &L, int lane) {
+static __device__ __forceinline__ void scatter_set(Chunk &C, char *At, char *Bt, const Lists &L, int lane,
+                                                   uint32_t junk) {
   typedef typename Op<BF16>::T T;
 #pragma unroll
-  for (int q = 0; q < REG_A; ++q) {
-    const uint32_t x = (q * 64 + lane < C.na) ? C.a[q].x : (uint32_t)KC;
-    At[x] = T(__uint_as_float(C.a[q].y));
-  }
+  for (int q = 0; q < REG_A; ++q)
+    if (C.na > 64 * q) {
+      const uint32_t x = lane < C.na - 64 * q ? C.a[q].x : junk;
+      C.a[q].x = x;
+      lds_put<T>(At, x, T(__uint_as_float(C.a[q].y)));
+    }
 #pragma unroll
-  for (int q = 0; q < REG_B; ++q) {
-    const uint32_t x = (q * 64 + lane < C.nb) ? C.b[q] : (uint32_t)KC;
-    Bt[x] = T(1.0f);
-  }
+  for (int q = 0; q < REG_B; ++q)
+    if (C.nb > 64 * q) {
+      const uint32_t x = lane < C.nb - 64 * q ? C.b[q] : junk;
+      C.b[q] = x;
+      lds_put<T>(Bt, x, T(1.0f));
+    }
   for (int e = REG_A * 64 + lane; e < C.na; e += 64) {
     const uint2 v = L.pa[C.a0 + e];
-    At[v.x] = T(__uint_as_float(v.y));
+    lds_put<T>(At, v.x, T(__uint_as_float(v.y)));
   }
-  for (int e = REG_B * 64 + lane; e < C.nb; e += 64) Bt[L.pb[C.b0 + e]] = T(1.0f);
+  for (int e = REG_B * 64 + lane; e < C.nb; e += 64) lds_put<T>(Bt, L.pb[C.b0 + e], T(1.0f));
 }
 
-// Return the tiles to zero after a chunk: its register entries, or the whole
-// buffer when the chunk overflowed the registers (no memory loads here).
+// Return the tiles to zero after a chunk, at the addresses its scatter used,
+// or both whole tiles when the chunk overflowed the registers.
 template <bool BF16>
-static __device__ __forceinline__ void scatter_clear(const Chunk &C, typename Op<BF16>::T *At,
-                                                     typename Op<BF16>::T *Bt, int lane) {
+static __device__ __forceinline__ void scatter_clear(const Chunk &C, char *At, char *Bt, int lane) {
   typedef typename Op<BF16>::T T;
-  constexpr int TILE_ELEMS = TM * Op<BF16>::PITCH;
+  constexpr int TILE_BYTES = TM * Op<BF16>::PITCH * (int)sizeof(T);
   if (C.na > REG_A * 64 || C.nb > REG_B * 64) {
     uint4 *p = reinterpret_cast<uint4 *>(At);
-    constexpr int N16 = 2 * TILE_ELEMS * (int)sizeof(T) / 16;
+    constexpr int N16 = 2 * TILE_BYTES / 16;
     for (int e = lane; e < N16; e += 64) p[e] = make_uint4(0u, 0u, 0u, 0u);
     return;
   }
 #pragma unroll
-  for (int q = 0; q < REG_A; ++q) {
-    const uint32_t x = (q * 64 + lane < C.na) ? C.a[q].x : (uint32_t)KC;
-    At[x] = T(0.0f);
-  }
+  for (int q = 0; q < REG_A; ++q)
+    if (C.na > 64 * q) lds_put<T>(At, C.a[q].x, T(0.0f));
 #pragma unroll
-  for (int q = 0; q < REG_B; ++q) {
-    const uint32_t x = (q * 64 + lane < C.nb) ? C.b[q] : (uint32_t)KC;
-    Bt[x] = T(0.0f);
-  }
+  for (int q = 0; q < REG_B; ++q)
+    if (C.nb > 64 * q) lds_put<T>(Bt, C.b[q], T(0.0f));
 }
 
 // MFMA operand fragments of one chunk (BF16: one K step of 32; FP32: eight
@@ -183,8 +175,10 @@ struct Frags<false> {
 };
 
 template <bool BF16>
-static __device__ __forceinline__ void read_frags(Frags<BF16> &F, const typename Op<BF16>::T *At,
-                                                  const typename Op<BF16>::T *Bt, int lane) {
+static __device__ __forceinline__ void read_frags(Frags<BF16> &F, const char *Atc, const char *Btc, int lane) {
+  typedef typename Op<BF16>::T T;
+  const T *At = reinterpret_cast<const T *>(Atc);
+  const T *Bt = reinterpret_cast<const T *>(Btc);
   constexpr int P = Op<BF16>::PITCH;
   const int r16 = lane & 15, kq = lane >> 4;
   if constexpr (BF16) {
@@ -224,6 +218,14 @@ static __device__ __forceinline__ void mfma_frags(const Frags<BF16> &F, f32x4 (&
 }
 
 template <bool BF16>
+struct ScoreLds {
+  static constexpr int TILE = TM * Op<BF16>::PITCH * (int)sizeof(typename Op<BF16>::T);   // one operand tile
+  static constexpr int OPS = 4 * TILE;                                                   // [2 buffers][A, B]
+  static constexpr int RED = (int)sizeof(float) * TM * (TN + 1);                         // epilogue
+  static constexpr int BYTES = OPS > RED ? OPS : RED;
+};
+
+template <bool BF16>
 __global__ __launch_bounds__(64) void k_score(PlanDev P, const int64_t *__restrict__ src_off,
                                               const int64_t *__restrict__ tgt_off, const uint2 *__restrict__ a_list,
                                               const int32_t *__restrict__ a_choff,
@@ -231,10 +233,10 @@ __global__ __launch_bounds__(64) void k_score(PlanDev P, const int64_t *__restri
                                               const int32_t *__restrict__ b_choff, nwm_scorer sc,
                                               float *__restrict__ S, float *__restrict__ S_raw) {
   typedef typename Op<BF16>::T T;
-  constexpr int PITCH = Op<BF16>::PITCH;
-  constexpr int TILE_ELEMS = TM * PITCH;  // == TN * PITCH
-  extern __shared__ __align__(16) char smem[];
-  T *tiles = reinterpret_cast<T *>(smem);                 // [2 buffers][A, B][TILE_ELEMS]
+  constexpr int TB = ScoreLds<BF16>::TILE;
+  // static LDS: tile addresses are compile-time constants folded into the
+  // DS instruction offsets
+  __shared__ __align__(16) char smem[ScoreLds<BF16>::BYTES];
   float *red = reinterpret_cast<float *>(smem);           // epilogue: [TM][TN + 1]
 
   // XCD-aware order: consecutive tiles (same pair, shared lists) on one XCD
@@ -251,15 +253,17 @@ __global__ __launch_bounds__(64) void k_score(PlanDev P, const int64_t *__restri
   const int m = P.m[pair];
   const int nch = P.nch;
   const int lane = threadIdx.x;
+  // this lane's padding word: row lane % 16, word lane / 16 of the row's
+  // padding (columns KC ..): the 64 lanes hit 64 distinct LDS banks
+  const uint32_t junk = (uint32_t)(((lane & 15) * Op<BF16>::PITCH + KC) * (int)sizeof(T) + 4 * (lane >> 4));
 
   const int32_t *chA = a_choff + (int64_t)rt * (nch + 1);
   const int32_t *chB = b_choff + (int64_t)ct * (nch + 1);
   Lists L;
   L.pa = a_list + src_off[s_first] * (int64_t)P.max_deg;
   L.pb = b_list + tgt_off[t_first];
-  L.a = __builtin_amdgcn_make_buffer_rsrc((void *)L.pa, (short)0, 0x7FFFFFFF, 0x00020000);
-  L.b = __builtin_amdgcn_make_buffer_rsrc((void *)L.pb, (short)0, 0x7FFFFFFF, 0x00020000);
-  for (int e = lane; e < 4 * TILE_ELEMS; e += 64) tiles[e] = T(0.0f);
+  for (int e = lane; e < ScoreLds<BF16>::OPS / 16; e += 64)
+    reinterpret_cast<uint4 *>(smem)[e] = make_uint4(0u, 0u, 0u, 0u);
 
   f32x4 acc[4][4];
 #pragma unroll
@@ -274,10 +278,11 @@ __global__ __launch_bounds__(64) void k_score(PlanDev P, const int64_t *__restri
   load_window(W.wa1, W.sa1, chA, 64, nch, lane);
   load_window(W.wb1, W.sb1, chB, 64, nch, lane);
 
-  // Pipeline per chunk c: operand reads of c (buffer c&1) -> clear chunk c-1
-  // from the other buffer -> scatter chunk c+1 into it -> MFMAs of c -> load
-  // the list entries of chunk c+3 into the registers chunk c-1 used.  Four
-  // register sets rotate by unrolling (no copies of registers in flight).
+  // Software pipeline, per chunk c: MFMAs of c (fragments read during chunk
+  // c-1) -> clear chunk c-1 from the other LDS buffer -> scatter chunk c+1
+  // into it -> read the fragments of c+1 -> load the list entries of chunk
+  // c+3 into the registers chunk c-1 used.  Four entry register sets and two
+  // fragment register sets rotate by unrolling (no register copies).
   Chunk S0, S1, S2, S3;
   S3.na = S3.nb = 0;
   S3.a0 = S3.b0 = 0;
@@ -290,32 +295,34 @@ __global__ __launch_bounds__(64) void k_score(PlanDev P, const int64_t *__restri
   load_chunk(S0, L, W, chA, chB, nch, 0, lane);
   load_chunk(S1, L, W, chA, chB, nch, 1, lane);
   load_chunk(S2, L, W, chA, chB, nch, 2, lane);
-  scatter_set<BF16>(S0, tiles, tiles + TILE_ELEMS, L, lane);
+  Frags<BF16> F0, F1;
+  wave_sync();
+  scatter_set<BF16>(S0, smem, smem + TB, L, lane, junk);
+  wave_sync();
+  read_frags<BF16>(F0, smem, smem + TB, lane);
 
-  // one chunk: operand reads of c -> clear c-1 / scatter c+1 in the other
-  // buffer (LDS writes overlap the reads) -> MFMAs of c -> entries of c+3
-#define NWM_SCORE_CHUNK(c, prev, nxt)                                          \
+#define NWM_SCORE_CHUNK(c, prev, nxt, Fc, Fn)                                  \
   {                                                                            \
-    T *At_ = tiles + ((c) & 1) * 2 * TILE_ELEMS;                               \
-    T *Ao_ = tiles + (((c) + 1) & 1) * 2 * TILE_ELEMS;                         \
-    wave_sync();                                                               \
-    Frags<BF16> F_;                                                            \
-    read_frags<BF16>(F_, At_, At_ + TILE_ELEMS, lane);                         \
-    scatter_clear<BF16>(prev, Ao_, Ao_ + TILE_ELEMS, lane);                    \
-    if ((c) + 1 < nch) scatter_set<BF16>(nxt, Ao_, Ao_ + TILE_ELEMS, L, lane); \
-    mfma_frags<BF16>(F_, acc);                                                 \
+    char *Ao_ = smem + (((c) + 1) & 1) * 2 * TB;                               \
+    mfma_frags<BF16>(Fc, acc);                                                 \
+    scatter_clear<BF16>(prev, Ao_, Ao_ + TB, lane);                            \
+    if ((c) + 1 < nch) {                                                       \
+      scatter_set<BF16>(nxt, Ao_, Ao_ + TB, L, lane, junk);                    \
+      wave_sync();                                                             \
+      read_frags<BF16>(Fn, Ao_, Ao_ + TB, lane);                               \
+    }                                                                          \
     load_chunk(prev, L, W, chA, chB, nch, (c) + 3, lane); /* empty past nch */ \
   }
   int c = 0;
   for (; c + 4 <= nch; c += 4) {
-    NWM_SCORE_CHUNK(c, S3, S1)
-    NWM_SCORE_CHUNK(c + 1, S0, S2)
-    NWM_SCORE_CHUNK(c + 2, S1, S3)
-    NWM_SCORE_CHUNK(c + 3, S2, S0)
+    NWM_SCORE_CHUNK(c, S3, S1, F0, F1)
+    NWM_SCORE_CHUNK(c + 1, S0, S2, F1, F0)
+    NWM_SCORE_CHUNK(c + 2, S1, S3, F0, F1)
+    NWM_SCORE_CHUNK(c + 3, S2, S0, F1, F0)
   }
-  if (c < nch) NWM_SCORE_CHUNK(c, S3, S1)
-  if (c + 1 < nch) NWM_SCORE_CHUNK(c + 1, S0, S2)
-  if (c + 2 < nch) NWM_SCORE_CHUNK(c + 2, S1, S3)
+  if (c < nch) NWM_SCORE_CHUNK(c, S3, S1, F0, F1)
+  if (c + 1 < nch) NWM_SCORE_CHUNK(c + 1, S0, S2, F1, F0)
+  if (c + 2 < nch) NWM_SCORE_CHUNK(c + 2, S1, S3, F0, F1)
 #undef NWM_SCORE_CHUNK
   wave_sync();
 
@@ -334,58 +341,45 @@ __global__ __launch_bounds__(64) void k_score(PlanDev P, const int64_t *__restri
   const float lt = vcol ? (float)(tgt_off[t_first + col + 1] - tgt_off[t_first + col]) : 0.0f;
   float *Sp = S + P.s_off[pair];
   float *Rp = S_raw ? S_raw + P.s_off[pair] : nullptr;
+  const float LOG2E = 1.4426950408889634f;
   for (int row = 0; row < rows; ++row) {
     const float dot = red[row * RP + col];
     const float ls = (float)(src_off[s_first + row + 1] - src_off[s_first + row]);
-    const float sraw = ls > 0.0f ? dot / ls : 0.0f;
-    float rho;
-    if (ls == 0.0f && lt == 0.0f) rho = 1.0f;
-    else rho = fminf(ls, lt) / fmaxf(ls, lt);
+    // S_raw = dot / l_i (0 for an empty sentence); rho = min / max of lengths
+    const float sraw = ls > 0.0f ? dot * __builtin_amdgcn_rcpf(ls) : 0.0f;
+    const float mx = fmaxf(ls, lt);
+    const float rho = mx > 0.0f ? fminf(ls, lt) * __builtin_amdgcn_rcpf(mx) : 1.0f;
     const float z = __builtin_fmaf(sc.w0, sraw, __builtin_fmaf(sc.w1, rho, sc.b));
-    float s;
-    if (z >= 0.0f) {
-      s = 1.0f / (1.0f + expf(-z));
-    } else {
-      const float ez = expf(z);
-      s = ez / (1.0f + ez);
-    }
+    // sigmoid in the overflow-free form: e = exp(-|z|), S = 1/(1+e) or e/(1+e)
+    const float e = __builtin_amdgcn_exp2f(-fabsf(z) * LOG2E);
+    const float inv = __builtin_amdgcn_rcpf(1.0f + e);
+    const float sv = z >= 0.0f ? inv : e * inv;
     if (vcol) {
       const int64_t o = (int64_t)(row0 + row) * m + col0 + col;
-      Sp[o] = s;
+      Sp[o] = sv;
       if (Rp) Rp[o] = sraw;
     }
   }
 }
 
 size_t score_lds_bytes(int, bool bf16) {
-  const size_t esz = bf16 ? 2 : 4;
-  const size_t pitch = bf16 ? PITCH_BF16 : PITCH_F32;
-  const size_t r1 = esz * 2 * 2 * TM * pitch;
-  const size_t r2 = sizeof(float) * TM * (TN + 1);
-  return r1 > r2 ? r1 : r2;
+  return bf16 ? (size_t)ScoreLds<true>::BYTES : (size_t)ScoreLds<false>::BYTES;
 }
 
 hipError_t launch_score(const PlanDev &P, bool bf16, const int64_t *src_off, const int64_t *tgt_off,
                         const uint2 *a_list, const int32_t *a_choff, const uint32_t *b_list,
                         const int32_t *b_choff, nwm_scorer sc, float *S, float *S_raw, hipStream_t st) {
   if (P.n_gt <= 0) return hipSuccess;
-  const size_t lds = score_lds_bytes(P.nch, bf16);
   const int grid = 8 * ((P.n_gt + 7) / 8);
   if (bf16)
-    hipLaunchKernelGGL(k_score<true>, dim3(grid), dim3(64), lds, st, P, src_off, tgt_off, a_list, a_choff, b_list,
+    hipLaunchKernelGGL(k_score<true>, dim3(grid), dim3(64), 0, st, P, src_off, tgt_off, a_list, a_choff, b_list,
                        b_choff, sc, S, S_raw);
   else
-    hipLaunchKernelGGL(k_score<false>, dim3(grid), dim3(64), lds, st, P, src_off, tgt_off, a_list, a_choff, b_list,
+    hipLaunchKernelGGL(k_score<false>, dim3(grid), dim3(64), 0, st, P, src_off, tgt_off, a_list, a_choff, b_list,
                        b_choff, sc, S, S_raw);
   return hipGetLastError();
 }
 
-hipError_t score_set_attrs(int nch) {
-  hipError_t e = hipFuncSetAttribute((const void *)k_score<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)score_lds_bytes(nch, true));
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void *)k_score<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)score_lds_bytes(nch, false));
-}
+hipError_t score_set_attrs(int) { return hipSuccess; }   // static LDS only
 
 }  // namespace nwm

@@ -3,7 +3,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -16,17 +15,17 @@
 #include "nwm_internal.h"
 
 namespace nwm {
-hipError_t launch_merge_src(int64_t, const int64_t *, const int32_t *, const int32_t *, const int32_t *,
-                            const float *, int, int, uint2 *, int32_t *, hipStream_t);
+hipError_t launch_merge_src(int64_t, int64_t, const int64_t *, const int32_t *, const int32_t *, const int32_t *,
+                            const float *, int, int, uint2 *, uint2 *, int32_t *, hipStream_t);
 hipError_t launch_build_a(const PlanDev &, const int64_t *, const uint2 *, const int32_t *, uint2 *, int32_t *,
-                          int, hipStream_t);
-hipError_t launch_build_b(const PlanDev &, const int64_t *, const int32_t *, uint32_t *, int32_t *, int,
+                          int, int, hipStream_t);
+hipError_t launch_build_b(const PlanDev &, const int64_t *, const int32_t *, uint32_t *, int32_t *, int, int,
                           hipStream_t);
 hipError_t launch_score(const PlanDev &, bool, const int64_t *, const int64_t *, const uint2 *, const int32_t *,
                         const uint32_t *, const int32_t *, nwm_scorer, float *, float *, hipStream_t);
 size_t score_lds_bytes(int nch, bool bf16);
 hipError_t score_set_attrs(int nch_max);
-hipError_t launch_nw_fill(const PlanDev &, const float *, float, float *, char *, uint64_t *, uint32_t, int32_t *,
+hipError_t launch_nw_fill(const PlanDev &, const float *, float, float *, char *, uint64_t *, int64_t, int32_t *,
                           hipStream_t);
 hipError_t fill_set_attrs(int);
 hipError_t launch_nw_walk(const PlanDev &, const char *, int2 *, int32_t *, hipStream_t);
@@ -80,6 +79,7 @@ struct nwm_plan {
   int B = 0, V = 0, max_deg = 0;
   nwm_prec prec = NWM_FP32;
   int64_t n_src = 0, n_tgt = 0, src_tokens = 0, tgt_tokens = 0;
+  int64_t n_bnd = 0;   // uint64 entries of the published-row region
   int max_m = 0;
   std::vector<int32_t> n, m;
   void *dmeta = nullptr;
@@ -87,6 +87,12 @@ struct nwm_plan {
   WsLayout ws{};
   nwm_sizes sizes{};
   Timer timer;
+  // graph replay of nwm_mine: captured on cap_stream, keyed by the arguments
+  bool graph_on = false;
+  bool capturing = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<uint64_t> graph_key;
 };
 
 namespace {
@@ -100,7 +106,7 @@ struct Mark {
   size_t idx = 0;
   bool active = false;
   Mark(nwm_plan *p_, int c, hipStream_t s) : p(p_), cls(c), st(s) {
-    if (p->timer.on) {
+    if (p->timer.on && !p->capturing) {
       hipEvent_t a = p->timer.get(), b = p->timer.get();
       if (a && b && hipEventRecord(a, st) == hipSuccess) {
         idx = p->timer.used - 2;
@@ -118,13 +124,6 @@ struct Mark {
 
 bool finite(float x) { return std::isfinite(x); }
 
-// Tag of one NW launch: boundary rows published between strips carry it, so
-// values left in the workspace by earlier launches are never taken as ready.
-uint32_t next_epoch() {
-  static std::atomic<uint32_t> epoch{0x9E3779B9u};
-  uint32_t e = epoch.fetch_add(1, std::memory_order_relaxed) + 1;
-  return e == 0 ? next_epoch() : e;
-}
 
 }  // namespace
 
@@ -242,12 +241,21 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
     const int64_t links = ns > 0 ? ns - 1 : 0;
     bnd_off[b + 1] = bnd_off[b] + links * ((int64_t)p->m[b] + BND_PAD);
   }
+  // the pairs whose strip chain is within 2x of the longest one run their
+  // strips at raised wave priority: that chain bounds the DP's duration
+  // (chain ~ one hand-off of ~80 steps per strip + the m + 63 steps of the
+  // last strip)
+  auto chain = [&](int b) { return (int64_t)((p->n[b] + 63) / 64 - 1) * 80 + p->m[b] + 63; };
+  int64_t max_chain = 0;
+  for (int b = 0; b < B; ++b)
+    if (p->n[b] > 0 && p->m[b] > 0) max_chain = std::max(max_chain, chain(b));
   for (int q = 0; q < B; ++q) {
     const int b = order[q];
     if (p->n[b] <= 0 || p->m[b] <= 0) continue;
+    const int32_t hot = 2 * chain(b) >= max_chain ? ITEM_HOT : 0;
     for (int s = 0; s < (p->n[b] + 63) / 64; ++s) {
       it_pair.push_back(b);
-      it_strip.push_back(s);
+      it_strip.push_back(s | hot);
     }
   }
   // ---- device metadata: one allocation -----------------------------------------
@@ -333,12 +341,13 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   const size_t a_ent = (size_t)p->src_tokens * (size_t)max_deg;
   W.a_merged = carve(8 * a_ent);
   W.a_cnt = carve(4 * (size_t)p->n_src);
-  W.a_list = carve(8 * a_ent);
+  W.a_list = carve(8 * (a_ent + LIST_SLACK_A));
   W.a_choff = carve(4 * (size_t)D.n_rt * (size_t)(nch + 1));
-  W.b_list = carve(4 * (size_t)p->tgt_tokens);
+  W.b_list = carve(4 * ((size_t)p->tgt_tokens + LIST_SLACK_B));
   W.b_choff = carve(4 * (size_t)D.n_ct * (size_t)(nch + 1));
   W.bwd = carve(16 * ((size_t)B + (size_t)D.n_rt));
-  W.bnd = carve(8 * (size_t)bnd_off[B]);
+  W.bnd = carve(8 * (size_t)bnd_off[B] + 16);   // + 16: cleared in 16-byte units
+  p->n_bnd = bnd_off[B] + 2;
   W.ctl = carve(8);
   W.total = o;
   p->sizes.S_elems = (size_t)s_off[B];
@@ -363,10 +372,10 @@ nwm_status nwm_plan_sizes(const nwm_plan *plan, nwm_sizes *sizes) {
 
 void nwm_plan_destroy(nwm_plan *plan) {
   if (!plan) return;
-  if (plan->dmeta) {
-    (void)hipSetDevice(plan->ctx->device);
-    (void)hipFree(plan->dmeta);
-  }
+  (void)hipSetDevice(plan->ctx->device);
+  if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+  if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+  if (plan->dmeta) (void)hipFree(plan->dmeta);
   delete plan;
 }
 
@@ -397,13 +406,16 @@ nwm_status nwm_score_pairs(nwm_plan *p, const nwm_batch *batch, const nwm_dict *
   uint32_t *b_list = (uint32_t *)(w + p->ws.b_list);
   int32_t *b_choff = (int32_t *)(w + p->ws.b_choff);
   const bool bf16 = p->prec == NWM_BF16;
+  // list entries are LDS byte offsets inside the operand tiles
   const int pitch = bf16 ? PITCH_BF16 : PITCH_F32;
+  const int esize = bf16 ? 2 : 4;
   {
     Mark mk(p, K_EXPAND, st);
-    hipError_t e = launch_merge_src(p->n_src, batch->src_off, batch->src_tok, dict->row_off, dict->col, dict->val,
-                                    p->V, p->max_deg, merged, cnt, st);
-    if (e == hipSuccess) e = launch_build_a(p->dev, batch->src_off, merged, cnt, a_list, a_choff, pitch, st);
-    if (e == hipSuccess) e = launch_build_b(p->dev, batch->tgt_off, batch->tgt_tok, b_list, b_choff, pitch, st);
+    // the per-token dictionary rows use a_list's memory before the lists do
+    hipError_t e = launch_merge_src(p->n_src, p->src_tokens, batch->src_off, batch->src_tok, dict->row_off,
+                                    dict->col, dict->val, p->V, p->max_deg, a_list, merged, cnt, st);
+    if (e == hipSuccess) e = launch_build_a(p->dev, batch->src_off, merged, cnt, a_list, a_choff, pitch, esize, st);
+    if (e == hipSuccess) e = launch_build_b(p->dev, batch->tgt_off, batch->tgt_tok, b_list, b_choff, pitch, esize, st);
     mk.done();
     if (e != hipSuccess) return NWM_EDEVICE;
   }
@@ -430,7 +442,7 @@ nwm_status nwm_align_batch(nwm_plan *p, const float *S, float gap, float thresho
   hipError_t e;
   {
     Mark mk(p, K_FILL, st);
-    e = launch_nw_fill(p->dev, S, gap, score, tbc, (uint64_t *)(w + p->ws.bnd), next_epoch(),
+    e = launch_nw_fill(p->dev, S, gap, score, tbc, (uint64_t *)(w + p->ws.bnd), p->n_bnd,
                        (int32_t *)(w + p->ws.ctl), st);
     mk.done();
   }
@@ -467,6 +479,71 @@ nwm_status nwm_align_backward(nwm_plan *p, const nwm_batch *batch, const void *t
                                  grad_S, grad_gap, S, S_raw, grad_wb, part_path, part_dense, st);
   mk.done();
   return dev_err(e);
+}
+
+nwm_status nwm_plan_set_graph(nwm_plan *p, int on) {
+  if (!p) return NWM_EINVAL;
+  p->graph_on = on != 0;
+  if (!p->graph_on && p->graph_exec) {
+    (void)hipGraphExecDestroy(p->graph_exec);
+    p->graph_exec = nullptr;
+    p->graph_key.clear();
+  }
+  return NWM_OK;
+}
+
+nwm_status nwm_mine(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, nwm_scorer sc, float gap,
+                    float threshold, float *S, float *S_raw, float *score, int32_t *n_diag, int32_t *kept,
+                    int32_t *n_kept, void *tb, void *ws, void *stream) {
+  if (!p) return NWM_EINVAL;
+  if (!p->graph_on) {
+    nwm_status s = nwm_score_pairs(p, batch, dict, sc, S, S_raw, ws, stream);
+    if (s != NWM_OK) return s;
+    return nwm_align_batch(p, S, gap, threshold, score, n_diag, kept, n_kept, tb, ws, stream);
+  }
+  if (!batch || !dict) return NWM_EINVAL;
+  uint32_t w0b, w1b, bb, gb, tb_;
+  std::memcpy(&w0b, &sc.w0, 4);
+  std::memcpy(&w1b, &sc.w1, 4);
+  std::memcpy(&bb, &sc.b, 4);
+  std::memcpy(&gb, &gap, 4);
+  std::memcpy(&tb_, &threshold, 4);
+  std::vector<uint64_t> key = {
+      (uint64_t)(uintptr_t)batch->src_off, (uint64_t)(uintptr_t)batch->src_tok, (uint64_t)(uintptr_t)batch->tgt_off,
+      (uint64_t)(uintptr_t)batch->tgt_tok, (uint64_t)(uintptr_t)dict->row_off,  (uint64_t)(uintptr_t)dict->col,
+      (uint64_t)(uintptr_t)dict->val,      (uint64_t)dict->max_deg,             ((uint64_t)w0b << 32) | w1b,
+      ((uint64_t)bb << 32) | gb,           (uint64_t)tb_,                       (uint64_t)(uintptr_t)S,
+      (uint64_t)(uintptr_t)S_raw,          (uint64_t)(uintptr_t)score,          (uint64_t)(uintptr_t)n_diag,
+      (uint64_t)(uintptr_t)kept,           (uint64_t)(uintptr_t)n_kept,         (uint64_t)(uintptr_t)tb,
+      (uint64_t)(uintptr_t)ws};
+  if (!p->graph_exec || key != p->graph_key) {
+    if (p->graph_exec) {
+      (void)hipGraphExecDestroy(p->graph_exec);
+      p->graph_exec = nullptr;
+    }
+    if (!p->cap_stream && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+      return NWM_EDEVICE;
+    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return NWM_EDEVICE;
+    p->capturing = true;
+    nwm_status s = nwm_score_pairs(p, batch, dict, sc, S, S_raw, ws, p->cap_stream);
+    if (s == NWM_OK) s = nwm_align_batch(p, S, gap, threshold, score, n_diag, kept, n_kept, tb, ws, p->cap_stream);
+    p->capturing = false;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (s != NWM_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess || !g) return NWM_EDEVICE;
+    e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      p->graph_exec = nullptr;
+      return NWM_EDEVICE;
+    }
+    p->graph_key = key;
+  }
+  return dev_err(hipGraphLaunch(p->graph_exec, (hipStream_t)stream));
 }
 
 nwm_status nwm_plan_set_timing(nwm_plan *p, int on) {

@@ -19,6 +19,14 @@ constexpr int GEMM_THREADS = 64 * GEMM_WAVES;
 // LDS row pitch (elements) of the dense operand tiles.
 constexpr int PITCH_BF16 = KC + 8;   // 80 B rows: conflict-free ds_read_b128
 constexpr int PITCH_F32 = KC + 4;    // 144 B rows
+
+// List entries of one K chunk held in registers per lane by the contraction
+// (A: 128 entries, B: 256).  Every chunk load reads that many entries from
+// the chunk start, so the lists carry that much slack at their end.
+constexpr int REG_A = 2;
+constexpr int REG_B = 4;
+constexpr int LIST_SLACK_A = 64 * REG_A;
+constexpr int LIST_SLACK_B = 64 * REG_B;
 // LDS staging capacity of tile lists (entries) per K segment.
 constexpr int CAP_A = 2048;
 constexpr int CAP_B = 2048;
@@ -30,7 +38,8 @@ constexpr int MAX_DEG = 64;
 
 // ---- NW wavefront -----------------------------------------------------------
 constexpr int BND_PAD = 192;          // slack floats after each published boundary row
-constexpr int MAX_M = 1 << 22;        // per-pair target sentences (64-row strip of S < 1 GiB)
+constexpr int MAX_M = 1 << 22;
+constexpr int32_t ITEM_HOT = 1 << 30;   // DP item flag: strip of a critical-chain pair        // per-pair target sentences (64-row strip of S < 1 GiB)
 
 // Direction codes of the traceback.
 constexpr int DIR_DIAG = 0, DIR_UP = 1, DIR_LEFT = 2;

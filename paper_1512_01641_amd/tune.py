@@ -54,7 +54,7 @@ class Tuner:
     def loss_and_grad(self):
         mn = self.mn
         B = mn.batch.B
-        mn.mine(self.w.astype(np.float32), self.gap, self.threshold)
+        mn.mine(self.w.astype(np.float32), self.gap, self.threshold, want_raw=True)
         dev = mn.ctx.device
         gwb = torch.zeros(3, dtype=torch.float64, device=dev)
         gg = torch.zeros(1, dtype=torch.float64, device=dev)
