@@ -77,6 +77,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
     ap.add_argument("--prec", choices=("both", "bf16", "f32"), default="both")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch parameters")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="run a plain device copy of MIB MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -119,9 +120,14 @@ def main():
     results = {}
     eager = {}
     kernel = {}
+    tuned = {}
     for prec_name, prec in precs:
         _log("batched %s" % prec_name)
         mn = nw.Miner(ctx, db, dd, prec)
+        if not args.no_autotune:
+            from paper_1512_01641_amd import autotune
+            tuned[prec_name] = autotune.autotune(mn, w, gap, thr, reps=3)["params"]
+            _log("autotuned %s: %s" % (prec_name, tuned[prec_name]))
         step = lambda mn=mn: mn.mine(w, gap, thr)
         for _ in range(args.warmup):
             step()
@@ -193,6 +199,7 @@ def main():
                    "pairs": B, "cells": cells, "V": V},
         "gcups": round(gcups, 3),
         "launch": "eager" if args.no_graph else "hipGraph replay of the whole path per step",
+        "launch_params": tuned if tuned else "defaults",
         "ms_per_step_eager": {p: round(v, 4) for p, v in eager.items()},
         "pairs_per_s_batched_fp32": round(B / (results["f32"] / 1000.0), 2) if "f32" in results else None,
         "pairs_per_s_plain_fp32": round(B / (plain / 1000.0), 2) if plain else None,

@@ -195,6 +195,30 @@ nwm_status nwm_mine(nwm_plan *plan, const nwm_batch *batch, const nwm_dict *dict
                     int32_t *n_kept, void *tb, void *ws, void *stream);
 nwm_status nwm_plan_set_graph(nwm_plan *plan, int on);
 
+/* --- launch parameters (for the autotuner) ------------------------------------ */
+
+/* Launch shapes that do not change any result, only the time:
+ *   NWM_PARAM_FILL_WAVES_PER_CU   persistent DP waves per compute unit
+ *                                 (0 = as many as fit; default 0)
+ *   NWM_PARAM_MERGE_WAVES_PER_CU  dictionary-merge waves per compute unit
+ *                                 (0 = as many as the LDS allows; default 0)
+ *   NWM_PARAM_SCORE_XCD_MAP       1 = contraction tiles of one pair on one XCD
+ *                                 (shared L2), 0 = dispatch order; default 1
+ *   NWM_PARAM_DP_HOT_PERCENT      DP strips of pairs whose dependency chain is
+ *                                 at least this percent of the longest one run
+ *                                 at raised wave priority (0 = never; default 50)
+ * Out-of-range values give NWM_EINVAL.  Setting DP_HOT_PERCENT uploads the
+ * plan's work list (synchronous).  A graph captured by nwm_mine is captured
+ * again after any change. */
+typedef enum {
+  NWM_PARAM_FILL_WAVES_PER_CU = 0,
+  NWM_PARAM_MERGE_WAVES_PER_CU = 1,
+  NWM_PARAM_SCORE_XCD_MAP = 2,
+  NWM_PARAM_DP_HOT_PERCENT = 3
+} nwm_param;
+nwm_status nwm_plan_set_param(nwm_plan *plan, nwm_param param, int32_t value);
+nwm_status nwm_plan_get_param(const nwm_plan *plan, nwm_param param, int32_t *value);
+
 /* --- measurement ------------------------------------------------------------ */
 
 /* Record HIP events around every kernel the plan launches (0 = off).  While

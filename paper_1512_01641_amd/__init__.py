@@ -134,6 +134,16 @@ class Plan:
     def workspace(self):
         return torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=self.ctx.device)
 
+    def set_param(self, name: str, value: int):
+        """A launch parameter (see nwm_param): fill_waves_per_cu,
+        merge_waves_per_cu, score_xcd_map, dp_hot_percent."""
+        _abi.check(self.lib.nwm_plan_set_param(self.h, _abi.PARAMS[name], int(value)), "nwm_plan_set_param")
+
+    def get_param(self, name: str) -> int:
+        v = ctypes.c_int32(0)
+        _abi.check(self.lib.nwm_plan_get_param(self.h, _abi.PARAMS[name], ctypes.byref(v)), "nwm_plan_get_param")
+        return int(v.value)
+
     def set_graph(self, on: bool):
         _abi.check(self.lib.nwm_plan_set_graph(self.h, int(bool(on))), "nwm_plan_set_graph")
 

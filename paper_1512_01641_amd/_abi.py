@@ -15,7 +15,10 @@ STATUS_NAMES = {0: "NWM_OK", 1: "NWM_EINVAL", 2: "NWM_ESHAPE", 3: "NWM_ENOMEM", 
 # exported symbols declared by include/libnwmine.h
 SYMBOLS = ["nwm_create", "nwm_destroy", "nwm_strerror", "nwm_plan_create", "nwm_plan_sizes",
            "nwm_plan_destroy", "nwm_score_pairs", "nwm_align_batch", "nwm_align_backward", "nwm_mine",
-           "nwm_plan_set_graph", "nwm_plan_set_timing", "nwm_plan_kernel_ms"]
+           "nwm_plan_set_graph", "nwm_plan_set_param", "nwm_plan_get_param", "nwm_plan_set_timing",
+           "nwm_plan_kernel_ms"]
+
+PARAMS = {"fill_waves_per_cu": 0, "merge_waves_per_cu": 1, "score_xcd_map": 2, "dp_hot_percent": 3}
 
 P = ctypes.c_void_p
 
@@ -83,6 +86,10 @@ def load(path: str | None = None):
     lib.nwm_mine.restype = I
     lib.nwm_plan_set_graph.argtypes = [P, I]
     lib.nwm_plan_set_graph.restype = I
+    lib.nwm_plan_set_param.argtypes = [P, I, ctypes.c_int32]
+    lib.nwm_plan_set_param.restype = I
+    lib.nwm_plan_get_param.argtypes = [P, I, ctypes.POINTER(ctypes.c_int32)]
+    lib.nwm_plan_get_param.restype = I
     lib.nwm_plan_set_timing.argtypes = [P, I]
     lib.nwm_plan_set_timing.restype = I
     lib.nwm_plan_kernel_ms.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), I]

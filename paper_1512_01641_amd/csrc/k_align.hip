@@ -471,22 +471,23 @@ __global__ __launch_bounds__(64) void k_keep(PlanDev P, const float *__restrict_
   if (lane == 0) n_kept[b] = nk;
 }
 
-static int g_fill_grid = 0;
+static int g_fill_cus = 0, g_fill_per = 0;   // compute units, resident fill waves per unit
 
 hipError_t fill_set_attrs(int) {
-  if (g_fill_grid == 0) {
+  if (g_fill_cus == 0) {
     int dev = 0, cus = 0, per = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_nw_fill, 64, 0);
     if (e != hipSuccess) return e;
-    g_fill_grid = cus * (per > 0 ? per : 1);
+    g_fill_per = per > 0 ? per : 1;
+    g_fill_cus = cus > 0 ? cus : 1;
   }
   return hipSuccess;
 }
 
 hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *score, char *tb, uint64_t *bnd,
-                          int64_t n_bnd, int32_t *ctl, hipStream_t st) {
+                          int64_t n_bnd, int32_t *ctl, int waves_per_cu, hipStream_t st) {
   if (P.B <= 0) return hipSuccess;
   FillArgs A;
   A.n_items = P.n_items;
@@ -504,11 +505,15 @@ hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *scor
                      reinterpret_cast<uint4 *>(bnd), n16, ctl, g, score);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || P.n_items <= 0) return e;
-  if (g_fill_grid == 0) {
+  if (g_fill_cus == 0) {
     e = fill_set_attrs(0);
     if (e != hipSuccess) return e;
   }
-  const int grid = P.n_items < g_fill_grid ? P.n_items : g_fill_grid;
+  // every wave of the grid is resident at once (the hand-off between strips
+  // waits on other waves), so the grid never exceeds the occupancy
+  const int per = (waves_per_cu > 0 && waves_per_cu < g_fill_per) ? waves_per_cu : g_fill_per;
+  const int full = g_fill_cus * per;
+  const int grid = P.n_items < full ? P.n_items : full;
   hipLaunchKernelGGL(k_nw_fill, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, ctl);
   return hipGetLastError();
 }

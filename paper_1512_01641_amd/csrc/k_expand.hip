@@ -2,13 +2,13 @@
 // (Sec. 4: dictionary with translation probabilities; the features are read as
 // the dictionary coverage of a target sentence by a source sentence).
 //
-// 1. k_expand_tok  one thread per source token: its dictionary row.
-//    k_merge_src   one wave per source sentence: T'[i][u] = sum over the
+// 1. k_merge_src   one wave per source sentence: T'[i][u] = sum over the
 //                  sentence's token occurrences t of D[t][u].  Duplicated
-//                  targets u are merged through an LDS owner table; the sums
-//                  are FP64 atomics of FP32 terms, exact (and hence independent
-//                  of the order of the atomics) while the terms of one sum
-//                  span fewer than 2^29 in magnitude, then rounded to FP32 once.
+//                  targets u are merged through a small LDS hash table; the
+//                  sums are FP64 atomics of FP32 terms, exact (and hence
+//                  independent of the order of the atomics) while the terms of
+//                  one sum span fewer than 2^29 in magnitude, then rounded to
+//                  FP32 once.
 // 2. k_build_a     one workgroup per row tile (TM source sentences of a pair):
 //                  the tile's merged entries regrouped chunk-major (K chunks of
 //                  KC words), each entry pre-encoded as its LDS byte offset in
@@ -27,96 +27,124 @@ static __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// One thread per source token occurrence: its dictionary row, written at a
-// fixed stride of max_deg entries {target word, weight bits} (empty slots get
-// word 0xFFFFFFFF).  Fully parallel, so the token -> row -> entries chain of
-// dependent loads is hidden by occupancy rather than paid per sentence.
-__global__ __launch_bounds__(256) void k_expand_tok(int64_t n_tok, const int32_t *__restrict__ src_tok,
-                                                    const int32_t *__restrict__ d_row_off,
-                                                    const int32_t *__restrict__ d_col,
-                                                    const float *__restrict__ d_val, int V, int max_deg,
-                                                    uint2 *__restrict__ raw) {
-  for (int64_t p = blockIdx.x * (int64_t)256 + threadIdx.x; p < n_tok; p += (int64_t)gridDim.x * 256) {
-    const int tok = src_tok[p];
-    int e0 = 0, deg = 0;
-    if ((uint32_t)tok < (uint32_t)V) {
-      e0 = d_row_off[tok];
-      deg = min(d_row_off[tok + 1] - e0, max_deg);
-    }
-    uint2 *out = raw + p * max_deg;
-    for (int q = 0; q < max_deg; ++q) {
-      uint2 e = make_uint2(0xFFFFFFFFu, 0u);
-      if (q < deg) {
-        const uint32_t u = (uint32_t)d_col[e0 + q];
-        if (u < (uint32_t)V) e = make_uint2(u, __float_as_uint(d_val[e0 + q]));
-      }
-      out[q] = e;
-    }
-  }
-}
+constexpr uint32_t HEMPTY = 0xFFFFFFFFu;
 
-// One wave per source sentence (grid-stride): merge the sentence's
-// contiguous block of dictionary entries by target word.  The first 128
-// entries of the next sentence are loaded while the current one merges.
+// One wave per source sentence (grid-stride): the sentence's tokens and
+// their dictionary rows (loaded one sentence ahead), merged by target word
+// through an LDS hash table of 2^hbits slots (open addressing, linear
+// probing, at most half full by the plan's bound on tokens x degree).  The
+// sums are FP64 LDS atomics of FP32 terms -- exact, so independent of the
+// order of the atomics -- rounded to FP32 once on the way out.  A sentence
+// longer than the caller's max_sent_tokens (a contract violation) cannot
+// hang or write out of bounds: a full table or slot list drops entries.
 __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t *__restrict__ src_off,
-                                                  const uint2 *__restrict__ raw, int V, int max_deg,
-                                                  uint2 *__restrict__ merged, int32_t *__restrict__ cnt) {
+                                                  const int32_t *__restrict__ src_tok,
+                                                  const int32_t *__restrict__ d_row_off,
+                                                  const int32_t *__restrict__ d_col, const float *__restrict__ d_val,
+                                                  int V, int max_deg, int hbits, uint2 *__restrict__ merged,
+                                                  int32_t *__restrict__ cnt) {
   extern __shared__ __align__(16) char smem[];
-  double *acc = reinterpret_cast<double *>(smem);                       // [MERGE_SLOTS]
-  uint32_t *su = reinterpret_cast<uint32_t *>(acc + MERGE_SLOTS);       // [MERGE_SLOTS]
-  volatile uint16_t *owner = reinterpret_cast<uint16_t *>(su + MERGE_SLOTS);  // [V]
+  const int HS = 1 << hbits;
+  const int CAPU = HS >> 1;                                  // distinct words per sentence
+  double *acc = reinterpret_cast<double *>(smem);            // [HS]
+  uint32_t *key = reinterpret_cast<uint32_t *>(acc + HS);    // [HS]
+  int *slots = reinterpret_cast<int *>(key + HS);            // [CAPU] claimed slots, claim order
   const int lane = threadIdx.x;
-  const uint16_t EMPTY = 0xFFFF;
-  for (int u = lane; u < V; u += 64) owner[u] = EMPTY;
-  for (int s = lane; s < MERGE_SLOTS; s += 64) acc[s] = 0.0;
-  __syncthreads();
+  for (int h = lane; h < HS; h += 64) {
+    key[h] = HEMPTY;
+    acc[h] = 0.0;
+  }
+  wave_sync();
 
-  auto fetch = [&](int64_t sent, uint2 &e0, uint2 &e1, int &ne, int64_t &base) {
-    const int64_t t0 = src_off[sent], t1 = src_off[sent + 1];
-    base = t0 * (int64_t)max_deg;
-    ne = (int)((t1 - t0) * max_deg);
-    e0 = lane < ne ? raw[base + lane] : make_uint2(0xFFFFFFFFu, 0u);
-    e1 = 64 + lane < ne ? raw[base + 64 + lane] : make_uint2(0xFFFFFFFFu, 0u);
-  };
-
-  int64_t sent = blockIdx.x;
-  uint2 n0 = make_uint2(0xFFFFFFFFu, 0u), n1 = n0;
-  int nne = 0;
-  int64_t nbase = 0;
-  if (sent < n_sent) fetch(sent, n0, n1, nne, nbase);
-  for (; sent < n_sent; sent += gridDim.x) {
-    const uint2 c0 = n0, c1 = n1;
-    const int ne = nne;
-    const int64_t base = nbase;
-    if (sent + gridDim.x < n_sent) fetch(sent + gridDim.x, n0, n1, nne, nbase);
-    int nuniq = 0;
-    for (int r0 = 0; r0 < ne; r0 += 64) {
-      const uint2 e = r0 == 0 ? c0 : r0 == 64 ? c1 : (r0 + lane < ne ? raw[base + r0 + lane] : make_uint2(0xFFFFFFFFu, 0u));
-      uint32_t u = e.x;
-      bool act = u < (uint32_t)V;
-      const float v = __uint_as_float(e.y);
-      uint16_t o = act ? owner[u] : EMPTY;
-      const bool claim = act && o == EMPTY;
-      const uint16_t tag = (uint16_t)(0x8000 | lane);
-      if (claim) owner[u] = tag;
-      wave_sync();
-      const bool winner = claim && owner[u] == tag;
-      const uint64_t wm = __ballot(winner);
-      const int slot_w = nuniq + __popcll(wm & ((1ull << lane) - 1ull));
-      const bool ok = winner && slot_w < MERGE_SLOTS;
-      if (winner) owner[u] = ok ? (uint16_t)slot_w : (uint16_t)0x7FFF;
-      if (ok) su[slot_w] = u;
-      wave_sync();
-      const uint16_t slot = act ? owner[u] : EMPTY;
-      if (act && slot < MERGE_SLOTS) atomicAdd(&acc[slot], (double)v);
-      nuniq += __popcll(wm);
-      if (nuniq > MERGE_SLOTS) nuniq = MERGE_SLOTS;
-      wave_sync();
+  // sentence `sent`: its token range, and lane l's token's dictionary row
+  // (tokens c0 + l)
+  auto fetch_rows = [&](int64_t t0, int len, int c0, int &e0, int &deg) {
+    e0 = 0;
+    deg = 0;
+    if (c0 + lane < len) {
+      const int tok = src_tok[t0 + c0 + lane];
+      if ((unsigned)tok < (unsigned)V) {
+        e0 = d_row_off[tok];
+        deg = min(d_row_off[tok + 1] - e0, max_deg);
+      }
     }
-    for (int s = lane; s < nuniq; s += 64) {
-      merged[base + s] = make_uint2(su[s], __float_as_uint((float)acc[s]));
-      acc[s] = 0.0;
-      owner[su[s]] = EMPTY;
+  };
+  int64_t sent = blockIdx.x;
+  int64_t nt0 = 0;
+  int nlen = 0, ne0 = 0, ndeg = 0;
+  if (sent < n_sent) {
+    nt0 = src_off[sent];
+    nlen = (int)(src_off[sent + 1] - nt0);
+    fetch_rows(nt0, nlen, 0, ne0, ndeg);
+  }
+  for (; sent < n_sent; sent += gridDim.x) {
+    const int64_t t0 = nt0;
+    const int len = nlen;
+    int e0 = ne0, deg = ndeg;
+    const int64_t nxt = sent + gridDim.x;
+    if (nxt < n_sent) {
+      nt0 = src_off[nxt];
+      nlen = (int)(src_off[nxt + 1] - nt0);
+      fetch_rows(nt0, nlen, 0, ne0, ndeg);
+    }
+    int nuniq = 0;
+    for (int c0 = 0; c0 < len; c0 += 64) {
+      if (c0 > 0) fetch_rows(t0, len, c0, e0, deg);   // tokens past the first 64
+      for (int q0 = 0; q0 < max_deg; q0 += 4) {
+        if (__ballot(q0 < deg) == 0) break;
+        // entries q0 .. q0+3 of this lane's row, loaded together
+        uint32_t u[4];
+        float v[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          u[d] = HEMPTY;
+          v[d] = 0.0f;
+          if (q0 + d < deg) {
+            u[d] = (uint32_t)d_col[e0 + q0 + d];
+            v[d] = d_val[e0 + q0 + d];
+          }
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          const bool act = u[d] < (uint32_t)V;
+          uint32_t h = act ? (u[d] * 0x9E3779B1u) >> (32 - hbits) : 0u;
+          bool pending = act, claimed = false, placed = false;
+          int probes = 0;
+          while (__ballot(pending) != 0) {
+            if (pending) {
+              const uint32_t old = atomicCAS(&key[h], HEMPTY, u[d]);
+              if (old == HEMPTY || old == u[d]) {
+                claimed = old == HEMPTY;
+                placed = true;
+                pending = false;
+              } else if (++probes >= HS) {
+                pending = false;   // table full: drop
+              } else {
+                h = (h + 1) & (uint32_t)(HS - 1);
+              }
+            }
+          }
+          if (placed) atomicAdd(&acc[h], (double)v[d]);
+          const uint64_t cm = __ballot(claimed);
+          const int rank = nuniq + __popcll(cm & ((1ull << lane) - 1ull));
+          if (claimed && rank < CAPU) slots[rank] = (int)h;
+          nuniq = min(nuniq + __popcll(cm), CAPU);
+        }
+      }
+    }
+    wave_sync();
+    const int64_t base = t0 * (int64_t)max_deg;
+    for (int e = lane; e < nuniq; e += 64) {
+      const int h = slots[e];
+      merged[base + e] = make_uint2(key[h], __float_as_uint((float)acc[h]));
+    }
+    wave_sync();
+    // clear every slot this sentence touched (claimed ones are in slots[];
+    // a dropped entry never claimed one)
+    for (int e = lane; e < nuniq; e += 64) {
+      const int h = slots[e];
+      key[h] = HEMPTY;
+      acc[h] = 0.0;
     }
     if (lane == 0) cnt[sent] = nuniq;
     wave_sync();
@@ -318,20 +346,39 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
 }
 
 // ---- launchers ----------------------------------------------------------------
-hipError_t launch_merge_src(int64_t n_sent, int64_t n_tok, const int64_t *src_off, const int32_t *src_tok,
+int merge_hbits(int max_entries) {
+  int hb = 7;
+  while ((1 << hb) < 2 * max_entries) ++hb;
+  return hb;
+}
+
+size_t merge_lds_bytes(int hbits) {
+  const size_t hs = (size_t)1 << hbits;
+  return hs * (sizeof(double) + sizeof(uint32_t)) + (hs / 2) * sizeof(int);
+}
+
+hipError_t launch_merge_src(int64_t n_sent, const int64_t *src_off, const int32_t *src_tok,
                             const int32_t *d_row_off, const int32_t *d_col, const float *d_val, int V,
-                            int max_deg, uint2 *raw, uint2 *merged, int32_t *cnt, hipStream_t st) {
+                            int max_deg, int max_entries, uint2 *merged, int32_t *cnt, int waves_per_cu,
+                            hipStream_t st) {
   if (n_sent <= 0) return hipSuccess;
-  if (n_tok > 0) {
-    const int64_t blocks = (n_tok + 255) / 256;
-    hipLaunchKernelGGL(k_expand_tok, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st, n_tok,
-                       src_tok, d_row_off, d_col, d_val, V, max_deg, raw);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  const int hb = merge_hbits(max_entries);
+  const size_t lds = merge_lds_bytes(hb);
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
   }
-  const size_t lds = MERGE_SLOTS * (sizeof(double) + sizeof(uint32_t)) + sizeof(uint16_t) * (size_t)V;
-  const int grid = (int)(n_sent < 16384 ? n_sent : 16384);
-  hipLaunchKernelGGL(k_merge_src, dim3(grid), dim3(64), lds, st, n_sent, src_off, raw, V, max_deg, merged, cnt);
+  // resident waves: LDS-bound (about 160 KiB per CU), at most 32 per CU
+  int per = (int)((160u * 1024u) / lds);
+  per = per < 1 ? 1 : (per > 32 ? 32 : per);
+  if (waves_per_cu > 0 && waves_per_cu < per) per = waves_per_cu;
+  const int64_t want = (int64_t)cus * per;
+  const int grid = (int)(n_sent < want ? n_sent : want);
+  hipLaunchKernelGGL(k_merge_src, dim3(grid), dim3(64), lds, st, n_sent, src_off, src_tok, d_row_off, d_col, d_val,
+                     V, max_deg, hb, merged, cnt);
   return hipGetLastError();
 }
 
@@ -353,9 +400,9 @@ hipError_t launch_build_b(const PlanDev &P, const int64_t *tgt_off, const int32_
   return hipGetLastError();
 }
 
-hipError_t merge_set_attrs(int V) {
-  const size_t lds = MERGE_SLOTS * (sizeof(double) + sizeof(uint32_t)) + sizeof(uint16_t) * (size_t)V;
-  return hipFuncSetAttribute((const void *)k_merge_src, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+hipError_t merge_set_attrs(int max_entries) {
+  return hipFuncSetAttribute((const void *)k_merge_src, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)merge_lds_bytes(merge_hbits(max_entries)));
 }
 
 }  // namespace nwm

@@ -231,7 +231,7 @@ __global__ __launch_bounds__(64) void k_score(PlanDev P, const int64_t *__restri
                                               const int32_t *__restrict__ a_choff,
                                               const uint32_t *__restrict__ b_list,
                                               const int32_t *__restrict__ b_choff, nwm_scorer sc,
-                                              float *__restrict__ S, float *__restrict__ S_raw) {
+                                              float *__restrict__ S, float *__restrict__ S_raw, int xcd_map) {
   typedef typename Op<BF16>::T T;
   constexpr int TB = ScoreLds<BF16>::TILE;
   // static LDS: tile addresses are compile-time constants folded into the
@@ -239,10 +239,11 @@ __global__ __launch_bounds__(64) void k_score(PlanDev P, const int64_t *__restri
   __shared__ __align__(16) char smem[ScoreLds<BF16>::BYTES];
   float *red = reinterpret_cast<float *>(smem);           // epilogue: [TM][TN + 1]
 
-  // XCD-aware order: consecutive tiles (same pair, shared lists) on one XCD
+  // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin, so
+  // consecutive tiles (same pair, shared lists) go to one XCD and its L2
   const int G = P.n_gt;
   const int per = (G + 7) >> 3;
-  const int gt = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  const int gt = xcd_map ? (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
   if (gt >= G) return;
   const int rt = P.gt_rt[gt], ct = P.gt_ct[gt];
   const int pair = P.rt_pair[rt];
@@ -368,15 +369,16 @@ size_t score_lds_bytes(int, bool bf16) {
 
 hipError_t launch_score(const PlanDev &P, bool bf16, const int64_t *src_off, const int64_t *tgt_off,
                         const uint2 *a_list, const int32_t *a_choff, const uint32_t *b_list,
-                        const int32_t *b_choff, nwm_scorer sc, float *S, float *S_raw, hipStream_t st) {
+                        const int32_t *b_choff, nwm_scorer sc, float *S, float *S_raw, int xcd_map,
+                        hipStream_t st) {
   if (P.n_gt <= 0) return hipSuccess;
-  const int grid = 8 * ((P.n_gt + 7) / 8);
+  const int grid = xcd_map ? 8 * ((P.n_gt + 7) / 8) : P.n_gt;
   if (bf16)
     hipLaunchKernelGGL(k_score<true>, dim3(grid), dim3(64), 0, st, P, src_off, tgt_off, a_list, a_choff, b_list,
-                       b_choff, sc, S, S_raw);
+                       b_choff, sc, S, S_raw, xcd_map);
   else
     hipLaunchKernelGGL(k_score<false>, dim3(grid), dim3(64), 0, st, P, src_off, tgt_off, a_list, a_choff, b_list,
-                       b_choff, sc, S, S_raw);
+                       b_choff, sc, S, S_raw, xcd_map);
   return hipGetLastError();
 }
 

@@ -15,23 +15,23 @@
 #include "nwm_internal.h"
 
 namespace nwm {
-hipError_t launch_merge_src(int64_t, int64_t, const int64_t *, const int32_t *, const int32_t *, const int32_t *,
-                            const float *, int, int, uint2 *, uint2 *, int32_t *, hipStream_t);
+hipError_t launch_merge_src(int64_t, const int64_t *, const int32_t *, const int32_t *, const int32_t *,
+                            const float *, int, int, int, uint2 *, int32_t *, int, hipStream_t);
 hipError_t launch_build_a(const PlanDev &, const int64_t *, const uint2 *, const int32_t *, uint2 *, int32_t *,
                           int, int, hipStream_t);
 hipError_t launch_build_b(const PlanDev &, const int64_t *, const int32_t *, uint32_t *, int32_t *, int, int,
                           hipStream_t);
 hipError_t launch_score(const PlanDev &, bool, const int64_t *, const int64_t *, const uint2 *, const int32_t *,
-                        const uint32_t *, const int32_t *, nwm_scorer, float *, float *, hipStream_t);
+                        const uint32_t *, const int32_t *, nwm_scorer, float *, float *, int, hipStream_t);
 size_t score_lds_bytes(int nch, bool bf16);
 hipError_t score_set_attrs(int nch_max);
 hipError_t launch_nw_fill(const PlanDev &, const float *, float, float *, char *, uint64_t *, int64_t, int32_t *,
-                          hipStream_t);
+                          int, hipStream_t);
 hipError_t fill_set_attrs(int);
 hipError_t launch_nw_walk(const PlanDev &, const char *, int2 *, int32_t *, hipStream_t);
 hipError_t launch_keep(const PlanDev &, const float *, float, const int2 *, const int32_t *, int2 *, int32_t *,
                        hipStream_t);
-hipError_t merge_set_attrs(int V);
+hipError_t merge_set_attrs(int max_entries);
 hipError_t launch_backward(const PlanDev &, const int64_t *, const int64_t *, const int2 *, const int32_t *,
                            const float *, const float *, float *, double *, const float *, const float *,
                            double *, float *, float *, hipStream_t);
@@ -80,6 +80,13 @@ struct nwm_plan {
   nwm_prec prec = NWM_FP32;
   int64_t n_src = 0, n_tgt = 0, src_tokens = 0, tgt_tokens = 0;
   int64_t n_bnd = 0;   // uint64 entries of the published-row region
+  int max_entries = 1; // dictionary entries of the longest source sentence (tokens x max_deg)
+  // launch parameters (nwm_param) and what re-deriving the DP priority flags needs
+  int32_t param[4] = {0, 0, 1, 50};
+  uint64_t param_version = 0;
+  std::vector<int32_t> it_strip;   // strip index per DP item (no flags)
+  std::vector<int64_t> it_chain;   // dependency chain of the item's pair
+  int64_t max_chain = 0;
   int max_m = 0;
   std::vector<int32_t> n, m;
   void *dmeta = nullptr;
@@ -98,6 +105,17 @@ struct nwm_plan {
 namespace {
 
 nwm_status dev_err(hipError_t e) { return e == hipSuccess ? NWM_OK : NWM_EDEVICE; }
+
+// DP item words: strip index, plus ITEM_HOT for pairs whose dependency chain
+// is at least NWM_PARAM_DP_HOT_PERCENT of the longest
+void hot_flags(const nwm_plan *p, std::vector<int32_t> &out) {
+  const int64_t pct = p->param[NWM_PARAM_DP_HOT_PERCENT];
+  out.resize(p->it_strip.size());
+  for (size_t k = 0; k < out.size(); ++k) {
+    const bool hot = pct > 0 && p->it_chain[k] * 100 >= pct * p->max_chain;
+    out[k] = p->it_strip[k] | (hot ? ITEM_HOT : 0);
+  }
+}
 
 struct Mark {
   nwm_plan *p;
@@ -181,6 +199,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   p->prec = prec;
   p->src_tokens = batch->src_tokens;
   p->tgt_tokens = batch->tgt_tokens;
+  p->max_entries = std::max(1, batch->max_sent_tokens * max_deg);
   p->n.assign(batch->n_host, batch->n_host + B);
   p->m.assign(batch->m_host, batch->m_host + B);
   for (int b = 0; b < B; ++b) {
@@ -246,18 +265,19 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   // (chain ~ one hand-off of ~80 steps per strip + the m + 63 steps of the
   // last strip)
   auto chain = [&](int b) { return (int64_t)((p->n[b] + 63) / 64 - 1) * 80 + p->m[b] + 63; };
-  int64_t max_chain = 0;
+  p->max_chain = 0;
   for (int b = 0; b < B; ++b)
-    if (p->n[b] > 0 && p->m[b] > 0) max_chain = std::max(max_chain, chain(b));
+    if (p->n[b] > 0 && p->m[b] > 0) p->max_chain = std::max(p->max_chain, chain(b));
   for (int q = 0; q < B; ++q) {
     const int b = order[q];
     if (p->n[b] <= 0 || p->m[b] <= 0) continue;
-    const int32_t hot = 2 * chain(b) >= max_chain ? ITEM_HOT : 0;
     for (int s = 0; s < (p->n[b] + 63) / 64; ++s) {
       it_pair.push_back(b);
-      it_strip.push_back(s | hot);
+      p->it_strip.push_back(s);
+      p->it_chain.push_back(chain(b));
     }
   }
+  hot_flags(p, it_strip);
   // ---- device metadata: one allocation -----------------------------------------
   struct Piece {
     const void *src;
@@ -355,7 +375,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   p->sizes.tb_bytes = (size_t)D.path_base + 8 * (size_t)p_off[B];
   p->sizes.ws_bytes = W.total;
   // ---- kernel attributes (dynamic LDS above the default) ---------------------------
-  if (merge_set_attrs(p->V) != hipSuccess || score_set_attrs(nch) != hipSuccess || fill_set_attrs(0) != hipSuccess) {
+  if (merge_set_attrs(p->max_entries) != hipSuccess || score_set_attrs(nch) != hipSuccess || fill_set_attrs(0) != hipSuccess) {
     (void)hipFree(p->dmeta);
     delete p;
     return NWM_EDEVICE;
@@ -411,9 +431,9 @@ nwm_status nwm_score_pairs(nwm_plan *p, const nwm_batch *batch, const nwm_dict *
   const int esize = bf16 ? 2 : 4;
   {
     Mark mk(p, K_EXPAND, st);
-    // the per-token dictionary rows use a_list's memory before the lists do
-    hipError_t e = launch_merge_src(p->n_src, p->src_tokens, batch->src_off, batch->src_tok, dict->row_off,
-                                    dict->col, dict->val, p->V, p->max_deg, a_list, merged, cnt, st);
+    hipError_t e = launch_merge_src(p->n_src, batch->src_off, batch->src_tok, dict->row_off, dict->col, dict->val,
+                                    p->V, p->max_deg, p->max_entries, merged, cnt,
+                                    p->param[NWM_PARAM_MERGE_WAVES_PER_CU], st);
     if (e == hipSuccess) e = launch_build_a(p->dev, batch->src_off, merged, cnt, a_list, a_choff, pitch, esize, st);
     if (e == hipSuccess) e = launch_build_b(p->dev, batch->tgt_off, batch->tgt_tok, b_list, b_choff, pitch, esize, st);
     mk.done();
@@ -421,7 +441,7 @@ nwm_status nwm_score_pairs(nwm_plan *p, const nwm_batch *batch, const nwm_dict *
   }
   Mark mk(p, K_SCORE, st);
   hipError_t e = launch_score(p->dev, bf16, batch->src_off, batch->tgt_off, a_list, a_choff, b_list, b_choff, sc,
-                              S, S_raw, st);
+                              S, S_raw, p->param[NWM_PARAM_SCORE_XCD_MAP], st);
   mk.done();
   return dev_err(e);
 }
@@ -443,7 +463,7 @@ nwm_status nwm_align_batch(nwm_plan *p, const float *S, float gap, float thresho
   {
     Mark mk(p, K_FILL, st);
     e = launch_nw_fill(p->dev, S, gap, score, tbc, (uint64_t *)(w + p->ws.bnd), p->n_bnd,
-                       (int32_t *)(w + p->ws.ctl), st);
+                       (int32_t *)(w + p->ws.ctl), p->param[NWM_PARAM_FILL_WAVES_PER_CU], st);
     mk.done();
   }
   if (e != hipSuccess) return NWM_EDEVICE;
@@ -481,6 +501,42 @@ nwm_status nwm_align_backward(nwm_plan *p, const nwm_batch *batch, const void *t
   return dev_err(e);
 }
 
+nwm_status nwm_plan_set_param(nwm_plan *p, nwm_param param, int32_t value) {
+  if (!p) return NWM_EINVAL;
+  switch (param) {
+    case NWM_PARAM_FILL_WAVES_PER_CU:
+    case NWM_PARAM_MERGE_WAVES_PER_CU:
+      if (value < 0 || value > 32) return NWM_EINVAL;
+      break;
+    case NWM_PARAM_SCORE_XCD_MAP:
+      if (value != 0 && value != 1) return NWM_EINVAL;
+      break;
+    case NWM_PARAM_DP_HOT_PERCENT:
+      if (value < 0 || value > 100) return NWM_EINVAL;
+      break;
+    default:
+      return NWM_EINVAL;
+  }
+  if (p->param[param] == value) return NWM_OK;
+  p->param[param] = value;
+  ++p->param_version;
+  if (param == NWM_PARAM_DP_HOT_PERCENT && !p->it_strip.empty()) {
+    std::vector<int32_t> words;
+    hot_flags(p, words);
+    if (hipSetDevice(p->ctx->device) != hipSuccess ||
+        hipMemcpy(const_cast<int32_t *>(p->dev.it_strip), words.data(), 4 * words.size(), hipMemcpyHostToDevice) !=
+            hipSuccess)
+      return NWM_EDEVICE;
+  }
+  return NWM_OK;
+}
+
+nwm_status nwm_plan_get_param(const nwm_plan *p, nwm_param param, int32_t *value) {
+  if (!p || !value || (int)param < 0 || (int)param > 3) return NWM_EINVAL;
+  *value = p->param[param];
+  return NWM_OK;
+}
+
 nwm_status nwm_plan_set_graph(nwm_plan *p, int on) {
   if (!p) return NWM_EINVAL;
   p->graph_on = on != 0;
@@ -515,7 +571,7 @@ nwm_status nwm_mine(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, n
       ((uint64_t)bb << 32) | gb,           (uint64_t)tb_,                       (uint64_t)(uintptr_t)S,
       (uint64_t)(uintptr_t)S_raw,          (uint64_t)(uintptr_t)score,          (uint64_t)(uintptr_t)n_diag,
       (uint64_t)(uintptr_t)kept,           (uint64_t)(uintptr_t)n_kept,         (uint64_t)(uintptr_t)tb,
-      (uint64_t)(uintptr_t)ws};
+      (uint64_t)(uintptr_t)ws,             p->param_version};
   if (!p->graph_exec || key != p->graph_key) {
     if (p->graph_exec) {
       (void)hipGraphExecDestroy(p->graph_exec);
