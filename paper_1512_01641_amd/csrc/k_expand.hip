@@ -29,14 +29,46 @@ static __device__ __forceinline__ void wave_sync() {
 
 constexpr uint32_t HEMPTY = 0xFFFFFFFFu;
 
-// One wave per source sentence (grid-stride): the sentence's tokens and
-// their dictionary rows (loaded one sentence ahead), merged by target word
-// through an LDS hash table of 2^hbits slots (open addressing, linear
-// probing, at most half full by the plan's bound on tokens x degree).  The
-// sums are FP64 LDS atomics of FP32 terms -- exact, so independent of the
-// order of the atomics -- rounded to FP32 once on the way out.  A sentence
-// longer than the caller's max_sent_tokens (a contract violation) cannot
-// hang or write out of bounds: a full table or slot list drops entries.
+// Software pipeline of the merge over a wave's sentences: the token range of
+// a sentence is loaded four sentences ahead, its tokens three ahead, their
+// dictionary row offsets two ahead and the first four entries of every row
+// one ahead, so each load has a whole sentence of merging to land.  Lane l holds token l of the
+// sentence's first 64 tokens.  Every pipelined load is an unconditional raw
+// buffer load (lanes with nothing to load use an offset past the buffer and
+// read 0), so the wait counts stay exact; validity is applied when a value
+// is used.
+struct MergeOff {
+  int64_t t0, t1;   // as loaded; the length is formed where it is used
+  bool ok;
+};
+struct MergeTok {
+  int64_t t0;
+  int len, tok;
+};
+struct MergeRow {
+  int64_t t0;
+  int len, e0, e1;   // row [e0, e1) of the lane's token (e1 = e0 if none)
+};
+struct MergeEnt {
+  int64_t t0;
+  int len, e0, deg;
+  uint32_t u[4];
+  float v[4];
+};
+constexpr uint32_t BUF_OOB = 0xFFFFFFF0u;
+
+static __device__ __forceinline__ uint32_t buf_u32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+
+// One wave per source sentence (grid-stride): T'[i][u] = sum over the
+// sentence's tokens t of D[t][u], merged by target word u through an LDS
+// hash table of 2^hbits slots (open addressing, linear probing, at most half
+// full by the plan's bound on tokens x degree).  The sums are FP64 LDS atomics
+// of FP32 terms -- exact, so independent of the order of the atomics --
+// rounded to FP32 once on the way out.  A sentence longer than the caller's
+// max_sent_tokens (a contract violation) cannot hang or write out of bounds:
+// a full table or slot list drops entries.
 __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t *__restrict__ src_off,
                                                   const int32_t *__restrict__ src_tok,
                                                   const int32_t *__restrict__ d_row_off,
@@ -56,91 +88,142 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
   }
   wave_sync();
 
-  // sentence `sent`: its token range, and lane l's token's dictionary row
-  // (tokens c0 + l)
-  auto fetch_rows = [&](int64_t t0, int len, int c0, int &e0, int &deg) {
-    e0 = 0;
-    deg = 0;
-    if (c0 + lane < len) {
-      const int tok = src_tok[t0 + c0 + lane];
-      if ((unsigned)tok < (unsigned)V) {
-        e0 = d_row_off[tok];
-        deg = min(d_row_off[tok + 1] - e0, max_deg);
+  const int nnz = d_row_off[V];   // dictionary entries
+  const __amdgpu_buffer_rsrc_t r_row =
+      __builtin_amdgcn_make_buffer_rsrc((void *)d_row_off, (short)0, (V + 1) * 4, 0x00020000);
+  const __amdgpu_buffer_rsrc_t r_col = __builtin_amdgcn_make_buffer_rsrc((void *)d_col, (short)0, nnz * 4, 0x00020000);
+  const __amdgpu_buffer_rsrc_t r_val = __builtin_amdgcn_make_buffer_rsrc((void *)d_val, (short)0, nnz * 4, 0x00020000);
+
+  // unconditional (clamped) scalar loads: nothing waits on them before the
+  // next sentence uses them
+  auto load_off = [&](int64_t sent) {
+    MergeOff O;
+    const int64_t k = sent < n_sent ? sent : n_sent - 1;
+    O.t0 = src_off[k];
+    O.t1 = src_off[k + 1];
+    O.ok = sent < n_sent;
+    return O;
+  };
+  auto load_tok = [&](const MergeOff &O) {
+    MergeTok T;
+    T.t0 = O.t0;
+    T.len = O.ok ? (int)(O.t1 - O.t0) : 0;
+    // a buffer over this sentence's first 64 tokens
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(src_tok + T.t0), (short)0, min(T.len, 64) * 4, 0x00020000);
+    T.tok = (int)buf_u32(r, (uint32_t)lane * 4u);
+    return T;
+  };
+  auto load_row = [&](const MergeTok &T) {
+    MergeRow R;
+    R.t0 = T.t0;
+    R.len = T.len;
+    const bool ok = lane < T.len && (unsigned)T.tok < (unsigned)V;
+    const uint32_t off = ok ? (uint32_t)T.tok * 4u : BUF_OOB;
+    R.e0 = (int)buf_u32(r_row, off);
+    R.e1 = (int)buf_u32(r_row, ok ? off + 4u : BUF_OOB);
+    return R;
+  };
+  auto load_ent = [&](const MergeRow &R) {
+    MergeEnt E;
+    E.t0 = R.t0;
+    E.len = R.len;
+    E.e0 = R.e0;
+    E.deg = max(0, min(R.e1 - R.e0, max_deg));
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const uint32_t off = d < E.deg ? (uint32_t)(E.e0 + d) * 4u : BUF_OOB;
+      E.u[d] = buf_u32(r_col, off);
+      E.v[d] = __uint_as_float(buf_u32(r_val, off));
+    }
+    return E;
+  };
+
+  int nuniq = 0;
+  // one dictionary entry per lane into the table
+  auto insert = [&](uint32_t u, float v) {
+    const bool act = u < (uint32_t)V;
+    uint32_t h = act ? (u * 0x9E3779B1u) >> (32 - hbits) : 0u;
+    bool pending = act, claimed = false, placed = false;
+    int probes = 0;
+    while (__ballot(pending) != 0) {
+      if (pending) {
+        const uint32_t old = atomicCAS(&key[h], HEMPTY, u);
+        if (old == HEMPTY || old == u) {
+          claimed = old == HEMPTY;
+          placed = true;
+          pending = false;
+        } else if (++probes >= HS) {
+          pending = false;   // table full: drop
+        } else {
+          h = (h + 1) & (uint32_t)(HS - 1);
+        }
       }
     }
+    if (placed) atomicAdd(&acc[h], (double)v);
+    const uint64_t cm = __ballot(claimed);
+    const int rank = nuniq + __popcll(cm & ((1ull << lane) - 1ull));
+    if (claimed && rank < CAPU) slots[rank] = (int)h;
+    nuniq = min(nuniq + __popcll(cm), CAPU);
   };
+
+  const int64_t G = gridDim.x;
   int64_t sent = blockIdx.x;
-  int64_t nt0 = 0;
-  int nlen = 0, ne0 = 0, ndeg = 0;
-  if (sent < n_sent) {
-    nt0 = src_off[sent];
-    nlen = (int)(src_off[sent + 1] - nt0);
-    fetch_rows(nt0, nlen, 0, ne0, ndeg);
-  }
-  for (; sent < n_sent; sent += gridDim.x) {
-    const int64_t t0 = nt0;
-    const int len = nlen;
-    int e0 = ne0, deg = ndeg;
-    const int64_t nxt = sent + gridDim.x;
-    if (nxt < n_sent) {
-      nt0 = src_off[nxt];
-      nlen = (int)(src_off[nxt + 1] - nt0);
-      fetch_rows(nt0, nlen, 0, ne0, ndeg);
+  MergeEnt E = load_ent(load_row(load_tok(load_off(sent))));
+  MergeRow R = load_row(load_tok(load_off(sent + G)));
+  MergeTok T = load_tok(load_off(sent + 2 * G));
+  MergeOff O = load_off(sent + 3 * G);
+  for (; sent < n_sent; sent += G) {
+    const MergeEnt cur = E;
+    E = load_ent(R);
+    R = load_row(T);
+    T = load_tok(O);
+    O = load_off(sent + 4 * G);
+
+    nuniq = 0;
+    // first 64 tokens: entries 0..3 loaded ahead, further entries here
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+      if (__ballot(d < cur.deg) != 0) insert(d < cur.deg ? cur.u[d] : HEMPTY, cur.v[d]);
+    for (int q = 4; q < max_deg; ++q) {
+      if (__ballot(q < cur.deg) == 0) break;
+      uint32_t u = HEMPTY;
+      float v = 0.0f;
+      if (q < cur.deg) {
+        u = (uint32_t)d_col[cur.e0 + q];
+        v = d_val[cur.e0 + q];
+      }
+      insert(u, v);
     }
-    int nuniq = 0;
-    for (int c0 = 0; c0 < len; c0 += 64) {
-      if (c0 > 0) fetch_rows(t0, len, c0, e0, deg);   // tokens past the first 64
-      for (int q0 = 0; q0 < max_deg; q0 += 4) {
-        if (__ballot(q0 < deg) == 0) break;
-        // entries q0 .. q0+3 of this lane's row, loaded together
-        uint32_t u[4];
-        float v[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          u[d] = HEMPTY;
-          v[d] = 0.0f;
-          if (q0 + d < deg) {
-            u[d] = (uint32_t)d_col[e0 + q0 + d];
-            v[d] = d_val[e0 + q0 + d];
-          }
+    // tokens past the first 64 (long sentences)
+    for (int c0 = 64; c0 < cur.len; c0 += 64) {
+      int e0 = 0, deg = 0;
+      if (c0 + lane < cur.len) {
+        const int tok = src_tok[cur.t0 + c0 + lane];
+        if ((unsigned)tok < (unsigned)V) {
+          e0 = d_row_off[tok];
+          deg = min(d_row_off[tok + 1] - e0, max_deg);
         }
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          const bool act = u[d] < (uint32_t)V;
-          uint32_t h = act ? (u[d] * 0x9E3779B1u) >> (32 - hbits) : 0u;
-          bool pending = act, claimed = false, placed = false;
-          int probes = 0;
-          while (__ballot(pending) != 0) {
-            if (pending) {
-              const uint32_t old = atomicCAS(&key[h], HEMPTY, u[d]);
-              if (old == HEMPTY || old == u[d]) {
-                claimed = old == HEMPTY;
-                placed = true;
-                pending = false;
-              } else if (++probes >= HS) {
-                pending = false;   // table full: drop
-              } else {
-                h = (h + 1) & (uint32_t)(HS - 1);
-              }
-            }
-          }
-          if (placed) atomicAdd(&acc[h], (double)v[d]);
-          const uint64_t cm = __ballot(claimed);
-          const int rank = nuniq + __popcll(cm & ((1ull << lane) - 1ull));
-          if (claimed && rank < CAPU) slots[rank] = (int)h;
-          nuniq = min(nuniq + __popcll(cm), CAPU);
+      }
+      for (int q = 0; q < max_deg; ++q) {
+        if (__ballot(q < deg) == 0) break;
+        uint32_t u = HEMPTY;
+        float v = 0.0f;
+        if (q < deg) {
+          u = (uint32_t)d_col[e0 + q];
+          v = d_val[e0 + q];
         }
+        insert(u, v);
       }
     }
     wave_sync();
-    const int64_t base = t0 * (int64_t)max_deg;
+    const int64_t base = cur.t0 * (int64_t)max_deg;
     for (int e = lane; e < nuniq; e += 64) {
       const int h = slots[e];
       merged[base + e] = make_uint2(key[h], __float_as_uint((float)acc[h]));
     }
     wave_sync();
-    // clear every slot this sentence touched (claimed ones are in slots[];
-    // a dropped entry never claimed one)
+    // clear every slot this sentence claimed (a dropped entry claimed none)
     for (int e = lane; e < nuniq; e += 64) {
       const int h = slots[e];
       key[h] = HEMPTY;

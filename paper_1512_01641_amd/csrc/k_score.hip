@@ -80,18 +80,24 @@ struct Lists {
   const uint32_t *pb;   // the tile's B list
 };
 
-static __device__ __forceinline__ void load_chunk(Chunk &C, const Lists &L, OffWin &W,
-                                                  const int32_t *__restrict__ chA, const int32_t *__restrict__ chB,
-                                                  int nch, int c, int lane) {
-  if (c >= W.base + 64) {   // slide: window 1 (loaded 64 chunks ago) becomes window 0
-    W.base += 64;
-    W.wa0 = W.wa1;
-    W.sa0 = W.sa1;
-    W.wb0 = W.wb1;
-    W.sb0 = W.sb1;
-    load_window(W.wa1, W.sa1, chA, W.base + 64, nch, lane);
-    load_window(W.wb1, W.sb1, chB, W.base + 64, nch, lane);
-  }
+// Window 1 (loaded 64 chunks ago) becomes window 0 when chunk c leaves
+// window 0; rare, uniform, kept out of the chunk's straight-line code.
+static __device__ __forceinline__ bool needs_slide(const OffWin &W, int c) { return c >= W.base + 64; }
+
+static __device__ __forceinline__ void slide_window(OffWin &W, const int32_t *__restrict__ chA,
+                                                    const int32_t *__restrict__ chB, int nch, int lane) {
+  W.base += 64;
+  W.wa0 = W.wa1;
+  W.sa0 = W.sa1;
+  W.wb0 = W.wb1;
+  W.sb0 = W.sb1;
+  load_window(W.wa1, W.sa1, chA, W.base + 64, nch, lane);
+  load_window(W.wb1, W.sb1, chB, W.base + 64, nch, lane);
+}
+
+// The list entries of chunk c (the window must cover c) into C.
+static __device__ __forceinline__ void load_chunk_regs(Chunk &C, const Lists &L, const OffWin &W, int c,
+                                                       int lane) {
   const int k = c - W.base;
   C.a0 = __builtin_amdgcn_readlane(W.wa0, k);
   C.na = __builtin_amdgcn_readlane(W.sa0, k) - C.a0;
@@ -107,33 +113,46 @@ static __device__ __forceinline__ void load_chunk(Chunk &C, const Lists &L, OffW
   for (int q = 0; q < REG_B; ++q) C.b[q] = pb[q * 64 + lane];
 }
 
+static __device__ __forceinline__ void load_chunk(Chunk &C, const Lists &L, OffWin &W,
+                                                  const int32_t *__restrict__ chA, const int32_t *__restrict__ chB,
+                                                  int nch, int c, int lane) {
+  if (needs_slide(W, c)) slide_window(W, chA, chB, nch, lane);
+  load_chunk_regs(C, L, W, c, lane);
+}
+
+static __device__ __forceinline__ bool overflows(const Chunk &C) { return C.na > REG_A * 64 || C.nb > REG_B * 64; }
+
 template <typename T>
 static __device__ __forceinline__ void lds_put(char *tile, uint32_t byte_off, T v) {
   *reinterpret_cast<T *>(tile + byte_off) = v;
 }
 
-// Set the chunk's entries in the tiles.  Lanes past the count write to their
-// own padding word (distinct banks, never read as a fragment), and the
-// address each lane used is kept in the chunk for the clear; groups of 64 entries wholly past the count are skipped by a uniform
-// branch.  Entries beyond the register capacity (rare) come from the lists.
+// Set the chunk's register entries in the tiles: every group of 64, with
+// lanes past the count writing to a padding element no fragment reads; the
+// address each lane used is kept in the chunk for the clear.  Straight-line
+// code (no branches), so it can be interleaved with the MFMAs.
 template <bool BF16>
-static __device__ __forceinline__ void scatter_set(Chunk &C, char *At, char *Bt, const Lists &L, int lane,
-                                                   uint32_t junk) {
+static __device__ __forceinline__ void scatter_set_regs(Chunk &C, char *At, char *Bt, int lane, uint32_t junk) {
   typedef typename Op<BF16>::T T;
 #pragma unroll
-  for (int q = 0; q < REG_A; ++q)
-    if (C.na > 64 * q) {
-      const uint32_t x = lane < C.na - 64 * q ? C.a[q].x : junk;
-      C.a[q].x = x;
-      lds_put<T>(At, x, T(__uint_as_float(C.a[q].y)));
-    }
+  for (int q = 0; q < REG_A; ++q) {
+    const uint32_t x = lane + 64 * q < C.na ? C.a[q].x : junk;
+    C.a[q].x = x;
+    lds_put<T>(At, x, T(__uint_as_float(C.a[q].y)));
+  }
 #pragma unroll
-  for (int q = 0; q < REG_B; ++q)
-    if (C.nb > 64 * q) {
-      const uint32_t x = lane < C.nb - 64 * q ? C.b[q] : junk;
-      C.b[q] = x;
-      lds_put<T>(Bt, x, T(1.0f));
-    }
+  for (int q = 0; q < REG_B; ++q) {
+    const uint32_t x = lane + 64 * q < C.nb ? C.b[q] : junk;
+    C.b[q] = x;
+    lds_put<T>(Bt, x, T(1.0f));
+  }
+}
+
+// Entries beyond the register capacity (rare) come straight from the lists.
+template <bool BF16>
+static __device__ __forceinline__ void scatter_set_rest(const Chunk &C, char *At, char *Bt, const Lists &L,
+                                                        int lane) {
+  typedef typename Op<BF16>::T T;
   for (int e = REG_A * 64 + lane; e < C.na; e += 64) {
     const uint2 v = L.pa[C.a0 + e];
     lds_put<T>(At, v.x, T(__uint_as_float(v.y)));
@@ -141,24 +160,23 @@ static __device__ __forceinline__ void scatter_set(Chunk &C, char *At, char *Bt,
   for (int e = REG_B * 64 + lane; e < C.nb; e += 64) lds_put<T>(Bt, L.pb[C.b0 + e], T(1.0f));
 }
 
-// Return the tiles to zero after a chunk, at the addresses its scatter used,
-// or both whole tiles when the chunk overflowed the registers.
+// Return the tiles to zero after a chunk, at the addresses its scatter used.
 template <bool BF16>
-static __device__ __forceinline__ void scatter_clear(const Chunk &C, char *At, char *Bt, int lane) {
+static __device__ __forceinline__ void scatter_clear_regs(const Chunk &C, char *At, char *Bt) {
   typedef typename Op<BF16>::T T;
-  constexpr int TILE_BYTES = TM * Op<BF16>::PITCH * (int)sizeof(T);
-  if (C.na > REG_A * 64 || C.nb > REG_B * 64) {
-    uint4 *p = reinterpret_cast<uint4 *>(At);
-    constexpr int N16 = 2 * TILE_BYTES / 16;
-    for (int e = lane; e < N16; e += 64) p[e] = make_uint4(0u, 0u, 0u, 0u);
-    return;
-  }
 #pragma unroll
-  for (int q = 0; q < REG_A; ++q)
-    if (C.na > 64 * q) lds_put<T>(At, C.a[q].x, T(0.0f));
+  for (int q = 0; q < REG_A; ++q) lds_put<T>(At, C.a[q].x, T(0.0f));
 #pragma unroll
-  for (int q = 0; q < REG_B; ++q)
-    if (C.nb > 64 * q) lds_put<T>(Bt, C.b[q], T(0.0f));
+  for (int q = 0; q < REG_B; ++q) lds_put<T>(Bt, C.b[q], T(0.0f));
+}
+
+// Both whole tiles of a buffer, after a chunk that overflowed the registers.
+template <bool BF16>
+static __device__ __forceinline__ void clear_tiles(char *At, int lane) {
+  constexpr int TILE_BYTES = TM * Op<BF16>::PITCH * (int)sizeof(typename Op<BF16>::T);
+  uint4 *p = reinterpret_cast<uint4 *>(At);
+  constexpr int N16 = 2 * TILE_BYTES / 16;
+  for (int e = lane; e < N16; e += 64) p[e] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // MFMA operand fragments of one chunk (BF16: one K step of 32; FP32: eight
@@ -217,6 +235,35 @@ static __device__ __forceinline__ void mfma_frags(const Frags<BF16> &F, f32x4 (&
   }
 }
 
+// Instruction groups for the scheduler over one chunk's straight-line code:
+// each MFMA followed by a slice of the other work -- first the LDS writes
+// (clear, then scatter) with their VALU, then the fragment reads of the next
+// chunk, then the list loads.  Dependencies are kept; groups that cannot be
+// filled stay empty.
+template <bool BF16>
+static __device__ __forceinline__ void interleave() {
+  constexpr int NMFMA = BF16 ? 16 : 128;
+  constexpr int NW = 2 * (REG_A + REG_B);   // LDS writes: clear + set
+  constexpr int NR = BF16 ? 8 : 64;         // fragment reads
+  constexpr int P1 = 6, P2 = 8;             // MFMAs carrying writes, reads
+  constexpr int PER_R = NR / P2;
+#pragma unroll
+  for (int i = 0; i < P1; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x200, (NW + P1 - 1) / P1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < P2; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, PER_R, 0);
+  }
+  __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+  __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+  __builtin_amdgcn_sched_group_barrier(0x020, REG_A + REG_B, 0);
+  __builtin_amdgcn_sched_group_barrier(0x008, NMFMA - P1 - P2 - 1, 0);
+}
+
 template <bool BF16>
 struct ScoreLds {
   static constexpr int TILE = TM * Op<BF16>::PITCH * (int)sizeof(typename Op<BF16>::T);   // one operand tile
@@ -254,9 +301,10 @@ __global__ __launch_bounds__(64) void k_score(PlanDev P, const int64_t *__restri
   const int m = P.m[pair];
   const int nch = P.nch;
   const int lane = threadIdx.x;
-  // this lane's padding word: row lane % 16, word lane / 16 of the row's
-  // padding (columns KC ..): the 64 lanes hit 64 distinct LDS banks
-  const uint32_t junk = (uint32_t)(((lane & 15) * Op<BF16>::PITCH + KC) * (int)sizeof(T) + 4 * (lane >> 4));
+  // where idle lanes write: one padding element (row 0, column KC) shared
+  // by all of them -- accesses to one address merge, so idle lanes add no
+  // bank conflicts to the valid lanes' scattered writes
+  const uint32_t junk = (uint32_t)(KC * (int)sizeof(T));
 
   const int32_t *chA = a_choff + (int64_t)rt * (nch + 1);
   const int32_t *chB = b_choff + (int64_t)ct * (nch + 1);
@@ -298,21 +346,34 @@ __global__ __launch_bounds__(64) void k_score(PlanDev P, const int64_t *__restri
   load_chunk(S2, L, W, chA, chB, nch, 2, lane);
   Frags<BF16> F0, F1;
   wave_sync();
-  scatter_set<BF16>(S0, smem, smem + TB, L, lane, junk);
+  scatter_set_regs<BF16>(S0, smem, smem + TB, lane, junk);
+  scatter_set_rest<BF16>(S0, smem, smem + TB, L, lane);
   wave_sync();
   read_frags<BF16>(F0, smem, smem + TB, lane);
 
+  // One chunk.  The core is straight-line code whose LDS and memory work the
+  // scheduler interleaves between the MFMAs (MFMA issue blocks a wave, so
+  // without interleaving a wave would start its LDS work only after its last
+  // MFMA).  Rare cases sit outside it: a full clear after an overflowing
+  // chunk and the offset-window slide before, the overflow entries of the
+  // next chunk (then its fragments are read again) after.  Past the last
+  // chunk the "next" chunk has no entries, so the core needs no test.
 #define NWM_SCORE_CHUNK(c, prev, nxt, Fc, Fn)                                  \
   {                                                                            \
     char *Ao_ = smem + (((c) + 1) & 1) * 2 * TB;                               \
+    if (overflows(prev)) clear_tiles<BF16>(Ao_, lane);                         \
+    if (needs_slide(W, (c) + 3)) slide_window(W, chA, chB, nch, lane);         \
     mfma_frags<BF16>(Fc, acc);                                                 \
-    scatter_clear<BF16>(prev, Ao_, Ao_ + TB, lane);                            \
-    if ((c) + 1 < nch) {                                                       \
-      scatter_set<BF16>(nxt, Ao_, Ao_ + TB, L, lane, junk);                    \
+    scatter_clear_regs<BF16>(prev, Ao_, Ao_ + TB);                             \
+    scatter_set_regs<BF16>(nxt, Ao_, Ao_ + TB, lane, junk);                    \
+    read_frags<BF16>(Fn, Ao_, Ao_ + TB, lane);                                 \
+    load_chunk_regs(prev, L, W, (c) + 3, lane);                                \
+    interleave<BF16>();                                                        \
+    if (overflows(nxt)) {                                                      \
+      scatter_set_rest<BF16>(nxt, Ao_, Ao_ + TB, L, lane);                     \
       wave_sync();                                                             \
       read_frags<BF16>(Fn, Ao_, Ao_ + TB, lane);                               \
     }                                                                          \
-    load_chunk(prev, L, W, chA, chB, nch, (c) + 3, lane); /* empty past nch */ \
   }
   int c = 0;
   for (; c + 4 <= nch; c += 4) {

@@ -21,10 +21,10 @@ constexpr int PITCH_BF16 = KC + 8;   // 80 B rows: conflict-free ds_read_b128
 constexpr int PITCH_F32 = KC + 4;    // 144 B rows
 
 // List entries of one K chunk held in registers per lane by the contraction
-// (A: 128 entries, B: 256).  Every chunk load reads that many entries from
+// (A: 128 entries, B: 128).  Every chunk load reads that many entries from
 // the chunk start, so the lists carry that much slack at their end.
 constexpr int REG_A = 2;
-constexpr int REG_B = 4;
+constexpr int REG_B = 2;
 constexpr int LIST_SLACK_A = 64 * REG_A;
 constexpr int LIST_SLACK_B = 64 * REG_B;
 // LDS staging capacity of tile lists (entries) per K segment.
