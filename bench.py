@@ -46,6 +46,23 @@ def _time_steps(fn, steps, warmup, torch):
     return (time.perf_counter() - t0) * 1000.0 / max(steps, 1)
 
 
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None once the kernel's source differs from the profiled one."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(kernel)
+    if not rec:
+        return None
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return rec["bytes_per_launch"]
+
+
 def cpu_baseline(batch, seconds_hint=30.0):
     """The CPU oracle (FP64 scores, FP32 DP) on the host cores, timed on a
     bounded sample of the same workload."""
@@ -206,13 +223,15 @@ def main():
         "ratio_batched_bf16_vs_plain_fp32": round(plain / bf_ms, 2) if plain else None,
         "kernel_ms_per_step": {p: {k: round(v, 4) for k, v in kernel[p].items()} for p, _ in precs},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": MFMA_PEAK_TFLOPS[head],
-                     "unit": "TFLOP/s", "frac": round(achieved / MFMA_PEAK_TFLOPS[head], 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / MFMA_PEAK_TFLOPS[head], 4),
+                     "traffic": profiled_traffic("k_score<%s>" % head),
                      "kernel": "k_score<%s> (contraction + logistic epilogue)" % head,
                      "algorithmic": "2*V*sum(n*m) = %.4g flop per launch" % flops},
         "dp_roofline": {"bound": "hbm", "achieved": round(dp_bytes / (fill_ms / 1000.0) / 1e9, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(dp_bytes / (fill_ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
-                        "kernel": "k_nw_fill", "algorithmic": "4.25 B/cell (S read + 2-bit traceback)"},
+                        "kernel": "k_nw_fill", "algorithmic": "4.25 B/cell (S read + 2-bit traceback)",
+                        "traffic": profiled_traffic("k_nw_fill")},
     }
     if not args.no_cpu:
         _log("cpu baseline")
