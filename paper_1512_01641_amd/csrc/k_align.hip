@@ -325,15 +325,29 @@ static __device__ __forceinline__ u32x4 load_block_async(const uint4 *p) {
   return v;
 }
 
+// The 2-bit code at position p (0..63) of a block row held as four words of
+// 16 codes (first position in the high bits); w0..w3 may be per lane.
+static __device__ __forceinline__ uint32_t code_at(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, int p) {
+  const int q = p >> 4;
+  const uint32_t w = q == 0 ? w0 : q == 1 ? w1 : q == 2 ? w2 : w3;
+  return (w >> (2 * (15 - (p & 15)))) & 3u;
+}
+
 // Traceback (Sec. 5.1): from (n, m) back to the first row or column,
 // following the stored directions; every DIAG step emits the aligned pair.
-// One wave per pair (longest pair first).  The walk reads one 64-step block
-// of one strip at a time (lane l: row l's four code words).  On entering a
-// block it prefetches the three blocks the walk can enter next -- the
-// previous block of the strip, or the block above or above-right in the
-// strip above -- so a block change waits only for loads issued one block
-// earlier.  Path cells collect in registers (one per lane) and LDS and reach
-// memory in coalesced stores at the end.
+// One wave per pair (longest pair first).  Position: strip s, row r of the
+// strip (lane r), anti-diagonal step t = j - 1 + r; the walk holds the 1 KiB
+// block of codes covering steps [64 G, 64 G + 64) of the strip (lane l: row
+// l's four words).  It moves by runs: at a cell whose code is DIAG or UP,
+// every lane evaluates the code on the line the path follows (rows below r,
+// steps t - 2 (r - row) or t - (r - row)), a ballot finds the first row where
+// the code differs or the block ends, and the whole run is one iteration; a
+// LEFT run is found the same way along the row.  The cells of a DIAG run are
+// written to LDS by their lanes at once.  On entering a block the walk
+// prefetches the three blocks it can enter next (the previous block of the
+// strip, the block above and the one above-right in the strip above), loads
+// it waits for itself at the next block change.  Path cells reach memory in
+// coalesced stores.
 __global__ __launch_bounds__(64) void k_nw_walk(PlanDev P, const char *__restrict__ tb_bits,
                                                 int2 *__restrict__ path, int32_t *__restrict__ n_diag) {
   __shared__ int2 lbuf[WALK_LDS];
@@ -354,26 +368,38 @@ __global__ __launch_bounds__(64) void k_nw_walk(PlanDev P, const char *__restric
     const bool ok = s >= 0 && s < nS && G >= 0 && G < nG;
     return tbw + (ok ? ((int64_t)s * nG + G) * 64 : 0) + lane;
   };
-  int i = n, j = m, k = 0, flushed = 0;
-  int cs = (n - 1) >> 6, cG = (m - 1 + ((n - 1) & 63)) >> 6;
+  // position: strip s, row r, step t  (i = 64 s + r + 1, j = t - r + 1)
+  int s = (n - 1) >> 6, r = (n - 1) & 63, t = m - 1 + r;
+  int k = 0, kb = 0, flushed = 0;   // cells emitted; cells in lbuf; cells stored
+  int cs = s, cG = t >> 6;
   u32x4 cur = load_block_async(blk_ptr(cs, cG));
   u32x4 pA = load_block_async(blk_ptr(cs, cG - 1));
   u32x4 pB = load_block_async(blk_ptr(cs - 1, cG));
   u32x4 pC = load_block_async(blk_ptr(cs - 1, cG + 1));
   asm volatile("s_waitcnt vmcnt(3)" : "+v"(cur));
-  int ckk = -1;
-  uint32_t cw = 0u;   // the current block's code word for 16 steps
-  int ri = 0, rj = 0;   // lane l: cell l of the current batch of 64
-  while (i > 0 && j > 0) {
-    const int s = (i - 1) >> 6;
-    const int r = (i - 1) & 63;
-    const int t = j - 1 + r;
+  auto flush = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int e = lane; e < kb; e += 64) {
+      const int q = flushed + e;
+      if (q < cap) pa[cap - 1 - q] = lbuf[e];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    flushed += kb;
+    kb = 0;
+  };
+  for (;;) {
+    if (r < 0) {   // into the strip above
+      --s;
+      r += 64;
+      t += 64;
+    }
+    if (s < 0 || t - r < 0) break;   // i == 0 or j == 0
     const int G = t >> 6;
     if (s != cs || G != cG) {
-      // The three prefetches (issued one block ago) must all have landed
-      // before any of their registers can be reused: the compiler does not
-      // know they are in flight, so a register it reuses (say, for the next
-      // load's address) could otherwise be overwritten by a late load.
+      // the three prefetches (one block old) must have landed before any of
+      // their registers can be reused; the compiler does not track them
       asm volatile("s_waitcnt vmcnt(0)" : "+v"(pA), "+v"(pB), "+v"(pC));
       if (s == cs && G == cG - 1) {
         cur = pA;
@@ -387,60 +413,51 @@ __global__ __launch_bounds__(64) void k_nw_walk(PlanDev P, const char *__restric
       }
       cs = s;
       cG = G;
-      ckk = -1;
       pA = load_block_async(blk_ptr(cs, cG - 1));
       pB = load_block_async(blk_ptr(cs - 1, cG));
       pC = load_block_async(blk_ptr(cs - 1, cG + 1));
     }
-    const int kk = (t >> 4) & 3;
-    if (kk != ckk) {
-      cw = kk == 0 ? cur.x : kk == 1 ? cur.y : kk == 2 ? cur.z : cur.w;
-      ckk = kk;
-    }
-    const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)cw, r);
-    const uint32_t code = (v >> (2 * (15 - (t & 15)))) & 3u;
-    if (code == DIR_UP) {
-      --i;
-    } else if (code == DIR_LEFT) {
-      --j;
+    const int base = 64 * G;
+    // code of the current cell: row r's word of step t
+    const uint32_t c0 = code_at((uint32_t)__builtin_amdgcn_readlane((int)cur.x, r),
+                                (uint32_t)__builtin_amdgcn_readlane((int)cur.y, r),
+                                (uint32_t)__builtin_amdgcn_readlane((int)cur.z, r),
+                                (uint32_t)__builtin_amdgcn_readlane((int)cur.w, r), t - base);
+    if (c0 == DIR_LEFT) {
+      // lane q: step t - q of row r
+      const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)cur.x, r);
+      const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)cur.y, r);
+      const uint32_t w2 = (uint32_t)__builtin_amdgcn_readlane((int)cur.z, r);
+      const uint32_t w3 = (uint32_t)__builtin_amdgcn_readlane((int)cur.w, r);
+      const int tq = t - lane;
+      const bool ok = tq >= base && tq - r >= 0 && code_at(w0, w1, w2, w3, max(tq - base, 0)) == DIR_LEFT;
+      const uint64_t brk = __ballot(!ok);
+      const int L = brk ? __builtin_ctzll(brk) : 64;   // >= 1: lane 0 is the current cell
+      t -= L;
     } else {
-      const int slot = k & 63;
-      if (lane == slot) {
-        ri = i - 1;
-        rj = j - 1;
+      // DIAG (slope 2) or UP (slope 1): lane rho <= r, step t - slope (r - rho)
+      const int slope = c0 == DIR_DIAG ? 2 : 1;
+      const int tr = t - slope * (r - lane);
+      const bool ok = lane <= r && tr >= base && tr - lane >= 0 &&
+                      code_at(cur.x, cur.y, cur.z, cur.w, max(tr - base, 0)) == c0;
+      const uint64_t below = r >= 63 ? ~0ull : ((2ull << r) - 1ull);   // rows 0..r
+      const uint64_t brk = __ballot(!ok) & below;
+      const int rs = brk ? 63 - __builtin_clzll(brk) : -1;   // highest breaking row (< r)
+      const int L = r - rs;
+      if (c0 == DIR_DIAG) {
+        if (kb + L > WALK_LDS) flush();
+        // rows rs+1 .. r emit cells k .. k+L-1 (row r first)
+        if (lane > rs && lane <= r) lbuf[kb + (r - lane)] = make_int2(64 * s + lane, tr - lane);
+        kb += L;
+        k += L;
       }
-      ++k;
-      if (slot == 63) {   // a full batch: to LDS, and LDS to memory when full
-        const int q0 = k - 64 - flushed;
-        lbuf[q0 + lane] = make_int2(ri, rj);
-        if (q0 + 64 == WALK_LDS) {
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          for (int e = lane; e < WALK_LDS; e += 64) {
-            const int q = flushed + e;
-            if (q < cap) pa[cap - 1 - q] = lbuf[e];
-          }
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          flushed += WALK_LDS;
-        }
-      }
-      --i;
-      --j;
+      r -= L;
+      t -= slope * L;
     }
   }
   // drain the prefetches before the wave ends
   asm volatile("s_waitcnt vmcnt(0)" : "+v"(pA), "+v"(pB), "+v"(pC));
-  // the last partial batch, then everything buffered since the last flush
-  const int rem = k - flushed;
-  const int q0 = (k & ~63) - flushed;
-  if (lane < (k & 63)) lbuf[q0 + lane] = make_int2(ri, rj);
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  for (int e = lane; e < rem; e += 64) {
-    const int q = flushed + e;
-    if (q < cap) pa[cap - 1 - q] = lbuf[e];
-  }
+  flush();
   if (lane == 0) n_diag[b] = k;
 }
 
