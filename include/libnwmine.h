@@ -224,7 +224,9 @@ nwm_status nwm_plan_get_param(const nwm_plan *plan, nwm_param param, int32_t *va
 /* Record HIP events around every kernel the plan launches (0 = off).  While
  * on, nwm_plan_kernel_ms returns the summed device time per kernel class of
  * all launches since the last reset, measured on the launching stream:
- *   [0] expand (dictionary rows + tile lists)  [1] contraction + logistic
+ *   [0] expand (merged dictionary rows + source-side tile lists; the
+ *       target-side lists run concurrently on a second stream, untimed)
+ *   [1] contraction + logistic
  *   [2] NW fill                                [3] traceback + keep
  *   [4] backward.
  * `counts` receives launches per class.  Reading waits for the events. */

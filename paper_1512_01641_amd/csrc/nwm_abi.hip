@@ -99,6 +99,9 @@ struct nwm_plan {
   bool capturing = false;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  // second stream for the target-side tile lists (fork / join by events)
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<uint64_t> graph_key;
 };
 
@@ -395,6 +398,9 @@ void nwm_plan_destroy(nwm_plan *plan) {
   (void)hipSetDevice(plan->ctx->device);
   if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
   if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+  if (plan->aux_stream) (void)hipStreamDestroy(plan->aux_stream);
+  if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
+  if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
   if (plan->dmeta) (void)hipFree(plan->dmeta);
   delete plan;
 }
@@ -430,13 +436,27 @@ nwm_status nwm_score_pairs(nwm_plan *p, const nwm_batch *batch, const nwm_dict *
   const int pitch = bf16 ? PITCH_BF16 : PITCH_F32;
   const int esize = bf16 ? 2 : 4;
   {
+    // The target-side lists do not depend on the source side: they are built
+    // on the plan's second stream, forked from and joined back to `st` by
+    // events (under graph capture: a parallel branch of the graph).
+    if (!p->aux_stream) {
+      if (hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess)
+        return NWM_EDEVICE;
+    }
+    hipError_t e = hipEventRecord(p->ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->aux_stream, p->ev_fork, 0);
+    if (e == hipSuccess)
+      e = launch_build_b(p->dev, batch->tgt_off, batch->tgt_tok, b_list, b_choff, pitch, esize, p->aux_stream);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_join, p->aux_stream);
     Mark mk(p, K_EXPAND, st);
-    hipError_t e = launch_merge_src(p->n_src, batch->src_off, batch->src_tok, dict->row_off, dict->col, dict->val,
-                                    p->V, p->max_deg, p->max_entries, merged, cnt,
-                                    p->param[NWM_PARAM_MERGE_WAVES_PER_CU], st);
+    if (e == hipSuccess)
+      e = launch_merge_src(p->n_src, batch->src_off, batch->src_tok, dict->row_off, dict->col, dict->val, p->V,
+                           p->max_deg, p->max_entries, merged, cnt, p->param[NWM_PARAM_MERGE_WAVES_PER_CU], st);
     if (e == hipSuccess) e = launch_build_a(p->dev, batch->src_off, merged, cnt, a_list, a_choff, pitch, esize, st);
-    if (e == hipSuccess) e = launch_build_b(p->dev, batch->tgt_off, batch->tgt_tok, b_list, b_choff, pitch, esize, st);
     mk.done();
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_join, 0);
     if (e != hipSuccess) return NWM_EDEVICE;
   }
   Mark mk(p, K_SCORE, st);
