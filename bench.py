@@ -28,6 +28,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    2: "%d document pairs, sentence counts lognormal median 60 clipped 20-2000 (+-30%% skew), V=%d hashed vocab, "
+       "Zipf(1.1) tokens, BF16 contraction operands, FP32 DP, gap -0.2, threshold 0.5",
+    3: "%d document pairs of 5000x5000 sentences, V=%d hashed vocab, Zipf(1.1) tokens, BF16 contraction "
+       "operands, FP32 DP, gap -0.2, threshold 0.5",
+    5: "%d document pairs, sentence counts lognormal median 60 clipped 1-4000, 8%% empty-or-tiny sides, V=%d "
+       "hashed vocab, Zipf(1.05) tokens, BF16 contraction operands, FP32 DP, gap -0.2, threshold 0.5",
+}
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
 
 
@@ -90,6 +98,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--pairs", type=int, default=None, help="fewer pairs of the same workload (testing)")
+    ap.add_argument("--workload", type=int, choices=(2, 3, 5), default=2,
+                    help="2: 4096 pairs, lognormal median 60, V=4096 (the benchmark line); 3: 256 pairs of "
+                         "5000x5000, V=16384; 5: 100k pairs, lognormal median 60, V=16384")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
@@ -109,7 +120,7 @@ def main():
     import paper_1512_01641_amd as nw
     from synth import corpus
 
-    cfg = 2
+    cfg = args.workload
     _log("generating workload")
     batch = corpus.make_batch(cfg, pairs=args.pairs)
     B = batch.B
@@ -210,9 +221,7 @@ def main():
         "vs_baseline": None,
         "dtype": head,
         "data": "synthetic (seeded comparable-corpus generator with planted alignments)",
-        "config": {"workload": "%d document pairs, sentence counts lognormal median 60 clipped 20-2000 "
-                               "(+-30%% skew), V=%d hashed vocab, Zipf(1.1) tokens, BF16 contraction operands, "
-                               "FP32 DP, gap -0.2, threshold 0.5" % (B, V),
+        "config": {"workload": WORKLOADS[cfg] % (B, V),
                    "pairs": B, "cells": cells, "V": V},
         "gcups": round(gcups, 3),
         "launch": "eager" if args.no_graph else "hipGraph replay of the whole path per step",

@@ -21,8 +21,9 @@
 //             behind (bounded re-read).
 //             S is staged through an LDS ring whose slot index equals the step
 //             index (row r of column c lands in slot c + r), so every lane reads
-//             the same slot and one ds_read_b128 serves four steps; the ring is
-//             fed one 32-step group ahead through registers.  Each lane packs
+//             the same slot and one ds_read_b128 serves four steps; the ring
+//             holds two 32-step groups and is filled a group ahead by
+//             LDS-direct buffer loads (no register holds S).  Each lane packs
 //             its 2-bit directions, 16 steps per word, and every 64 steps the
 //             wave writes one coalesced 1 KiB block.  H never reaches HBM.
 // k_nw_reset  clears the published-row region and the queue; scores of
@@ -37,8 +38,8 @@
 
 namespace nwm {
 
-constexpr int RING = 64;              // ring slots (steps) per row
-constexpr int RPITCH = RING + 4;      // floats per ring row
+constexpr int PAIR_PITCH = 68;        // ring floats per row pair: 2 x 32 steps + 4 padding
+constexpr int HALF = 32 * PAIR_PITCH;  // ring floats per group of 32 steps (64 rows)
 constexpr int GROUP = 32;             // steps per S staging group
 constexpr int SPIN_LIMIT = 1 << 22;   // polls before a wave gives up (error flag)
 
@@ -62,9 +63,12 @@ static __device__ __forceinline__ T *uniform_ptr(T *p) {
   return reinterpret_cast<T *>(((uint64_t)hi << 32) | lo);
 }
 
-// Load the parallelogram of S used by steps [GROUP*q, GROUP*q + GROUP):
-// row r, columns GROUP*q - r + [0, GROUP); cells outside the strip read 0.
-// `rs` is a raw buffer over the strip's rows of S.
+// The parallelogram of S used by steps [GROUP*q, GROUP*q + GROUP): row r,
+// columns GROUP*q - r + [0, GROUP); cells outside the strip read 0.  It goes
+// straight from memory into ring half (q & 1) by LDS-direct buffer loads, one
+// per row pair (lanes 0..31 row 2k, lanes 32..63 row 2k + 1, one step each),
+// so row r of the half starts at float (r >> 1) * PAIR_PITCH + (r & 1) * 32
+// and step t of the group is float t of the row.  No register holds S.
 struct StripSrc {
   __amdgpu_buffer_rsrc_t rs;
   int m, rows;
@@ -76,39 +80,49 @@ static __device__ __forceinline__ bool group_interior(const StripSrc &src, int q
   return src.rows == 64 && q >= 2 && GROUP * q + GROUP <= src.m;
 }
 
-static __device__ __forceinline__ void load_group(float (&R)[GROUP], const StripSrc &src, int q, int lane) {
+typedef __attribute__((address_space(3))) void lds_void;
+constexpr uint32_t S_OOB = 0xFFFFFFF0u;   // a buffer offset past every strip: the load returns 0
+
+// One LDS-direct buffer load: lane l's dword at (voff + soff) of the strip
+// lands at LDS byte address lds + 4 l.  Written as one asm statement so that
+// the compiler neither reorders it with other memory accesses nor adds waits
+// for it: every read of the ring waits for it with an explicit vmcnt (below).
+// M0, which gives the LDS address, is restored afterwards.
+static __device__ __forceinline__ void s_to_lds(const StripSrc &src, const float *lds, uint32_t voff, int soff) {
+  const uint32_t la = (uint32_t)(uintptr_t)(lds_void *)lds;
+  uint32_t save;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %1\n\t"
+      "s_nop 0\n\t"
+      "buffer_load_dword %2, %3, %4 offen lds\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(save)
+      : "s"(la), "v"(voff), "s"(src.rs), "s"(soff)
+      : "memory");
+}
+
+static __device__ __forceinline__ void load_group(float *ring, const StripSrc &src, int q, int lane) {
+  float *dst = ring + (q & 1) * HALF;
   if (group_interior(src, q)) {
     int soff = GROUP * q * 4;
     const int step = (2 * src.m - 2) * 4;
 #pragma unroll
     for (int k = 0; k < GROUP; ++k) {
-      R[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(src.rs, src.lane_off, soff, 0));
+      s_to_lds(src, dst + k * PAIR_PITCH, (uint32_t)src.lane_off, soff);
       soff += step;
-      asm volatile("" : "+s"(soff));   // keep one running offset, not 32 live ones
     }
   } else {
-    // boundary group: load from a clamped in-range cell, then zero the
-    // cells outside the strip
     const int h = lane >> 5, cl = lane & (GROUP - 1);
 #pragma unroll
     for (int k = 0; k < GROUP; ++k) {
       const int row = 2 * k + h;
       const int c = GROUP * q + cl - row;
       const bool ok = row < src.rows && (unsigned)c < (unsigned)src.m;
-      const int rc = min(row, src.rows - 1);
-      const int cc = min(max(c, 0), src.m - 1);
-      const float v =
-          __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(src.rs, (rc * src.m + cc) * 4, 0, 0));
-      R[k] = ok ? v : 0.0f;
+      s_to_lds(src, dst + k * PAIR_PITCH, ok ? (uint32_t)(row * src.m + c) * 4u : S_OOB, 0);
       if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);   // bound the live offsets
     }
   }
-}
-
-static __device__ __forceinline__ void store_group(const float (&R)[GROUP], float *ring, int q, int lane) {
-  const int slot = (GROUP * q + (lane & (GROUP - 1))) & (RING - 1);
-#pragma unroll
-  for (int k = 0; k < GROUP; ++k) ring[(2 * k + (lane >> 5)) * RPITCH + slot] = R[k];
 }
 
 struct StripState {
@@ -127,7 +141,8 @@ static __device__ __forceinline__ void run16(StripState &st, const float *ring, 
   float4 sv[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q)
-    sv[q] = *reinterpret_cast<const float4 *>(ring + lane * RPITCH + ((t0 + 4 * q) & (RING - 1)));
+    sv[q] = *reinterpret_cast<const float4 *>(ring + ((t0 >> 5) & 1) * HALF + (lane >> 1) * PAIR_PITCH +
+                                               (lane & 1) * 32 + (t0 & 31) + 4 * q);
   float H = st.H, diag = st.diag, pw = st.pw, col = st.col;
   uint32_t bits = 0;
   int d = t0 - lane;   // column - 1 of this lane at the current step
@@ -187,10 +202,13 @@ __global__ __launch_bounds__(256) void k_nw_reset(FillArgs A, uint4 *__restrict_
 
 __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restrict__ S, float g,
                                                 float *__restrict__ score, char *__restrict__ tb,
-                                                uint64_t *__restrict__ bnd, int32_t *__restrict__ ctl) {
+                                                uint64_t *__restrict__ bnd, uint64_t *__restrict__ sink,
+                                                int32_t *__restrict__ ctl) {
   constexpr uint32_t epoch = 1u;   // tag of a published value (the reset clears to 0)
-  __shared__ __align__(16) float ring[64 * RPITCH];
+  __shared__ __align__(16) float ring[2 * HALF];
+  __shared__ __align__(16) uint64_t winbufA[64], winbufB[64];   // boundary windows (LDS-direct loads)
   const int lane = threadIdx.x;
+  uint64_t *my_sink = sink + (int64_t)(blockIdx.x & (FILL_SINK_WAVES - 1)) * 16;   // this wave's line
   for (;;) {
     int item = 0;
     if (lane == 0) item = atomicAdd(&ctl[0], 1);
@@ -207,7 +225,7 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     const int i0 = 64 * s;
     const int rows = min(64, n - i0);
     const float *Sb = S + A.s_off[b];
-    const int64_t mstride = (int64_t)m + BND_PAD;
+    const int64_t mstride = bnd_stride(m);
     const uint64_t *in_row = bnd + A.bnd_off[b] + (int64_t)(s - 1) * mstride;   // used when s > 0
     uint64_t *out_row = bnd + A.bnd_off[b] + (int64_t)s * mstride;               // used when !last
     const int nG = (m + 63 + 63) >> 6;
@@ -231,77 +249,132 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     st.col = 0.0f;
     st.bits = 0u;
     st.pw = 0.0f;
-    uint32_t w0 = 0u, w1 = 0u, w2 = 0u;
 
-    // S ring prologue: group 0 in the ring, group 1 in flight
-    float R[GROUP];
-#pragma nounroll
-    for (int q = 0; q < 2; ++q) {
-      load_group(R, src, q, lane);
-      if (q == 0) store_group(R, ring, 0, lane);
-    }
-    __builtin_amdgcn_wave_barrier();
+    // S ring prologue: groups 0 and 1 in flight
+    load_group(ring, src, 0, lane);
+    load_group(ring, src, 1, lane);
 
     // Boundary window prev[tw + 1 + lane]: the first row, or the previous
     // strip's last row published by another wave.  Every published value is
     // one 64-bit agent-coherent (sc1) store of (value, tag 1) into memory the
     // reset kernel cleared, so a consumer knows a value is there when its tag
-    // is set: no counters, no store drains and no cache flushes.  The window of the next chunk is
-    // loaded one chunk ahead and re-read (bounded) only if incomplete.
+    // is set: no counters, no store drains and no cache flushes.  Windows
+    // are prefetched two chunks ahead straight into LDS (16-byte agent-coherent
+    // LDS-direct loads, slots tw .. tw + 63), so no register holds a load in
+    // flight; the wait for one is an explicit vmcnt over the fixed sequence of
+    // memory operations of a group (below).
     auto load_window = [&](int tw) -> uint64_t {
       return __hip_atomic_load(in_row + tw + 1 + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    auto prefetch_window = [&](int tw, uint64_t *buf) {
+      if (lane < 32)
+        __builtin_amdgcn_global_load_lds((const void *)(in_row + tw + 2 * lane),
+                                         (__attribute__((address_space(3))) void *)buf, 16, 0, 16 /* sc1 */);
     };
     auto window_ready = [&](uint64_t v, int tw) -> bool {
       // lanes 0..15 feed the next 16 steps; columns beyond m are never used
       const bool need = lane < 16 && tw + 1 + lane <= m;
       return __ballot(need && (uint32_t)(v >> 32) != epoch) == 0;
     };
-    uint64_t wv = (s > 0) ? load_window(0) : 0ull;
-    for (int t0 = 0; t0 < T_pad; t0 += 16) {
-      if (s > 0) {
-        int spins = 0;
-        while (!window_ready(wv, t0)) {
-          if (++spins > SPIN_LIMIT) {
-            failed = true;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          wv = load_window(t0);
+    // the producer has not got this far yet: reload (bounded) until it has
+    auto wait_window = [&](int tw) -> uint64_t {
+      uint64_t v = 0ull;
+      int spins = 0;
+      do {
+        if (++spins > SPIN_LIMIT) {
+          failed = true;
+          break;
         }
-        st.pw = __uint_as_float((uint32_t)wv);
-        if (t0 + 16 < T_pad) wv = load_window(t0 + 16);
-      } else {
-        st.pw = (float)(t0 + 1 + lane) * g;
-      }
-      if (failed) break;
-
+        __builtin_amdgcn_s_sleep(1);
+        v = load_window(tw);
+      } while (!window_ready(v, tw));
+      return v;
+    };
+    // One chunk of 16 steps from its boundary window.  The publish of the
+    // strip's last row is one unconditional store (lanes with nothing to
+    // publish write the wave's own sink line), so every chunk issues the same
+    // memory operations and the explicit wait counts stay exact.
+    auto chunk = [&](int t0, uint64_t win) {
+      st.pw = s > 0 ? __uint_as_float((uint32_t)win) : (float)(t0 + 1 + lane) * g;
       if (t0 < 64 || t0 + 16 > m) run16<true>(st, ring, t0, m, g, lane);
       else run16<false>(st, ring, t0, m, g, lane);
+      // lane l of the collector holds H of row 64 at step t0 + 15 - 63 + l,
+      // i.e. column t0 - 110 + l; lanes 48.. publish
+      const int j = t0 - 110 + lane;
+      const bool pub = !last && lane >= 48 && j >= 1 && j <= m;
+      uint64_t *dst = pub ? out_row + j : my_sink + (lane & 15);
+      __hip_atomic_store(dst, ((uint64_t)epoch << 32) | __float_as_uint(st.col), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      return st.bits;
+    };
 
-      const int t_last = t0 + 15;
-      // direction words: 4 per 64-step block, one coalesced store per block
-      const int kword = (t0 >> 4) & 3;
-      if (kword == 0) w0 = st.bits;
-      else if (kword == 1) w1 = st.bits;
-      else if (kword == 2) w2 = st.bits;
-      if (kword == 3 || t0 + 16 >= T_pad) tbs[(int64_t)(t0 >> 6) * 64 + lane] = make_uint4(w0, w1, w2, st.bits);
-      // publish the strip's last row: lane l of the collector holds H of row
-      // 64 at step t_last - 63 + l, i.e. column t_last - 125 + l
-      if (!last) {
-        const int j = t_last - 125 + lane;
-        if (lane >= 48 && j >= 1 && j <= m)
-          __hip_atomic_store(out_row + j, ((uint64_t)epoch << 32) | __float_as_uint(st.col), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+    // Two chunks (one group of 32 steps) per iteration, in a fixed order of
+    // memory operations: [chunk A: window of the next group's A, publish]
+    // [chunk B: window of the next group's B, publish] [direction words of
+    // the group: one 8-byte store, half of the block's 16-byte word] [S of
+    // the group after next: 32 loads into the half just consumed].  A window
+    // is therefore followed by exactly 36 memory operations when its chunk
+    // comes (1 and 2 in the first group, whose windows the prologue issued
+    // last), which is the vmcnt it waits for.  The window of chunk A was
+    // issued after the S of its group, so its wait also covers the ring;
+    // without windows (first strip) the ring's own wait is 35 operations (32
+    // in the first group).  A drained counter (after a reload) only makes a
+    // wait shorter.
+    if (s > 0) {
+      prefetch_window(0, winbufA);
+      prefetch_window(16, winbufB);
+    }
+    uint2 *tbh = reinterpret_cast<uint2 *>(tbs);
+    int t0 = 0;
+    bool first = true;
+    auto take_window = [&](int tw, const uint64_t *buf, int ahead) -> uint64_t {
+      // ahead: memory operations issued after this window's load
+      if (ahead == 36) asm volatile("s_waitcnt vmcnt(36)" ::: "memory");
+      else if (ahead == 2) asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
+      else asm volatile("s_waitcnt vmcnt(1)" ::: "memory");
+      uint64_t v = buf[1 + lane];   // slot tw + 1 + lane (lanes 0..15 matter)
+      if (!window_ready(v, tw)) v = wait_window(tw);
+      return v;
+    };
+    // the ring half of the group at t0 has landed (chunk A of a group)
+    auto take_group = [&]() -> uint64_t {
+      if (s > 0) return take_window(t0, winbufA, first ? 1 : 36);
+      if (first) asm volatile("s_waitcnt vmcnt(32)" ::: "memory");
+      else asm volatile("s_waitcnt vmcnt(35)" ::: "memory");
+      return 0ull;
+    };
+    for (; t0 + 32 <= T_pad; t0 += 32) {
+      uint64_t wb = 0ull;
+      const uint64_t wa = take_group();
+      if (s > 0) {
+        __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the slot is read before it is refilled
+        prefetch_window(t0 + 32, winbufA);
       }
-      // S ring: after the second chunk of group q, group q+1 (loaded one
-      // group ago) enters the ring and the registers start loading group q+2
-      if ((t0 & (GROUP - 1)) == 16 && t0 + 16 < T_pad) {
-        const int q = t0 / GROUP;
-        store_group(R, ring, q + 1, lane);
-        load_group(R, src, q + 2, lane);
-        __builtin_amdgcn_wave_barrier();
+      if (failed) break;
+      const uint32_t bitsA = chunk(t0, wa);
+      if (s > 0) {
+        wb = take_window(t0 + 16, winbufB, first ? 2 : 36);
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        prefetch_window(t0 + 48, winbufB);
+      }
+      if (failed) break;
+      const uint32_t bitsB = chunk(t0 + 16, wb);
+      tbh[((t0 >> 6) * 64 + lane) * 2 + ((t0 >> 5) & 1)] = make_uint2(bitsA, bitsB);
+      // every ring read of this group has returned (lgkmcnt(0)) before its
+      // half is refilled with the group after next
+      __builtin_amdgcn_s_waitcnt(0xc07f);
+      load_group(ring, src, t0 / GROUP + 2, lane);
+      first = false;
+    }
+    if (t0 < T_pad && !failed) {   // a last single chunk
+      const uint64_t wa = take_group();
+      if (!failed) {
+        const uint32_t bitsA = chunk(t0, wa);
+        tbh[((t0 >> 6) * 64 + lane) * 2 + ((t0 >> 5) & 1)] = make_uint2(bitsA, 0u);
       }
     }
+    // no LDS-direct load may still be writing LDS when the next item starts
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     if (last) {
       // lane r_last stopped updating after column m: it holds H[n][m]
       const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(st.H), r_last));
@@ -531,7 +604,9 @@ hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *scor
   const int per = (waves_per_cu > 0 && waves_per_cu < g_fill_per) ? waves_per_cu : g_fill_per;
   const int full = g_fill_cus * per;
   const int grid = P.n_items < full ? P.n_items : full;
-  hipLaunchKernelGGL(k_nw_fill, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, ctl);
+  // the sink: FILL_SINK_WAVES 128-byte lines after the published rows
+  uint64_t *sink = reinterpret_cast<uint64_t *>((reinterpret_cast<uintptr_t>(bnd + n_bnd) + 127) & ~(uintptr_t)127);
+  hipLaunchKernelGGL(k_nw_fill, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, sink, ctl);
   return hipGetLastError();
 }
 

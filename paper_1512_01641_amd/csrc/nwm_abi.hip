@@ -261,7 +261,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   for (int b = 0; b < B; ++b) {
     const int64_t ns = (p->n[b] > 0 && p->m[b] > 0) ? (p->n[b] + 63) / 64 : 0;
     const int64_t links = ns > 0 ? ns - 1 : 0;
-    bnd_off[b + 1] = bnd_off[b] + links * ((int64_t)p->m[b] + BND_PAD);
+    bnd_off[b + 1] = bnd_off[b] + links * bnd_stride(p->m[b]);
   }
   // the pairs whose strip chain is within 2x of the longest one run their
   // strips at raised wave priority: that chain bounds the DP's duration
@@ -369,7 +369,8 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   W.b_list = carve(4 * ((size_t)p->tgt_tokens + LIST_SLACK_B));
   W.b_choff = carve(4 * (size_t)D.n_ct * (size_t)(nch + 1));
   W.bwd = carve(16 * ((size_t)B + (size_t)D.n_rt));
-  W.bnd = carve(8 * (size_t)bnd_off[B] + 16);   // + 16: cleared in 16-byte units
+  // published rows, + 2 entries (cleared in 16-byte units), + the sink
+  W.bnd = carve(8 * ((size_t)bnd_off[B] + 2 + FILL_SINK_SLOTS));
   p->n_bnd = bnd_off[B] + 2;
   W.ctl = carve(8);
   W.total = o;
