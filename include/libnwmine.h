@@ -197,7 +197,8 @@ nwm_status nwm_plan_set_graph(nwm_plan *plan, int on);
 
 /* --- launch parameters (for the autotuner) ------------------------------------ */
 
-/* Launch shapes that do not change any result, only the time:
+/* Launch shapes that do not change any result, only the time (all but
+ * SCORE_COMPACT):
  *   NWM_PARAM_FILL_WAVES_PER_CU   persistent DP waves per compute unit
  *                                 (0 = as many as fit; default 0)
  *   NWM_PARAM_MERGE_WAVES_PER_CU  dictionary-merge waves per compute unit
@@ -207,6 +208,12 @@ nwm_status nwm_plan_set_graph(nwm_plan *plan, int on);
  *   NWM_PARAM_DP_HOT_PERCENT      DP strips of pairs whose dependency chain is
  *                                 at least this percent of the longest one run
  *                                 at raised wave priority (0 = never; default 50)
+ *   NWM_PARAM_SCORE_COMPACT       1 = the contraction of each 64 x 64 tile runs
+ *                                 over the words of its 64 target sentences
+ *                                 only (the other words have a zero Y factor);
+ *                                 0 = over the whole vocabulary.  Default 1.
+ *                                 The FP32 sums are taken in another order, so
+ *                                 S may differ in the last bits.
  * Out-of-range values give NWM_EINVAL.  Setting DP_HOT_PERCENT uploads the
  * plan's work list (synchronous).  A graph captured by nwm_mine is captured
  * again after any change. */
@@ -214,7 +221,8 @@ typedef enum {
   NWM_PARAM_FILL_WAVES_PER_CU = 0,
   NWM_PARAM_MERGE_WAVES_PER_CU = 1,
   NWM_PARAM_SCORE_XCD_MAP = 2,
-  NWM_PARAM_DP_HOT_PERCENT = 3
+  NWM_PARAM_DP_HOT_PERCENT = 3,
+  NWM_PARAM_SCORE_COMPACT = 4
 } nwm_param;
 nwm_status nwm_plan_set_param(nwm_plan *plan, nwm_param param, int32_t value);
 nwm_status nwm_plan_get_param(const nwm_plan *plan, nwm_param param, int32_t *value);

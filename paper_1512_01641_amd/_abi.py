@@ -18,7 +18,8 @@ SYMBOLS = ["nwm_create", "nwm_destroy", "nwm_strerror", "nwm_plan_create", "nwm_
            "nwm_plan_set_graph", "nwm_plan_set_param", "nwm_plan_get_param", "nwm_plan_set_timing",
            "nwm_plan_kernel_ms"]
 
-PARAMS = {"fill_waves_per_cu": 0, "merge_waves_per_cu": 1, "score_xcd_map": 2, "dp_hot_percent": 3}
+PARAMS = {"fill_waves_per_cu": 0, "merge_waves_per_cu": 1, "score_xcd_map": 2, "dp_hot_percent": 3,
+          "score_compact": 4}
 
 P = ctypes.c_void_p
 

@@ -265,10 +265,17 @@ static __device__ void block_exclusive_scan(int *vals, int len, int *tmp) {
 // Rows handled by one wave of a 256-thread tile builder: w, w+4, ... (<= 16).
 constexpr int ROWS_PER_WAVE = TM / 4;
 
+// Entry encoding: dense contraction -- the LDS byte offset of (row, word %
+// KC) in the operand tile; compacted contraction (compact != 0) -- word << 6 |
+// row, placed by the contraction once it knows the column tile's vocabulary.
+static __device__ __forceinline__ uint32_t a_code(uint32_t u, int r, int pitch, int esize, int compact) {
+  return compact ? (u << 6) | (uint32_t)r : (uint32_t)((r * pitch + (int)(u % KC)) * esize);
+}
+
 __global__ __launch_bounds__(256) void k_build_a(PlanDev P, const int64_t *__restrict__ src_off,
                                                  const uint2 *__restrict__ merged,
                                                  const int32_t *__restrict__ cnt, uint2 *__restrict__ a_list,
-                                                 int32_t *__restrict__ a_choff, int pitch, int esize) {
+                                                 int32_t *__restrict__ a_choff, int pitch, int esize, int compact) {
   extern __shared__ __align__(16) char smem[];
   int *off = reinterpret_cast<int *>(smem);  // [nch + 1]
   int *tmp = off + P.nch + 1;                // [256]
@@ -315,7 +322,7 @@ __global__ __launch_bounds__(256) void k_build_a(PlanDev P, const int64_t *__res
       const uint2 ent = e[k][q];
       if (ent.x != 0xFFFFFFFFu) {
         const int pos = atomicAdd(&off[ent.x / KC], 1);
-        a_list[tile_base + pos] = make_uint2((uint32_t)((r * pitch + (int)(ent.x % KC)) * esize), ent.y);
+        a_list[tile_base + pos] = make_uint2(a_code(ent.x, r, pitch, esize, compact), ent.y);
       }
     }
     const int c = __shfl(rc, k, 64);
@@ -323,20 +330,30 @@ __global__ __launch_bounds__(256) void k_build_a(PlanDev P, const int64_t *__res
     for (int x = 128 + lane; x < c; x += 64) {
       const uint2 ent = merged[base + x];
       const int pos = atomicAdd(&off[ent.x / KC], 1);
-      a_list[tile_base + pos] = make_uint2((uint32_t)((r * pitch + (int)(ent.x % KC)) * esize), ent.y);
+      a_list[tile_base + pos] = make_uint2(a_code(ent.x, r, pitch, esize, compact), ent.y);
     }
   }
 }
 
+// Compacted contraction (compact != 0): the column tile's vocabulary W (the
+// distinct words of its sentences, ascending) numbers the K positions, so the
+// contraction only walks ceil(|W| / KC) chunks.  Per global chunk c of KC
+// words the builder writes mt[c] = {bit mask of W's words in c, |W| words in
+// chunks before c}: the compacted position of word u is then
+// mt[u/KC].base + popcount(mt[u/KC].mask below bit u%KC).  The B entries are
+// grouped by compacted chunk and encoded at their compacted position.
 __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__restrict__ tgt_off,
                                                  const int32_t *__restrict__ tgt_tok,
                                                  uint32_t *__restrict__ b_list, int32_t *__restrict__ b_choff,
-                                                 int pitch, int esize) {
+                                                 int pitch, int esize, int compact, uint2 *__restrict__ mt,
+                                                 int32_t *__restrict__ kcn) {
   extern __shared__ __align__(16) char smem[];
   int *off = reinterpret_cast<int *>(smem);        // [nch + 1]
   int *tmp = off + P.nch + 1;                      // [256]
   uint32_t *bits = reinterpret_cast<uint32_t *>(tmp + 256);  // 4 waves x [V/32]
   const int words = (P.V + 31) / 32;
+  int *ubase = reinterpret_cast<int *>(bits + 4 * words);    // [words + 1] (compact)
+  uint32_t *ubits = reinterpret_cast<uint32_t *>(ubase + words + 1);   // [words] (compact)
   const int ct = blockIdx.x;
   const int pair = P.ct_pair[ct];
   const int cols = P.ct_cols[ct];
@@ -345,6 +362,8 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
   uint32_t *mybits = bits + wave * words;
   for (int c = threadIdx.x; c <= P.nch; c += 256) off[c] = 0;
   for (int w = lane; w < words; w += 64) mybits[w] = 0u;
+  if (compact)
+    for (int w = threadIdx.x; w < words; w += 256) ubits[w] = 0u;
   // sentences of this wave: lane k fetches sentence wave + 4k's token range,
   // then the first 64 tokens of every sentence are loaded together
   const int mycol = wave + 4 * lane;
@@ -359,6 +378,41 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
     tok[k] = lane < l ? (uint32_t)tgt_tok[a + lane] : 0xFFFFFFFFu;
   }
   __syncthreads();
+  if (compact) {
+    // the tile's vocabulary: union of its sentences' words, then the
+    // compacted position base of every chunk
+#pragma unroll
+    for (int k = 0; k < ROWS_PER_WAVE; ++k) {
+      const uint32_t u = tok[k];
+      if (u < (uint32_t)P.V) atomicOr(&ubits[u >> 5], 1u << (u & 31));
+      const int64_t a = __shfl(q0, k, 64);
+      const int l = __shfl(ql, k, 64);
+      for (int x = 64 + lane; x < l; x += 64) {
+        const uint32_t v = (uint32_t)tgt_tok[a + x];
+        if (v < (uint32_t)P.V) atomicOr(&ubits[v >> 5], 1u << (v & 31));
+      }
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < words; w += 256) ubase[w] = __popc(ubits[w]);
+    __syncthreads();
+    block_exclusive_scan(ubase, words, tmp);
+    for (int w = threadIdx.x; w < words; w += 256)
+      mt[(int64_t)ct * words + w] = make_uint2(ubits[w], (uint32_t)ubase[w]);
+    if (threadIdx.x == 0) kcn[ct] = (ubase[words] + KC - 1) / KC;
+    __syncthreads();
+  }
+  // K chunk and position inside it of word u
+  auto kchunk = [&](uint32_t u) -> int {
+    if (!compact) return (int)(u / KC);
+    const uint32_t w = u >> 5, bit = u & 31;
+    return (ubase[w] + __popc(ubits[w] & ((1u << bit) - 1u))) / KC;
+  };
+  auto kcode = [&](uint32_t u, int r) -> uint32_t {
+    if (!compact) return (uint32_t)((r * pitch + (int)(u % KC)) * esize);
+    const uint32_t w = u >> 5, bit = u & 31;
+    const int pos = ubase[w] + __popc(ubits[w] & ((1u << bit) - 1u));
+    return (uint32_t)((r * pitch + pos % KC) * esize);
+  };
   // pass 1: distinct tokens of each sentence (first occurrence per word),
   // counted by chunk; first occurrences are remembered for pass 2
   uint32_t first = 0u;   // bit k: this lane's token of sentence k is a first occurrence
@@ -368,7 +422,7 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
       const uint32_t bit = 1u << (u & 31);
       if (!(atomicOr(&mybits[u >> 5], bit) & bit)) {
         first |= 1u << k;
-        atomicAdd(&off[u / KC], 1);
+        atomicAdd(&off[kchunk(u)], 1);
       }
     }
     const int64_t a = __shfl(q0, k, 64);
@@ -377,7 +431,7 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
       const uint32_t v = (uint32_t)tgt_tok[a + x];
       if (v < (uint32_t)P.V) {
         const uint32_t bit = 1u << (v & 31);
-        if (!(atomicOr(&mybits[v >> 5], bit) & bit)) atomicAdd(&off[v / KC], 1);
+        if (!(atomicOr(&mybits[v >> 5], bit) & bit)) atomicAdd(&off[kchunk(v)], 1);
       }
     }
     wave_sync();
@@ -398,8 +452,8 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
     const int r = wave + 4 * k;
     if (first & (1u << k)) {
       const uint32_t u = tok[k];
-      const int pos = atomicAdd(&off[u / KC], 1);
-      b_list[tile_base + pos] = (uint32_t)((r * pitch + (int)(u % KC)) * esize);
+      const int pos = atomicAdd(&off[kchunk(u)], 1);
+      b_list[tile_base + pos] = kcode(u, r);
     }
     const int64_t a = __shfl(q0, k, 64);
     const int l = __shfl(ql, k, 64);
@@ -412,8 +466,8 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
         if (v < (uint32_t)P.V) {
           const uint32_t bit = 1u << (v & 31);
           if (!(atomicOr(&mybits[v >> 5], bit) & bit)) {
-            const int pos = atomicAdd(&off[v / KC], 1);
-            b_list[tile_base + pos] = (uint32_t)((r * pitch + (int)(v % KC)) * esize);
+            const int pos = atomicAdd(&off[kchunk(v)], 1);
+            b_list[tile_base + pos] = kcode(v, r);
           }
         }
       }
@@ -466,21 +520,31 @@ hipError_t launch_merge_src(int64_t n_sent, const int64_t *src_off, const int32_
 }
 
 hipError_t launch_build_a(const PlanDev &P, const int64_t *src_off, const uint2 *merged, const int32_t *cnt,
-                          uint2 *a_list, int32_t *a_choff, int pitch, int esize, hipStream_t st) {
+                          uint2 *a_list, int32_t *a_choff, int pitch, int esize, int compact, hipStream_t st) {
   if (P.n_rt <= 0) return hipSuccess;
   const size_t lds = sizeof(int) * (size_t)(P.nch + 1 + 256);
   hipLaunchKernelGGL(k_build_a, dim3(P.n_rt), dim3(256), lds, st, P, src_off, merged, cnt, a_list, a_choff,
-                     pitch, esize);
+                     pitch, esize, compact);
   return hipGetLastError();
 }
 
+size_t build_b_lds_bytes(int nch, int V) {
+  const size_t words = (size_t)((V + 31) / 32);
+  return sizeof(int) * (size_t)(nch + 1 + 256) + sizeof(uint32_t) * (4 * words + 2 * words + 1);
+}
+
 hipError_t launch_build_b(const PlanDev &P, const int64_t *tgt_off, const int32_t *tgt_tok, uint32_t *b_list,
-                          int32_t *b_choff, int pitch, int esize, hipStream_t st) {
+                          int32_t *b_choff, int pitch, int esize, int compact, uint2 *mt, int32_t *kcn,
+                          hipStream_t st) {
   if (P.n_ct <= 0) return hipSuccess;
-  const size_t lds = sizeof(int) * (size_t)(P.nch + 1 + 256) + sizeof(uint32_t) * 4 * (size_t)((P.V + 31) / 32);
-  hipLaunchKernelGGL(k_build_b, dim3(P.n_ct), dim3(256), lds, st, P, tgt_off, tgt_tok, b_list, b_choff, pitch,
-                     esize);
+  hipLaunchKernelGGL(k_build_b, dim3(P.n_ct), dim3(256), build_b_lds_bytes(P.nch, P.V), st, P, tgt_off, tgt_tok,
+                     b_list, b_choff, pitch, esize, compact, mt, kcn);
   return hipGetLastError();
+}
+
+hipError_t build_set_attrs(int nch, int V) {
+  return hipFuncSetAttribute((const void *)k_build_b, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)build_b_lds_bytes(nch, V));
 }
 
 hipError_t merge_set_attrs(int max_entries) {

@@ -272,6 +272,93 @@ struct ScoreLds {
   static constexpr int BYTES = OPS > RED ? OPS : RED;
 };
 
+// Epilogue of a tile: accumulators -> LDS (transpose) -> per row the
+// logistic scorer and coalesced stores of S (and S_raw).
+static __device__ __forceinline__ void score_epilogue(const f32x4 (&acc)[4][4], float *red, const PlanDev &P,
+                                                      const int64_t *__restrict__ src_off,
+                                                      const int64_t *__restrict__ tgt_off, const nwm_scorer &sc,
+                                                      float *__restrict__ S, float *__restrict__ S_raw, int pair,
+                                                      int row0, int rows, int col0, int cols, int64_t s_first,
+                                                      int64_t t_first, int m, int lane) {
+  constexpr int RP = TN + 1;
+  const int r16 = lane & 15, rq = lane >> 4;
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[(16 * bi + 4 * rq + r) * RP + 16 * bj + r16] = acc[bi][bj][r];
+  wave_sync();
+  const int col = lane;
+  const bool vcol = col < cols;
+  const float lt = vcol ? (float)(tgt_off[t_first + col + 1] - tgt_off[t_first + col]) : 0.0f;
+  float *Sp = S + P.s_off[pair];
+  float *Rp = S_raw ? S_raw + P.s_off[pair] : nullptr;
+  const float LOG2E = 1.4426950408889634f;
+  for (int row = 0; row < rows; ++row) {
+    const float dot = red[row * RP + col];
+    const float ls = (float)(src_off[s_first + row + 1] - src_off[s_first + row]);
+    // S_raw = dot / l_i (0 for an empty sentence); rho = min / max of lengths
+    const float sraw = ls > 0.0f ? dot * __builtin_amdgcn_rcpf(ls) : 0.0f;
+    const float mx = fmaxf(ls, lt);
+    const float rho = mx > 0.0f ? fminf(ls, lt) * __builtin_amdgcn_rcpf(mx) : 1.0f;
+    const float z = __builtin_fmaf(sc.w0, sraw, __builtin_fmaf(sc.w1, rho, sc.b));
+    // sigmoid in the overflow-free form: e = exp(-|z|), S = 1/(1+e) or e/(1+e)
+    const float e = __builtin_amdgcn_exp2f(-fabsf(z) * LOG2E);
+    const float inv = __builtin_amdgcn_rcpf(1.0f + e);
+    const float sv = z >= 0.0f ? inv : e * inv;
+    if (vcol) {
+      const int64_t o = (int64_t)(row0 + row) * m + col0 + col;
+      Sp[o] = sv;
+      if (Rp) Rp[o] = sraw;
+    }
+  }
+}
+
+// Epilogue straight from the accumulators (no LDS): lane l holds rows
+// 16 bi + 4 (l >> 4) + r, column 16 bj + (l & 15) of the tile.  Sentence
+// lengths come from the lane that owns that row / column index.
+static __device__ __forceinline__ void score_epilogue_regs(const f32x4 (&acc)[4][4], const PlanDev &P,
+                                                           const int64_t *__restrict__ src_off,
+                                                           const int64_t *__restrict__ tgt_off, const nwm_scorer &sc,
+                                                           float *__restrict__ S, float *__restrict__ S_raw, int pair,
+                                                           int row0, int rows, int col0, int cols, int64_t s_first,
+                                                           int64_t t_first, int m, int lane) {
+  const float my_ls = lane < rows ? (float)(src_off[s_first + lane + 1] - src_off[s_first + lane]) : 0.0f;
+  const float my_lt = lane < cols ? (float)(tgt_off[t_first + lane + 1] - tgt_off[t_first + lane]) : 0.0f;
+  float *Sp = S + P.s_off[pair] + (int64_t)row0 * m + col0;
+  float *Rp = S_raw ? S_raw + P.s_off[pair] + (int64_t)row0 * m + col0 : nullptr;
+  const float LOG2E = 1.4426950408889634f;
+  const int r16 = lane & 15, rq = lane >> 4;
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj) {
+    const int col = 16 * bj + r16;
+    const float lt = __shfl(my_lt, col, 64);
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * bi + 4 * rq + r;
+        const float ls = __shfl(my_ls, row, 64);
+        const float dot = acc[bi][bj][r];
+        // S_raw = dot / l_i (0 for an empty sentence); rho = min / max of lengths
+        const float sraw = ls > 0.0f ? dot * __builtin_amdgcn_rcpf(ls) : 0.0f;
+        const float mx = fmaxf(ls, lt);
+        const float rho = mx > 0.0f ? fminf(ls, lt) * __builtin_amdgcn_rcpf(mx) : 1.0f;
+        const float z = __builtin_fmaf(sc.w0, sraw, __builtin_fmaf(sc.w1, rho, sc.b));
+        // sigmoid in the overflow-free form: e = exp(-|z|), S = 1/(1+e) or e/(1+e)
+        const float e = __builtin_amdgcn_exp2f(-fabsf(z) * LOG2E);
+        const float inv = __builtin_amdgcn_rcpf(1.0f + e);
+        const float sv = z >= 0.0f ? inv : e * inv;
+        if (row < rows && col < cols) {
+          const int64_t o = (int64_t)row * m + col;
+          Sp[o] = sv;
+          if (Rp) Rp[o] = sraw;
+        }
+      }
+  }
+}
+
 template <bool BF16>
 __global__ __launch_bounds__(64) void k_score(PlanDev P, const int64_t *__restrict__ src_off,
                                               const int64_t *__restrict__ tgt_off, const uint2 *__restrict__ a_list,
@@ -388,40 +475,217 @@ __global__ __launch_bounds__(64) void k_score(PlanDev P, const int64_t *__restri
 #undef NWM_SCORE_CHUNK
   wave_sync();
 
-  // ---- epilogue: accumulators -> LDS (transpose) -> coalesced rows ---------
-  constexpr int RP = TN + 1;
-  const int r16 = lane & 15, rq = lane >> 4;
+  score_epilogue(acc, red, P, src_off, tgt_off, sc, S, S_raw, pair, row0, rows, col0, cols, s_first, t_first, m,
+                 lane);
+}
+
+// ---- compacted contraction -------------------------------------------------------
+// The same tile contraction with K restricted to the column tile's vocabulary
+// W (built by k_build_b in compact mode): a word outside W has a zero Y
+// factor in every column of the tile, so the sum over W equals the sum over
+// the whole vocabulary.  Compacted chunk kc holds W's words KC kc ..
+// KC kc + KC - 1; the A entries that can land in it are those of the global
+// chunks c_lo(kc) .. c_hi(kc) those words span, one contiguous range of the
+// row tile's chunk-major A list.  Each entry (word u, row r, value) is looked
+// up in the column tile's chunk table staged in LDS and, when u is in W at a
+// position of chunk kc, written to the dense A tile; entries of a global
+// chunk that straddles two compacted chunks are read for both.  B entries
+// come pre-encoded at their compacted positions.  The entries of chunk kc + 1
+// are loaded while chunk kc is scattered and multiplied; the tiles are
+// cleared whole after their fragments are read.
+struct CChunk {
+  uint2 a[CREG_A];     // {word << 6 | row, FP32 value bits}
+  uint32_t b[CREG_B];  // LDS byte offset in the B tile
+  int a0, na, b0, nb;
+};
+
+// Lane l: A range [a0, a1) and B range [b0, b1) of compacted chunk base + l.
+struct CWin {
+  int base;
+  int a0, a1, b0, b1;
+};
+
+template <bool BF16>
+struct ScoreLdsC {
+  static constexpr int OPS = 2 * ScoreLds<BF16>::TILE;   // [A, B]
+  static constexpr int BYTES = OPS;
+};
+
+static __device__ __forceinline__ void cwin_load(CWin &W, int base, int Kc, const int2 *rng,
+                                                 const int32_t *__restrict__ chA, const int32_t *__restrict__ chB,
+                                                 int lane) {
+  W.base = base;
+  const int kc = base + lane;
+  W.a0 = W.a1 = W.b0 = W.b1 = 0;
+  if (kc < Kc) {
+    const int2 r = rng[kc];
+    W.a0 = chA[r.x];
+    W.a1 = chA[r.y + 1];
+    W.b0 = chB[kc];
+    W.b1 = chB[kc + 1];
+  }
+}
+
+static __device__ __forceinline__ void cload(CChunk &C, const uint2 *pa, const uint32_t *pb, const CWin &W, int kc,
+                                             int lane) {
+  // the chunk after a full window's last one loads an empty range
+  const int k = kc - W.base;
+  const bool in = k < 64;
+  const int kk = in ? k : 63;
+  C.a0 = __builtin_amdgcn_readlane(W.a0, kk);
+  C.na = in ? __builtin_amdgcn_readlane(W.a1, kk) - C.a0 : 0;
+  C.b0 = __builtin_amdgcn_readlane(W.b0, kk);
+  C.nb = in ? __builtin_amdgcn_readlane(W.b1, kk) - C.b0 : 0;
+  // unconditional: reads past the last list stay inside its slack
+  const uint2 *a = pa + C.a0;
+  const uint32_t *b = pb + C.b0;
+#pragma unroll
+  for (int q = 0; q < CREG_A; ++q) C.a[q] = a[q * 64 + lane];
+#pragma unroll
+  for (int q = 0; q < CREG_B; ++q) C.b[q] = b[q * 64 + lane];
+}
+
+// The A entries of compacted chunk kc into the dense A tile.  Register
+// entries first, branch-free: every lane looks its CREG_A words up in the
+// chunk table at once (lanes past the count look up word 0) and writes each
+// entry either at its compacted position or, when its word is not in the
+// chunk, to the shared padding element `junk`.  Entries past the registers
+// (rare) follow from the list.
+template <bool BF16>
+static __device__ __forceinline__ void cscatter(const CChunk &C, char *At, char *Bt, const uint2 *mtl,
+                                                const uint2 *pa, const uint32_t *pb, int kc, int lane,
+                                                uint32_t junk) {
+  typedef typename Op<BF16>::T T;
+  constexpr uint32_t P = (uint32_t)Op<BF16>::PITCH;
+  uint2 mm[CREG_A];
+#pragma unroll
+  for (int q = 0; q < CREG_A; ++q) {
+    const uint32_t u = lane + 64 * q < C.na ? C.a[q].x >> 6 : 0u;
+    mm[q] = mtl[u >> 5];
+  }
+#pragma unroll
+  for (int q = 0; q < CREG_A; ++q) {
+    const uint32_t x = C.a[q].x, u = x >> 6, bit = u & 31u;
+    const uint32_t pos = mm[q].y + (uint32_t)__popc(mm[q].x & ((1u << bit) - 1u));
+    const bool hit = lane + 64 * q < C.na && ((mm[q].x >> bit) & 1u) && (pos >> 5) == (uint32_t)kc;
+    const uint32_t o = hit ? ((x & 63u) * P + (pos & 31u)) * (uint32_t)sizeof(T) : junk;
+    lds_put<T>(At, o, T(__uint_as_float(C.a[q].y)));
+  }
+  for (int e = CREG_A * 64 + lane; e < C.na; e += 64) {
+    const uint2 v = pa[C.a0 + e];
+    const uint32_t u = v.x >> 6, bit = u & 31u;
+    const uint2 w = mtl[u >> 5];
+    const uint32_t pos = w.y + (uint32_t)__popc(w.x & ((1u << bit) - 1u));
+    if (((w.x >> bit) & 1u) && (pos >> 5) == (uint32_t)kc)
+      lds_put<T>(At, ((v.x & 63u) * P + (pos & 31u)) * (uint32_t)sizeof(T), T(__uint_as_float(v.y)));
+  }
+#pragma unroll
+  for (int q = 0; q < CREG_B; ++q) lds_put<T>(Bt, lane + 64 * q < C.nb ? C.b[q] : junk, T(1.0f));
+  for (int e = CREG_B * 64 + lane; e < C.nb; e += 64) lds_put<T>(Bt, pb[C.b0 + e], T(1.0f));
+}
+
+template <bool BF16>
+__global__ __launch_bounds__(64) void k_score_c(PlanDev P, const int64_t *__restrict__ src_off,
+                                                const int64_t *__restrict__ tgt_off,
+                                                const uint2 *__restrict__ a_list, const int32_t *__restrict__ a_choff,
+                                                const uint32_t *__restrict__ b_list,
+                                                const int32_t *__restrict__ b_choff, const uint2 *__restrict__ mt,
+                                                const int32_t *__restrict__ kcn, nwm_scorer sc,
+                                                float *__restrict__ S, float *__restrict__ S_raw, int xcd_map) {
+  constexpr int TB = ScoreLds<BF16>::TILE;
+  __shared__ __align__(16) char smem[ScoreLdsC<BF16>::BYTES];   // [A tile, B tile]
+  extern __shared__ __align__(16) uint2 dyn[];                  // chunk table [nch], chunk ranges [nch]
+  char *At = smem, *Bt = smem + TB;
+
+  const int G = P.n_gt;
+  const int per = (G + 7) >> 3;
+  const int gt = xcd_map ? (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
+  if (gt >= G) return;
+  const int rt = P.gt_rt[gt], ct = P.gt_ct[gt];
+  const int pair = P.rt_pair[rt];
+  const int row0 = P.rt_row0[rt], rows = P.rt_rows[rt];
+  const int col0 = P.ct_col0[ct], cols = P.ct_cols[ct];
+  const int64_t s_first = P.sfirst[pair] + row0;
+  const int64_t t_first = P.tfirst[pair] + col0;
+  const int m = P.m[pair];
+  const int nch = P.nch;
+  const int lane = threadIdx.x;
+  const int Kc = kcn[ct];
+  uint2 *mtl = dyn;
+  int2 *rng = reinterpret_cast<int2 *>(dyn + nch);
+
+  // stage the column tile's chunk table; compacted chunk -> global chunk range
+  for (int c = lane; c < nch; c += 64) rng[c] = make_int2(0x7fffffff, -1);
+  for (int e = lane; e < ScoreLdsC<BF16>::OPS / 16; e += 64)
+    reinterpret_cast<uint4 *>(smem)[e] = make_uint4(0u, 0u, 0u, 0u);
+  wave_sync();
+  const uint2 *mtg = mt + (int64_t)ct * nch;
+  for (int c = lane; c < nch; c += 64) {
+    const uint2 mm = mtg[c];
+    mtl[c] = mm;
+    if (mm.x) {
+      const int k1 = (int)(mm.y >> 5), k2 = (int)((mm.y + (uint32_t)__popc(mm.x) - 1u) >> 5);
+      atomicMin(&rng[k1].x, c);
+      atomicMax(&rng[k1].y, c);
+      if (k2 != k1) {
+        atomicMin(&rng[k2].x, c);
+        atomicMax(&rng[k2].y, c);
+      }
+    }
+  }
+  wave_sync();
+
+  f32x4 acc[4][4];
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) red[(16 * bi + 4 * rq + r) * RP + 16 * bj + r16] = acc[bi][bj][r];
-  wave_sync();
-  const int col = lane;
-  const bool vcol = col < cols;
-  const float lt = vcol ? (float)(tgt_off[t_first + col + 1] - tgt_off[t_first + col]) : 0.0f;
-  float *Sp = S + P.s_off[pair];
-  float *Rp = S_raw ? S_raw + P.s_off[pair] : nullptr;
-  const float LOG2E = 1.4426950408889634f;
-  for (int row = 0; row < rows; ++row) {
-    const float dot = red[row * RP + col];
-    const float ls = (float)(src_off[s_first + row + 1] - src_off[s_first + row]);
-    // S_raw = dot / l_i (0 for an empty sentence); rho = min / max of lengths
-    const float sraw = ls > 0.0f ? dot * __builtin_amdgcn_rcpf(ls) : 0.0f;
-    const float mx = fmaxf(ls, lt);
-    const float rho = mx > 0.0f ? fminf(ls, lt) * __builtin_amdgcn_rcpf(mx) : 1.0f;
-    const float z = __builtin_fmaf(sc.w0, sraw, __builtin_fmaf(sc.w1, rho, sc.b));
-    // sigmoid in the overflow-free form: e = exp(-|z|), S = 1/(1+e) or e/(1+e)
-    const float e = __builtin_amdgcn_exp2f(-fabsf(z) * LOG2E);
-    const float inv = __builtin_amdgcn_rcpf(1.0f + e);
-    const float sv = z >= 0.0f ? inv : e * inv;
-    if (vcol) {
-      const int64_t o = (int64_t)(row0 + row) * m + col0 + col;
-      Sp[o] = sv;
-      if (Rp) Rp[o] = sraw;
-    }
+    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int32_t *chA = a_choff + (int64_t)rt * (nch + 1);
+  const int32_t *chB = b_choff + (int64_t)ct * (nch + 1);
+  const uint2 *pa = a_list + src_off[s_first] * (int64_t)P.max_deg;
+  const uint32_t *pb = b_list + tgt_off[t_first];
+  // padding element (row 0, column KC) no fragment reads: where lanes with
+  // nothing to write go, all to one address
+  const uint32_t junk = (uint32_t)(KC * (int)sizeof(typename Op<BF16>::T));
+  constexpr int NCLR = ScoreLdsC<BF16>::OPS / 16 / 64;
+  static_assert(ScoreLdsC<BF16>::OPS % (16 * 64) == 0, "tile clear");
+  Frags<BF16> F;
+  CChunk X, Y, Z;
+
+  // chunk kc from register set Cur while the chunk after next (of the same
+  // window of 64) loads into Nxt; the tiles are cleared whole after their
+  // fragments are read (LDS operations of a wave complete in order)
+#define NWM_SCORE_CCHUNK(kc, Cur, Nxt)                                         \
+  {                                                                            \
+    cload(Nxt, pa, pb, W, (kc) + 2, lane);                                     \
+    cscatter<BF16>(Cur, At, Bt, mtl, pa, pb, (kc), lane, junk);                \
+    wave_sync();                                                               \
+    read_frags<BF16>(F, At, Bt, lane);                                         \
+    _Pragma("unroll") for (int e_ = 0; e_ < NCLR; ++e_)                        \
+      reinterpret_cast<uint4 *>(smem)[e_ * 64 + lane] = make_uint4(0u, 0u, 0u, 0u); \
+    mfma_frags<BF16>(F, acc);                                                  \
   }
+  // windows of 64 compacted chunks (one almost always covers the tile); the
+  // loads past the window's last chunk read an empty range
+  for (int wb = 0; wb < Kc; wb += 64) {
+    CWin W;
+    cwin_load(W, wb, Kc, rng, chA, chB, lane);
+    const int we = min(Kc, wb + 64) - wb;   // chunks in this window
+    cload(X, pa, pb, W, wb, lane);
+    cload(Y, pa, pb, W, wb + 1, lane);
+    int k = 0;
+    for (; k + 3 <= we; k += 3) {
+      NWM_SCORE_CCHUNK(wb + k, X, Z)
+      NWM_SCORE_CCHUNK(wb + k + 1, Y, X)
+      NWM_SCORE_CCHUNK(wb + k + 2, Z, Y)
+    }
+    if (k < we) NWM_SCORE_CCHUNK(wb + k, X, Z)
+    if (k + 1 < we) NWM_SCORE_CCHUNK(wb + k + 1, Y, X)
+  }
+#undef NWM_SCORE_CCHUNK
+  score_epilogue_regs(acc, P, src_off, tgt_off, sc, S, S_raw, pair, row0, rows, col0, cols, s_first, t_first, m,
+                      lane);
 }
 
 size_t score_lds_bytes(int, bool bf16) {
@@ -430,10 +694,20 @@ size_t score_lds_bytes(int, bool bf16) {
 
 hipError_t launch_score(const PlanDev &P, bool bf16, const int64_t *src_off, const int64_t *tgt_off,
                         const uint2 *a_list, const int32_t *a_choff, const uint32_t *b_list,
-                        const int32_t *b_choff, nwm_scorer sc, float *S, float *S_raw, int xcd_map,
-                        hipStream_t st) {
+                        const int32_t *b_choff, nwm_scorer sc, float *S, float *S_raw, int xcd_map, int compact,
+                        const uint2 *mt, const int32_t *kcn, hipStream_t st) {
   if (P.n_gt <= 0) return hipSuccess;
   const int grid = xcd_map ? 8 * ((P.n_gt + 7) / 8) : P.n_gt;
+  if (compact) {
+    const size_t dyn = 2 * sizeof(uint2) * (size_t)P.nch;
+    if (bf16)
+      hipLaunchKernelGGL(k_score_c<true>, dim3(grid), dim3(64), dyn, st, P, src_off, tgt_off, a_list, a_choff,
+                         b_list, b_choff, mt, kcn, sc, S, S_raw, xcd_map);
+    else
+      hipLaunchKernelGGL(k_score_c<false>, dim3(grid), dim3(64), dyn, st, P, src_off, tgt_off, a_list, a_choff,
+                         b_list, b_choff, mt, kcn, sc, S, S_raw, xcd_map);
+    return hipGetLastError();
+  }
   if (bf16)
     hipLaunchKernelGGL(k_score<true>, dim3(grid), dim3(64), 0, st, P, src_off, tgt_off, a_list, a_choff, b_list,
                        b_choff, sc, S, S_raw, xcd_map);

@@ -18,11 +18,13 @@ namespace nwm {
 hipError_t launch_merge_src(int64_t, const int64_t *, const int32_t *, const int32_t *, const int32_t *,
                             const float *, int, int, int, uint2 *, int32_t *, int, hipStream_t);
 hipError_t launch_build_a(const PlanDev &, const int64_t *, const uint2 *, const int32_t *, uint2 *, int32_t *,
-                          int, int, hipStream_t);
-hipError_t launch_build_b(const PlanDev &, const int64_t *, const int32_t *, uint32_t *, int32_t *, int, int,
-                          hipStream_t);
+                          int, int, int, hipStream_t);
+hipError_t launch_build_b(const PlanDev &, const int64_t *, const int32_t *, uint32_t *, int32_t *, int, int, int,
+                          uint2 *, int32_t *, hipStream_t);
+hipError_t build_set_attrs(int nch, int V);
 hipError_t launch_score(const PlanDev &, bool, const int64_t *, const int64_t *, const uint2 *, const int32_t *,
-                        const uint32_t *, const int32_t *, nwm_scorer, float *, float *, int, hipStream_t);
+                        const uint32_t *, const int32_t *, nwm_scorer, float *, float *, int, int, const uint2 *,
+                        const int32_t *, hipStream_t);
 size_t score_lds_bytes(int nch, bool bf16);
 hipError_t score_set_attrs(int nch_max);
 hipError_t launch_nw_fill(const PlanDev &, const float *, float, float *, char *, uint64_t *, int64_t, int32_t *,
@@ -82,7 +84,7 @@ struct nwm_plan {
   int64_t n_bnd = 0;   // uint64 entries of the published-row region
   int max_entries = 1; // dictionary entries of the longest source sentence (tokens x max_deg)
   // launch parameters (nwm_param) and what re-deriving the DP priority flags needs
-  int32_t param[4] = {0, 0, 1, 50};
+  int32_t param[5] = {0, 0, 1, 50, 1};
   uint64_t param_version = 0;
   std::vector<int32_t> it_strip;   // strip index per DP item (no flags)
   std::vector<int64_t> it_chain;   // dependency chain of the item's pair
@@ -368,6 +370,8 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   W.a_choff = carve(4 * (size_t)D.n_rt * (size_t)(nch + 1));
   W.b_list = carve(4 * ((size_t)p->tgt_tokens + LIST_SLACK_B));
   W.b_choff = carve(4 * (size_t)D.n_ct * (size_t)(nch + 1));
+  W.b_mt = carve(8 * (size_t)D.n_ct * (size_t)nch);
+  W.b_kcn = carve(4 * (size_t)D.n_ct);
   W.bwd = carve(16 * ((size_t)B + (size_t)D.n_rt));
   // published rows, + 2 entries (cleared in 16-byte units), + the sink
   W.bnd = carve(8 * ((size_t)bnd_off[B] + 2 + FILL_SINK_SLOTS));
@@ -379,7 +383,8 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   p->sizes.tb_bytes = (size_t)D.path_base + 8 * (size_t)p_off[B];
   p->sizes.ws_bytes = W.total;
   // ---- kernel attributes (dynamic LDS above the default) ---------------------------
-  if (merge_set_attrs(p->max_entries) != hipSuccess || score_set_attrs(nch) != hipSuccess || fill_set_attrs(0) != hipSuccess) {
+  if (merge_set_attrs(p->max_entries) != hipSuccess || score_set_attrs(nch) != hipSuccess ||
+      build_set_attrs(nch, p->V) != hipSuccess || fill_set_attrs(0) != hipSuccess) {
     (void)hipFree(p->dmeta);
     delete p;
     return NWM_EDEVICE;
@@ -432,6 +437,9 @@ nwm_status nwm_score_pairs(nwm_plan *p, const nwm_batch *batch, const nwm_dict *
   int32_t *a_choff = (int32_t *)(w + p->ws.a_choff);
   uint32_t *b_list = (uint32_t *)(w + p->ws.b_list);
   int32_t *b_choff = (int32_t *)(w + p->ws.b_choff);
+  uint2 *b_mt = (uint2 *)(w + p->ws.b_mt);
+  int32_t *b_kcn = (int32_t *)(w + p->ws.b_kcn);
+  const int compact = p->param[NWM_PARAM_SCORE_COMPACT];
   const bool bf16 = p->prec == NWM_BF16;
   // list entries are LDS byte offsets inside the operand tiles
   const int pitch = bf16 ? PITCH_BF16 : PITCH_F32;
@@ -449,20 +457,22 @@ nwm_status nwm_score_pairs(nwm_plan *p, const nwm_batch *batch, const nwm_dict *
     hipError_t e = hipEventRecord(p->ev_fork, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(p->aux_stream, p->ev_fork, 0);
     if (e == hipSuccess)
-      e = launch_build_b(p->dev, batch->tgt_off, batch->tgt_tok, b_list, b_choff, pitch, esize, p->aux_stream);
+      e = launch_build_b(p->dev, batch->tgt_off, batch->tgt_tok, b_list, b_choff, pitch, esize, compact, b_mt, b_kcn,
+                         p->aux_stream);
     if (e == hipSuccess) e = hipEventRecord(p->ev_join, p->aux_stream);
     Mark mk(p, K_EXPAND, st);
     if (e == hipSuccess)
       e = launch_merge_src(p->n_src, batch->src_off, batch->src_tok, dict->row_off, dict->col, dict->val, p->V,
                            p->max_deg, p->max_entries, merged, cnt, p->param[NWM_PARAM_MERGE_WAVES_PER_CU], st);
-    if (e == hipSuccess) e = launch_build_a(p->dev, batch->src_off, merged, cnt, a_list, a_choff, pitch, esize, st);
+    if (e == hipSuccess)
+      e = launch_build_a(p->dev, batch->src_off, merged, cnt, a_list, a_choff, pitch, esize, compact, st);
     mk.done();
     if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_join, 0);
     if (e != hipSuccess) return NWM_EDEVICE;
   }
   Mark mk(p, K_SCORE, st);
   hipError_t e = launch_score(p->dev, bf16, batch->src_off, batch->tgt_off, a_list, a_choff, b_list, b_choff, sc,
-                              S, S_raw, p->param[NWM_PARAM_SCORE_XCD_MAP], st);
+                              S, S_raw, p->param[NWM_PARAM_SCORE_XCD_MAP], compact, b_mt, b_kcn, st);
   mk.done();
   return dev_err(e);
 }
@@ -530,6 +540,7 @@ nwm_status nwm_plan_set_param(nwm_plan *p, nwm_param param, int32_t value) {
       if (value < 0 || value > 32) return NWM_EINVAL;
       break;
     case NWM_PARAM_SCORE_XCD_MAP:
+    case NWM_PARAM_SCORE_COMPACT:
       if (value != 0 && value != 1) return NWM_EINVAL;
       break;
     case NWM_PARAM_DP_HOT_PERCENT:
@@ -553,7 +564,7 @@ nwm_status nwm_plan_set_param(nwm_plan *p, nwm_param param, int32_t value) {
 }
 
 nwm_status nwm_plan_get_param(const nwm_plan *p, nwm_param param, int32_t *value) {
-  if (!p || !value || (int)param < 0 || (int)param > 3) return NWM_EINVAL;
+  if (!p || !value || (int)param < 0 || (int)param > 4) return NWM_EINVAL;
   *value = p->param[param];
   return NWM_OK;
 }

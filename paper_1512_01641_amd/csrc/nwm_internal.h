@@ -25,8 +25,13 @@ constexpr int PITCH_F32 = KC + 4;    // 144 B rows
 // the chunk start, so the lists carry that much slack at their end.
 constexpr int REG_A = 2;
 constexpr int REG_B = 2;
-constexpr int LIST_SLACK_A = 64 * REG_A;
-constexpr int LIST_SLACK_B = 64 * REG_B;
+// The compacted contraction (K restricted to the column tile's words) holds
+// up to 64 * CREG_A entries of a compacted chunk's A range in registers, for
+// three chunks at a time.
+constexpr int CREG_A = 6;
+constexpr int CREG_B = 2;
+constexpr int LIST_SLACK_A = 64 * (CREG_A > REG_A ? CREG_A : REG_A);
+constexpr int LIST_SLACK_B = 64 * (CREG_B > REG_B ? CREG_B : REG_B);
 // LDS staging capacity of tile lists (entries) per K segment.
 constexpr int CAP_A = 2048;
 constexpr int CAP_B = 2048;
@@ -90,6 +95,8 @@ struct WsLayout {
   size_t a_choff;    // int32 [n_rt * (nch + 1)]
   size_t b_list;     // uint32 lds offset [tgt_tokens]
   size_t b_choff;    // int32 [n_ct * (nch + 1)]
+  size_t b_mt;       // uint2 {word mask, words before} [n_ct * nch] (compacted contraction)
+  size_t b_kcn;      // int32 [n_ct] compacted chunks per column tile
   size_t bwd;        // float [B * 4] per-pair partials + float [n_blocks * 4]
   size_t bnd;        // uint64 (value, epoch) boundary rows between strips
   size_t ctl;        // int32 [2]: DP queue head, error flag

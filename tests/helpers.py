@@ -17,13 +17,16 @@ def gpu_available() -> bool:
         return False
 
 
-def run_gpu(batch, prec=0, scorer=None, gap=None, threshold=None, device="cuda:0", want_raw=True):
-    """Score + align a synth batch on the GPU; returns host numpy results."""
+def run_gpu(batch, prec=0, scorer=None, gap=None, threshold=None, device="cuda:0", want_raw=True, params=None):
+    """Score + align a synth batch on the GPU; returns host numpy results.
+    `params`: launch parameters set on the plan first ({name: value})."""
     import paper_1512_01641_amd as nw
     ctx = nw.Context(0)
     db = nw.DeviceBatch.from_host(batch, device)
     dd = nw.DeviceDict.from_host(batch, device)
     mn = nw.Miner(ctx, db, dd, prec)
+    for k, v in (params or {}).items():
+        mn.plan.set_param(k, v)
     w = batch.scorer if scorer is None else np.asarray(scorer, np.float32)
     mn.score_pairs(w, want_raw=want_raw)
     mn.align(batch.gap if gap is None else gap, batch.threshold if threshold is None else threshold)

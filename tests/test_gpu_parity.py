@@ -87,8 +87,8 @@ def test_dp_large_pair_bitexact():
 
 
 # --- scores ---------------------------------------------------------------------------
-def _check_scores(batch, prec, tol_rel=None, tol_abs=None, scorer=None):
-    gpu = H.run_gpu(batch, prec=prec, scorer=scorer)
+def _check_scores(batch, prec, tol_rel=None, tol_abs=None, scorer=None, params=None):
+    gpu = H.run_gpu(batch, prec=prec, scorer=scorer, params=params)
     ora = oracle.score(batch, scorer=scorer)
     if tol_rel is not None:
         err = H.s_rel_err(gpu["S"], ora["S64"])
@@ -125,6 +125,41 @@ def test_scores_ragged_batch_fp32():
     b2.n[3] = 0
     gpu_ok = b.subset(list(range(40)))
     _check_scores(gpu_ok, 0, tol_rel=1e-5)
+
+
+def _wide_vocabulary_batch():
+    """Two pairs of 70 x 70 sentences over V = 4096 with uniformly drawn words:
+    a 64-sentence target tile holds about 2500 distinct words (more than 64
+    compacted chunks: the chunk-range window slides) and 150-token source
+    sentences put more A entries into one compacted chunk than the registers
+    hold (the overflow loop runs)."""
+    import dataclasses
+    b = corpus.make_batch(2, pairs=2, sizes=([70, 70], [70, 70]), V=4096)
+    rng = np.random.default_rng(11)
+    s_len = rng.integers(100, 151, size=140)
+    t_len = rng.integers(40, 61, size=140)
+    s_len[5] = 0    # an empty source sentence
+    t_len[77] = 0   # an empty target sentence
+    return dataclasses.replace(
+        b, src_off=np.concatenate([[0], np.cumsum(s_len)]).astype(np.int64),
+        src_tok=rng.integers(0, 4096, size=int(s_len.sum())).astype(np.int32),
+        tgt_off=np.concatenate([[0], np.cumsum(t_len)]).astype(np.int64),
+        tgt_tok=rng.integers(0, 4096, size=int(t_len.sum())).astype(np.int32))
+
+
+@pytest.mark.parametrize("compact", [1, 0])
+def test_scores_compacted_and_dense_contraction(compact):
+    # both contraction modes against the oracle: the ragged 40-pair batch and
+    # the wide-vocabulary batch (window slide, register overflow)
+    p = {"score_compact": compact}
+    b = corpus.make_batch(2, pairs=40)
+    gpu, ora = _check_scores(b, 0, tol_rel=1e-5, params=p)
+    np.testing.assert_allclose(gpu["S_raw"], ora["S_raw"], rtol=1e-5, atol=1e-7)
+    _check_scores(b, 1, tol_abs=2e-2, params=p)
+    w = _wide_vocabulary_batch()
+    gpu, ora = _check_scores(w, 0, tol_rel=1e-5, params=p)
+    np.testing.assert_allclose(gpu["S_raw"], ora["S_raw"], rtol=1e-5, atol=1e-7)
+    _check_scores(w, 1, tol_abs=2e-2, params=p)
 
 
 def test_end_to_end_dp_bitexact_on_gpu_scores():
