@@ -121,6 +121,8 @@ def main():
                     help="2: 4096 pairs, lognormal median 60, V=4096 (the benchmark line); 3: 256 pairs of "
                          "5000x5000, V=16384; 5: 100k pairs, lognormal median 60, V=16384")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-bidir", action="store_true", help="skip the bi-directional mining measurement")
+    ap.add_argument("--no-search", action="store_true", help="skip the random-search tuning measurement")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
     ap.add_argument("--prec", choices=("both", "bf16", "f32"), default="both")
@@ -197,6 +199,50 @@ def main():
                                                           results[prec_name]))
         del mn
 
+    bidir = None
+    if not args.no_bidir:
+        # bi-directional mining (Sec. 5.4, Table 3 "BI"): forward + reverse
+        # direction (target side as the source, reverse dictionary) + union
+        _log("bi-directional %s" % precs[0][0])
+        rbatch = corpus.reverse_batch(batch)
+        bm = nw.BiMiner(ctx, db, dd, nw.DeviceDict.from_host(rbatch), precs[0][1])
+        gb = not args.no_graph
+        bstep = lambda: bm.mine(w, rbatch.scorer, gap, thr, graph=gb)
+        bi_ms = _time_steps(bstep, args.steps, max(args.warmup, 1), torch)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(args.steps):
+            bm.union()
+        ev1.record()
+        torch.cuda.synchronize()
+        n_bi = int(bm.n_kept[:B].sum().item())
+        n_mono = int(bm.fwd.n_kept[:B].sum().item())
+        bidir = {"pairs_per_s": round(B / (bi_ms / 1000.0), 2), "ms_per_step": round(bi_ms, 4),
+                 "union_ms": round(ev0.elapsed_time(ev1) / args.steps, 4),
+                 "kept_pairs_forward": n_mono, "kept_pairs_bidirectional": n_bi,
+                 "launch": "two graph replays + union kernel" if gb else "eager"}
+        del bm
+
+    search = None
+    if not args.no_search:
+        # the tuning script (Sec. 5.2): random search over (threshold, gap) on
+        # a 100-pair tuning set (the paper tunes on 100 human-aligned pairs;
+        # planted alignments stand in)
+        from paper_1512_01641_amd import tune
+        tb_ = batch.subset(range(min(100, B)))
+        smn = nw.Miner(ctx, nw.DeviceBatch.from_host(tb_), dd, precs[0][1])
+        tune.random_search(smn, w, tb_.gold_off, tb_.gold, trials=2, seed=1)   # warm-up
+        torch.cuda.synchronize()
+        trials = 64
+        t0 = time.perf_counter()
+        res = tune.random_search(smn, w, tb_.gold_off, tb_.gold, trials=trials, seed=0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        search = {"trials_per_s": round(trials / dt, 2), "pairs": tb_.B, "trials": trials,
+                  "best": {"threshold": res["threshold"], "gap": res["gap"], "similarity": round(res["similarity"], 3)},
+                  "note": "per trial: NW fill + traceback + keep on the GPU, similarity on the host"}
+        del smn
+
     plain = None
     if not args.no_plain:
         _log("plain per-pair FP32")
@@ -272,6 +318,10 @@ def main():
                         "kernel": "k_nw_fill", "algorithmic": "4.25 B/cell (S read + 2-bit traceback)",
                         "traffic": profiled_traffic("k_nw_fill")},
     }
+    if bidir is not None:
+        out["bidirectional"] = bidir
+    if search is not None:
+        out["random_search"] = search
     if not args.no_cpu:
         _log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(batch)

@@ -195,6 +195,31 @@ nwm_status nwm_mine(nwm_plan *plan, const nwm_batch *batch, const nwm_dict *dict
                     int32_t *n_kept, void *tb, void *ws, void *stream);
 nwm_status nwm_plan_set_graph(nwm_plan *plan, int on);
 
+/* --- bi-directional mining ----------------------------------------------------- */
+
+/* Union of the aligned pairs two mining directions keep (Sec. 5.4, Table 3
+ * "BI": a second classifier trained in the reverse direction adds pairs the
+ * first misses).  `plan` is the forward plan.  The reverse direction is a
+ * plan of the same document pairs with the roles swapped (target sentences
+ * as the source side, a target-to-source dictionary); both have the same
+ * kept-pair offsets, p_off[b] = sum over c < b of min(n_c, m_c).
+ *   kept_fwd    [kept_cap][2] int32, device: (i, j) of the forward plan's
+ *               nwm_align_batch; n_kept_fwd [B] its counts.
+ *   kept_rev    [kept_cap][2] int32, device: the reverse plan's kept pairs,
+ *               as that plan reports them: (target index, source index);
+ *               n_kept_rev [B].
+ *   kept_out    [2 kept_cap][2] int32, device, caller-owned: pair b's union
+ *               at 2 p_off[b], as (i, j) = (source, target) in ascending
+ *               order, each sentence pair once; n_out [B] its size
+ *               (<= 2 min(n_b, m_b)).
+ * Both inputs must be strictly increasing in i and in j per pair, as
+ * nwm_align_batch writes them (other inputs give an unspecified but
+ * in-bounds result).  Asynchronous on `stream`.  NWM_EINVAL for null
+ * pointers the sizes need. */
+nwm_status nwm_union_kept(const nwm_plan *plan, const int32_t *kept_fwd, const int32_t *n_kept_fwd,
+                          const int32_t *kept_rev, const int32_t *n_kept_rev, int32_t *kept_out, int32_t *n_out,
+                          void *stream);
+
 /* --- launch parameters (for the autotuner) ------------------------------------ */
 
 /* Launch shapes that do not change any result, only the time (all but

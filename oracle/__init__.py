@@ -17,6 +17,13 @@ Functions and the passages they follow (Wolk & Marasek, arXiv 1512.01641):
   backward() -- subgradient of the NW score (path indicator, gap count) chained
                 through the sigmoid scorer; drives the tuning of Sec. 5.2.
   f1()       -- micro F1 of kept pairs against the planted alignment.
+  union_kept() -- Sec. 5.4 / Table 3 "BI": bi-directional mining keeps the
+                pairs either direction's classifier keeps; read here as the
+                set union of the two kept sets (each sentence pair once),
+                the reverse direction's (target, source) pairs swapped.
+  similarity() -- Sec. 5.2: how closely an automatic alignment resembles a
+                reference one, by NW over the two aligned-pair sequences
+                (match 1, mismatch and gaps 0), in percent.
 """
 from __future__ import annotations
 
@@ -200,3 +207,48 @@ def f1(kept_sets, gold_sets) -> float:
     P = tp / nk
     R = tp / ng
     return 200.0 * P * R / (P + R)
+
+
+def union_kept(kept_fwd, kept_rev):
+    """Per document pair: the sentence pairs kept by the forward direction
+    (i, j) or by the reverse direction (given as (j, i)), each once, in
+    ascending (i, j) order.  Arguments: sequences of [k, 2] arrays."""
+    out = []
+    for F, R in zip(kept_fwd, kept_rev):
+        F = np.asarray(F, np.int64).reshape(-1, 2)
+        R = np.asarray(R, np.int64).reshape(-1, 2)
+        u = set(map(tuple, F.tolist())) | set((j, i) for i, j in R.tolist())
+        out.append(np.array(sorted(u), np.int32).reshape(-1, 2))
+    return out
+
+
+def _nw_match_count(A, G) -> int:
+    """NW over two sequences of aligned pairs, match 1, mismatch 0, gaps 0:
+    the best total is the number of matched pairs.  Row by row: with gaps
+    free, a row of the DP is the running maximum of max(up, diag + match)."""
+    if len(A) == 0 or len(G) == 0:
+        return 0
+    keyA = [tuple(x) for x in np.asarray(A).reshape(-1, 2).tolist()]
+    keyG = [tuple(x) for x in np.asarray(G).reshape(-1, 2).tolist()]
+    prev = np.zeros(len(keyG) + 1, np.int64)
+    for a in keyA:
+        match = np.fromiter((1 if g == a else 0 for g in keyG), np.int64, len(keyG))
+        cur = np.empty_like(prev)
+        cur[0] = 0
+        cur[1:] = np.maximum(prev[1:], prev[:-1] + match)
+        prev = np.maximum.accumulate(cur)
+    return int(prev[-1])
+
+
+def similarity(auto_sets, ref_sets) -> float:
+    """Sec. 5.2: resemblance (percent) of automatic alignments to reference
+    ones, the sentence-pair sequences compared by NW (match 1, else 0):
+    100 * 2 * sum_b M_b / sum_b (|A_b| + |G_b|), M_b the NW optimum of pair b;
+    100 when both sides are empty everywhere."""
+    m = tot = 0
+    for A, G in zip(auto_sets, ref_sets):
+        A = np.asarray(A).reshape(-1, 2)
+        G = np.asarray(G).reshape(-1, 2)
+        m += _nw_match_count(A, G)
+        tot += len(A) + len(G)
+    return 100.0 if tot == 0 else 200.0 * m / tot

@@ -20,8 +20,9 @@ import torch
 from . import _abi
 from ._abi import NWM_BF16, NWM_FP32, NwmError
 
-__all__ = ["Context", "DeviceBatch", "DeviceDict", "Plan", "Miner", "score_pairs", "align_batch",
-           "align_backward", "NWAlign", "MineScore", "LogisticScore", "NWM_FP32", "NWM_BF16", "NwmError"]
+__all__ = ["Context", "DeviceBatch", "DeviceDict", "Plan", "Miner", "BiMiner", "score_pairs", "align_batch",
+           "align_backward", "mine", "union_kept", "NWAlign", "MineScore", "LogisticScore", "NWM_FP32", "NWM_BF16",
+           "NwmError"]
 
 
 def _ptr(t):
@@ -76,7 +77,19 @@ class DeviceBatch:
             so = np.asarray(src_off)
             max_sent_tokens = int(np.diff(so).max()) if len(so) > 1 else 0
         self.max_sent_tokens = int(max_sent_tokens)
+        to = np.asarray(tgt_off)
+        self.max_tgt_sent_tokens = int(np.diff(to).max()) if len(to) > 1 else 0
         self.device = dev
+
+    def reversed(self) -> "DeviceBatch":
+        """The same document pairs with the roles of the two sides swapped
+        (target sentences as the source side); shares the device arrays."""
+        r = DeviceBatch.__new__(DeviceBatch)
+        r.n, r.m, r.V, r.device = self.m, self.n, self.V, self.device
+        r.src_off, r.src_tok, r.tgt_off, r.tgt_tok = self.tgt_off, self.tgt_tok, self.src_off, self.src_tok
+        r.src_tokens, r.tgt_tokens = self.tgt_tokens, self.src_tokens
+        r.max_sent_tokens, r.max_tgt_sent_tokens = self.max_tgt_sent_tokens, self.max_sent_tokens
+        return r
 
     @classmethod
     def from_host(cls, b, device="cuda:0"):
@@ -208,6 +221,13 @@ def mine(plan: Plan, batch: DeviceBatch, dic: DeviceDict, scorer, gap: float, th
                                  _ptr(n_kept), _ptr(tb), _ptr(ws), _stream(plan.ctx.device)), "nwm_mine")
 
 
+def union_kept(plan: Plan, kept_fwd, n_kept_fwd, kept_rev, n_kept_rev, kept_out, n_out):
+    """Union of the kept pairs of the forward plan and of the reverse plan
+    (whose pairs are (target, source)), each sentence pair once, ascending."""
+    _abi.check(plan.lib.nwm_union_kept(plan.h, _ptr(kept_fwd), _ptr(n_kept_fwd), _ptr(kept_rev), _ptr(n_kept_rev),
+                                       _ptr(kept_out), _ptr(n_out), _stream(plan.ctx.device)), "nwm_union_kept")
+
+
 class Miner:
     """Owns a plan and the device buffers of one batch: score -> align -> keep."""
 
@@ -252,6 +272,38 @@ class Miner:
     def kept_pairs(self, b: int):
         """Kept (i, j) pairs of pair b (host copy)."""
         o = int(self.p_off[b])
+        k = int(self.n_kept[b].item())
+        return self.kept[o:o + k].cpu().numpy()
+
+
+class BiMiner:
+    """Bi-directional mining (Sec. 5.4, Table 3 "BI"): the forward miner, a
+    reverse miner over the same document pairs (target sentences as the
+    source side, a target-to-source dictionary and its own scorer), and the
+    union of what the two keep."""
+
+    def __init__(self, ctx: Context, batch: DeviceBatch, dic_fwd: DeviceDict, dic_rev: DeviceDict,
+                 prec: int = NWM_FP32):
+        self.fwd = Miner(ctx, batch, dic_fwd, prec)
+        self.rev = Miner(ctx, batch.reversed(), dic_rev, prec)
+        dev = ctx.device
+        B = batch.B
+        self.p_off = self.fwd.p_off
+        self.kept = torch.empty((max(2 * self.fwd.plan.kept_cap, 1), 2), dtype=torch.int32, device=dev)
+        self.n_kept = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
+
+    def union(self):
+        union_kept(self.fwd.plan, self.fwd.kept, self.fwd.n_kept, self.rev.kept, self.rev.n_kept, self.kept,
+                   self.n_kept)
+
+    def mine(self, scorer_fwd, scorer_rev, gap: float, threshold: float, graph: bool = False):
+        self.fwd.mine(scorer_fwd, gap, threshold, graph=graph)
+        self.rev.mine(scorer_rev, gap, threshold, graph=graph)
+        self.union()
+
+    def kept_pairs(self, b: int):
+        """Union of pair b (host copy), (source, target) ascending."""
+        o = 2 * int(self.p_off[b])
         k = int(self.n_kept[b].item())
         return self.kept[o:o + k].cpu().numpy()
 

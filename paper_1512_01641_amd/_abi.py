@@ -16,7 +16,7 @@ STATUS_NAMES = {0: "NWM_OK", 1: "NWM_EINVAL", 2: "NWM_ESHAPE", 3: "NWM_ENOMEM", 
 SYMBOLS = ["nwm_create", "nwm_destroy", "nwm_strerror", "nwm_plan_create", "nwm_plan_sizes",
            "nwm_plan_destroy", "nwm_score_pairs", "nwm_align_batch", "nwm_align_backward", "nwm_mine",
            "nwm_plan_set_graph", "nwm_plan_set_param", "nwm_plan_get_param", "nwm_plan_set_timing",
-           "nwm_plan_kernel_ms"]
+           "nwm_plan_kernel_ms", "nwm_union_kept"]
 
 PARAMS = {"fill_waves_per_cu": 0, "merge_waves_per_cu": 1, "score_xcd_map": 2, "dp_hot_percent": 3,
           "score_compact": 4}
@@ -95,6 +95,8 @@ def load(path: str | None = None):
     lib.nwm_plan_set_timing.restype = I
     lib.nwm_plan_kernel_ms.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), I]
     lib.nwm_plan_kernel_ms.restype = I
+    lib.nwm_union_kept.argtypes = [P, P, P, P, P, P, P, P]
+    lib.nwm_union_kept.restype = I
     if path == LIB_PATH:
         _lib = lib
     return lib

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnwmine.so")
-SOURCES = ["k_expand.hip", "k_score.hip", "k_align.hip", "k_backward.hip", "nwm_abi.hip"]
+SOURCES = ["k_expand.hip", "k_score.hip", "k_align.hip", "k_backward.hip", "k_bidir.hip", "nwm_abi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

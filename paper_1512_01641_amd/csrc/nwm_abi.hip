@@ -34,6 +34,8 @@ hipError_t launch_nw_walk(const PlanDev &, const char *, int2 *, int32_t *, hipS
 hipError_t launch_keep(const PlanDev &, const float *, float, const int2 *, const int32_t *, int2 *, int32_t *,
                        hipStream_t);
 hipError_t merge_set_attrs(int max_entries);
+hipError_t launch_union_kept(int, const int64_t *, const int2 *, const int32_t *, const int2 *, const int32_t *,
+                             int2 *, int32_t *, hipStream_t);
 hipError_t launch_backward(const PlanDev &, const int64_t *, const int64_t *, const int2 *, const int32_t *,
                            const float *, const float *, float *, double *, const float *, const float *,
                            double *, float *, float *, hipStream_t);
@@ -567,6 +569,17 @@ nwm_status nwm_plan_get_param(const nwm_plan *p, nwm_param param, int32_t *value
   if (!p || !value || (int)param < 0 || (int)param > 4) return NWM_EINVAL;
   *value = p->param[param];
   return NWM_OK;
+}
+
+nwm_status nwm_union_kept(const nwm_plan *p, const int32_t *kept_fwd, const int32_t *n_kept_fwd,
+                          const int32_t *kept_rev, const int32_t *n_kept_rev, int32_t *kept_out, int32_t *n_out,
+                          void *stream) {
+  if (!p) return NWM_EINVAL;
+  if (p->B == 0) return NWM_OK;
+  if (!n_kept_fwd || !n_kept_rev || !n_out) return NWM_EINVAL;
+  if (p->sizes.kept_cap > 0 && (!kept_fwd || !kept_rev || !kept_out)) return NWM_EINVAL;
+  return dev_err(launch_union_kept(p->B, p->dev.p_off, (const int2 *)kept_fwd, n_kept_fwd, (const int2 *)kept_rev,
+                                   n_kept_rev, (int2 *)kept_out, n_out, (hipStream_t)stream));
 }
 
 nwm_status nwm_plan_set_graph(nwm_plan *p, int on) {

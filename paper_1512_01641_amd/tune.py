@@ -127,3 +127,52 @@ class Tuner:
         self.gap = float(s["gap"])
         self.threshold = float(s["threshold"])
         self.step_no = int(s["step"])
+
+
+def similarity(auto_sets, ref_sets) -> float:
+    """Resemblance (percent) of automatic to reference alignments (Sec. 5.2:
+    the two aligned-pair sequences compared by NW, match 1 and 0 otherwise).
+    Both sequences of a document pair are strictly increasing in i and in j,
+    so the NW optimum is the number of pairs they share:
+    100 * 2 * sum |A & G| / sum (|A| + |G|), 100 if both are empty."""
+    m = tot = 0
+    for A, G in zip(auto_sets, ref_sets):
+        A = np.asarray(A).reshape(-1, 2)
+        G = np.asarray(G).reshape(-1, 2)
+        if len(A) and len(G):
+            ka = A[:, 0].astype(np.int64) << 32 | A[:, 1].astype(np.int64)
+            kg = G[:, 0].astype(np.int64) << 32 | G[:, 1].astype(np.int64)
+            m += len(np.intersect1d(ka, kg, assume_unique=True))
+        tot += len(A) + len(G)
+    return 100.0 if tot == 0 else 200.0 * m / tot
+
+
+def random_search(miner: Miner, scorer, gold_off, gold, trials: int = 32, tau=(0.05, 0.95), gap=(-1.0, -0.01),
+                  seed: int = 0):
+    """The paper's tuning script (Sec. 5.2): naive random selection of the
+    threshold and the gap penalty, keeping the pair whose alignments are most
+    similar to the reference ones.  S does not depend on either, so the batch
+    is scored once and each trial runs the DP + keep only.  Draws per trial:
+    threshold ~ U(tau), then gap ~ U(gap), both rounded to FP32.  Returns the
+    best (first on ties) and the history [(threshold, gap, similarity)]."""
+    rng = np.random.default_rng(seed)
+    B = miner.batch.B
+    gold_off = np.asarray(gold_off, np.int64)
+    gold = np.asarray(gold, np.int32).reshape(-1, 2)
+    ref = [gold[gold_off[b]:gold_off[b + 1]] for b in range(B)]
+    miner.score_pairs(scorer, want_raw=False)
+    hist = []
+    for _ in range(trials):
+        th = float(np.float32(rng.uniform(*tau)))
+        g = float(np.float32(rng.uniform(*gap)))
+        miner.align(g, th)
+        torch.cuda.synchronize()
+        nk = miner.n_kept[:B].cpu().numpy()
+        kept = miner.kept.cpu().numpy()
+        auto = [kept[int(miner.p_off[b]):int(miner.p_off[b]) + int(nk[b])] for b in range(B)]
+        hist.append((th, g, similarity(auto, ref)))
+    best = max(range(len(hist)), key=lambda k: (hist[k][2], -k)) if hist else None
+    out = {"history": hist}
+    if best is not None:
+        out.update(threshold=hist[best][0], gap=hist[best][1], similarity=hist[best][2])
+    return out

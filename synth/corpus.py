@@ -278,6 +278,43 @@ def make_batch(cfg: int, pairs: int | None = None, first: int = 0, V: int | None
     )
 
 
+def reverse_dictionary(b: Batch, deg: int = DICT_DEG):
+    """A target-to-source dictionary drawn from the same translation table:
+    row u lists the source words t whose forward row holds u, keeping the
+    ``deg`` largest weights D[t][u] (ties: smaller t first), rescaled to sum
+    to 1.  Target words no source word translates to get an empty row."""
+    V = b.V
+    src = np.repeat(np.arange(V, dtype=np.int64), np.diff(b.d_row_off))
+    u = b.d_col.astype(np.int64)
+    w = b.d_val.astype(np.float64)
+    order = np.lexsort((src, -w, u))          # by target word, then weight desc, then source word
+    u, src, w = u[order], src[order], w[order]
+    first = np.concatenate([[0], np.flatnonzero(np.diff(u)) + 1])
+    rank = np.arange(len(u)) - np.repeat(first, np.diff(np.concatenate([first, [len(u)]])))
+    keep = rank < deg
+    u, src, w = u[keep], src[keep], w[keep]
+    cnt = np.bincount(u, minlength=V)
+    row_off = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int32)
+    tot = np.repeat(np.add.reduceat(w, row_off[:-1][cnt > 0]), cnt[cnt > 0])
+    return row_off, src.astype(np.int32), (w / tot).astype(np.float32)
+
+
+def reverse_batch(b: Batch) -> Batch:
+    """The same document pairs seen from the other side: target sentences as
+    the source side, the reverse dictionary, planted pairs as (j, i)."""
+    d_row_off, d_col, d_val = reverse_dictionary(b)
+    gold = b.gold[:, ::-1].copy() if len(b.gold) else b.gold.reshape(-1, 2).copy()
+    golds = []
+    for k in range(b.B):
+        g = gold[b.gold_off[k]:b.gold_off[k + 1]]
+        golds.append(g[np.argsort(g[:, 0], kind="stable")])
+    return dataclasses.replace(
+        b, n=b.m.copy(), m=b.n.copy(), src_off=b.tgt_off, src_tok=b.tgt_tok, tgt_off=b.src_off, tgt_tok=b.src_tok,
+        d_row_off=d_row_off, d_col=d_col, d_val=d_val,
+        d_deg=int(np.diff(d_row_off).max()) if len(d_row_off) > 1 else 0,
+        gold=(np.concatenate(golds) if golds else gold).astype(np.int32).reshape(-1, 2))
+
+
 def identity_batch(cfg: int, n: int, V: int = 2048, b: int = 0) -> Batch:
     """Source document with its exact translation through a permutation
     dictionary (one target per word, weight 1), no noise and no indels.

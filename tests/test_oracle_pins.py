@@ -464,3 +464,82 @@ def test_generator_planted_alignment():
     cols = b.d_col.reshape(V, 4)
     assert np.all(np.sort(cols, 1)[:, 1:] != np.sort(cols, 1)[:, :-1])
     np.testing.assert_allclose(b.d_val.reshape(V, 4).sum(1), 1.0, rtol=1e-6)
+
+
+# --- bi-directional mining: union of kept sets (Sec. 5.4, Table 3 "BI") -------------
+def _monotone(rng, n, k):
+    """k pairs strictly increasing in i and in j, coordinates < n."""
+    k = min(k, n)
+    return np.stack([np.sort(rng.choice(n, k, replace=False)), np.sort(rng.choice(n, k, replace=False))], 1)
+
+
+def test_union_kept_hand_example():
+    fwd = [np.array([[0, 0], [2, 1], [4, 4]])]
+    rev = [np.array([[0, 0], [2, 3], [5, 6]])]     # (j, i): (0,0) (3,2) (6,5)
+    u = oracle.union_kept(fwd, rev)[0]
+    np.testing.assert_array_equal(u, [[0, 0], [2, 1], [3, 2], [4, 4], [6, 5]])
+
+
+def test_union_kept_inclusion_exclusion_and_order():
+    rng = np.random.default_rng(5)
+    for t in range(200):
+        n = int(rng.integers(1, 300))
+        F = _monotone(rng, n, int(rng.integers(0, n + 1)))
+        Rf = _monotone(rng, n, int(rng.integers(0, n + 1)))
+        if t % 3 == 0 and len(F):          # force shared pairs
+            Rf = F[np.sort(rng.choice(len(F), int(rng.integers(0, len(F) + 1)), replace=False))]
+        u = oracle.union_kept([F], [Rf[:, ::-1]])[0]
+        kf = F[:, 0].astype(np.int64) * 4096 + F[:, 1]
+        kr = Rf[:, 0].astype(np.int64) * 4096 + Rf[:, 1]
+        ku = u[:, 0].astype(np.int64) * 4096 + u[:, 1]
+        assert len(u) == len(F) + len(Rf) - len(np.intersect1d(kf, kr))
+        assert np.all(np.diff(ku) > 0)                   # ascending, each once
+        assert np.all(np.isin(kf, ku)) and np.all(np.isin(kr, ku))
+
+
+def test_reverse_dictionary_is_the_transposed_table():
+    b = corpus.make_batch(2, pairs=2)
+    ro, col, val = corpus.reverse_dictionary(b)
+    fwd = {}
+    for t in range(b.V):
+        for k in range(b.d_row_off[t], b.d_row_off[t + 1]):
+            fwd[(t, int(b.d_col[k]))] = float(b.d_val[k])
+    for u in range(0, b.V, 7):
+        row = range(ro[u], ro[u + 1])
+        assert len(row) <= corpus.DICT_DEG
+        if len(row) == 0:
+            assert not any(uu == u for (_, uu) in fwd)
+            continue
+        ws = [fwd[(int(col[k]), u)] for k in row]          # every entry is a forward entry t -> u
+        assert ws == sorted(ws, reverse=True)
+        assert abs(float(np.sum(val[ro[u]:ro[u + 1]], dtype=np.float64)) - 1.0) < 1e-6
+        np.testing.assert_allclose(val[ro[u]:ro[u + 1]], np.array(ws) / np.sum(ws), rtol=1e-6)
+
+
+# --- tuning script similarity (Sec. 5.2) ----------------------------------------------
+def test_similarity_hand_example_and_special_cases():
+    A = [np.array([[0, 0], [1, 1], [2, 3]])]
+    G = [np.array([[0, 0], [2, 3]])]
+    assert oracle.similarity(A, G) == pytest.approx(80.0)      # 2 * 2 / (3 + 2)
+    e = np.zeros((0, 2), np.int32)
+    assert oracle.similarity([e], [e]) == 100.0
+    assert oracle.similarity([A[0]], [e]) == 0.0
+    assert oracle.similarity(A, A) == 100.0
+
+
+def test_similarity_nw_equals_shared_pairs_for_monotone_sequences():
+    # two strictly increasing sequences: the NW optimum (match 1, else 0) is
+    # the number of common elements
+    rng = np.random.default_rng(6)
+    for _ in range(100):
+        n = int(rng.integers(1, 80))
+        A = _monotone(rng, n, int(rng.integers(0, n + 1)))
+        G = _monotone(rng, n, int(rng.integers(0, n + 1)))
+        if len(A) and rng.random() < 0.5:
+            G = A[np.sort(rng.choice(len(A), int(rng.integers(0, len(A) + 1)), replace=False))]
+        common = len(set(map(tuple, A.tolist())) & set(map(tuple, G.tolist())))
+        assert oracle._nw_match_count(A, G) == common
+    # not monotone: the NW optimum is an LCS, below the set intersection
+    A = np.array([[0, 0], [1, 1]])
+    G = np.array([[1, 1], [0, 0]])
+    assert oracle._nw_match_count(A, G) == 1
