@@ -167,6 +167,50 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
     nuniq = min(nuniq + __popcll(cm), CAPU);
   };
 
+  // the (up to) four entries of every lane at once: their CAS probes are
+  // issued together, so one LDS round trip serves four entries
+  auto insert4 = [&](const MergeEnt &E) {
+    uint32_t h[4];
+    bool pend[4], claimed[4], placed[4];
+    int probes[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const bool act = d < E.deg && E.u[d] < (uint32_t)V;
+      h[d] = act ? (E.u[d] * 0x9E3779B1u) >> (32 - hbits) : 0u;
+      pend[d] = act;
+      claimed[d] = placed[d] = false;
+      probes[d] = 0;
+    }
+    while (__ballot(pend[0] || pend[1] || pend[2] || pend[3]) != 0) {
+      uint32_t old[4];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) old[d] = pend[d] ? atomicCAS(&key[h[d]], HEMPTY, E.u[d]) : HEMPTY;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        if (!pend[d]) continue;
+        if (old[d] == HEMPTY || old[d] == E.u[d]) {
+          claimed[d] = old[d] == HEMPTY;
+          placed[d] = true;
+          pend[d] = false;
+        } else if (++probes[d] >= HS) {
+          pend[d] = false;   // table full: drop
+        } else {
+          h[d] = (h[d] + 1) & (uint32_t)(HS - 1);
+        }
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+      if (placed[d]) atomicAdd(&acc[h[d]], (double)E.v[d]);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const uint64_t cm = __ballot(claimed[d]);
+      const int rank = nuniq + __popcll(cm & ((1ull << lane) - 1ull));
+      if (claimed[d] && rank < CAPU) slots[rank] = (int)h[d];
+      nuniq = min(nuniq + __popcll(cm), CAPU);
+    }
+  };
+
   const int64_t G = gridDim.x;
   int64_t sent = blockIdx.x;
   MergeEnt E = load_ent(load_row(load_tok(load_off(sent))));
@@ -182,9 +226,7 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
 
     nuniq = 0;
     // first 64 tokens: entries 0..3 loaded ahead, further entries here
-#pragma unroll
-    for (int d = 0; d < 4; ++d)
-      if (__ballot(d < cur.deg) != 0) insert(d < cur.deg ? cur.u[d] : HEMPTY, cur.v[d]);
+    insert4(cur);
     for (int q = 4; q < max_deg; ++q) {
       if (__ballot(q < cur.deg) == 0) break;
       uint32_t u = HEMPTY;
@@ -275,7 +317,8 @@ static __device__ __forceinline__ uint32_t a_code(uint32_t u, int r, int pitch, 
 __global__ __launch_bounds__(256) void k_build_a(PlanDev P, const int64_t *__restrict__ src_off,
                                                  const uint2 *__restrict__ merged,
                                                  const int32_t *__restrict__ cnt, uint2 *__restrict__ a_list,
-                                                 int32_t *__restrict__ a_choff, int pitch, int esize, int compact) {
+                                                 int32_t *__restrict__ a_choff, int pitch, int esize, int compact,
+                                                 int64_t *__restrict__ a_base) {
   extern __shared__ __align__(16) char smem[];
   int *off = reinterpret_cast<int *>(smem);  // [nch + 1]
   int *tmp = off + P.nch + 1;                // [256]
@@ -314,6 +357,7 @@ __global__ __launch_bounds__(256) void k_build_a(PlanDev P, const int64_t *__res
   for (int c = threadIdx.x; c <= P.nch; c += 256) choff[c] = off[c];
   __syncthreads();
   const int64_t tile_base = src_off[s0] * (int64_t)P.max_deg;
+  if (threadIdx.x == 0) a_base[rt] = tile_base;
 #pragma unroll
   for (int k = 0; k < ROWS_PER_WAVE; ++k) {
     const int r = wave + 4 * k;
@@ -346,7 +390,8 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
                                                  const int32_t *__restrict__ tgt_tok,
                                                  uint32_t *__restrict__ b_list, int32_t *__restrict__ b_choff,
                                                  int pitch, int esize, int compact, uint2 *__restrict__ mt,
-                                                 int32_t *__restrict__ kcn) {
+                                                 int32_t *__restrict__ kcn, int2 *__restrict__ krng,
+                                                 int64_t *__restrict__ b_base) {
   extern __shared__ __align__(16) char smem[];
   int *off = reinterpret_cast<int *>(smem);        // [nch + 1]
   int *tmp = off + P.nch + 1;                      // [256]
@@ -396,11 +441,27 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
     for (int w = threadIdx.x; w < words; w += 256) ubase[w] = __popc(ubits[w]);
     __syncthreads();
     block_exclusive_scan(ubase, words, tmp);
-    for (int w = threadIdx.x; w < words; w += 256)
-      mt[(int64_t)ct * words + w] = make_uint2(ubits[w], (uint32_t)ubase[w]);
-    if (threadIdx.x == 0) kcn[ct] = (ubase[words] + KC - 1) / KC;
+    // compacted chunk kc covers positions KC kc .. min(KC kc + KC, K) - 1:
+    // its first / last global chunk is the one holding the first / last of
+    // these positions (each written by exactly one thread)
+    const int K = ubase[words];
+    int32_t *rng = reinterpret_cast<int32_t *>(krng + (int64_t)ct * words);
+    for (int w = threadIdx.x; w < words; w += 256) {
+      const uint32_t msk = ubits[w];
+      mt[(int64_t)ct * words + w] = make_uint2(msk, (uint32_t)ubase[w]);
+      if (msk) {
+        const int b0 = ubase[w], b1 = b0 + __popc(msk);   // positions [b0, b1)
+        for (int kc = b0 / KC; kc <= (b1 - 1) / KC; ++kc) {
+          const int first = KC * kc, last = min(KC * kc + KC, K) - 1;
+          if (first >= b0 && first < b1) rng[2 * kc] = w;
+          if (last >= b0 && last < b1) rng[2 * kc + 1] = w;
+        }
+      }
+    }
+    if (threadIdx.x == 0) kcn[ct] = (K + KC - 1) / KC;
     __syncthreads();
   }
+  if (threadIdx.x == 0) b_base[ct] = tgt_off[t0];
   // K chunk and position inside it of word u
   auto kchunk = [&](uint32_t u) -> int {
     if (!compact) return (int)(u / KC);
@@ -520,11 +581,12 @@ hipError_t launch_merge_src(int64_t n_sent, const int64_t *src_off, const int32_
 }
 
 hipError_t launch_build_a(const PlanDev &P, const int64_t *src_off, const uint2 *merged, const int32_t *cnt,
-                          uint2 *a_list, int32_t *a_choff, int pitch, int esize, int compact, hipStream_t st) {
+                          uint2 *a_list, int32_t *a_choff, int pitch, int esize, int compact, int64_t *a_base,
+                          hipStream_t st) {
   if (P.n_rt <= 0) return hipSuccess;
   const size_t lds = sizeof(int) * (size_t)(P.nch + 1 + 256);
   hipLaunchKernelGGL(k_build_a, dim3(P.n_rt), dim3(256), lds, st, P, src_off, merged, cnt, a_list, a_choff,
-                     pitch, esize, compact);
+                     pitch, esize, compact, a_base);
   return hipGetLastError();
 }
 
@@ -535,10 +597,10 @@ size_t build_b_lds_bytes(int nch, int V) {
 
 hipError_t launch_build_b(const PlanDev &P, const int64_t *tgt_off, const int32_t *tgt_tok, uint32_t *b_list,
                           int32_t *b_choff, int pitch, int esize, int compact, uint2 *mt, int32_t *kcn,
-                          hipStream_t st) {
+                          int2 *krng, int64_t *b_base, hipStream_t st) {
   if (P.n_ct <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_build_b, dim3(P.n_ct), dim3(256), build_b_lds_bytes(P.nch, P.V), st, P, tgt_off, tgt_tok,
-                     b_list, b_choff, pitch, esize, compact, mt, kcn);
+                     b_list, b_choff, pitch, esize, compact, mt, kcn, krng, b_base);
   return hipGetLastError();
 }
 

@@ -318,16 +318,17 @@ static __device__ __forceinline__ void score_epilogue(const f32x4 (&acc)[4][4], 
 // Epilogue straight from the accumulators (no LDS): lane l holds rows
 // 16 bi + 4 (l >> 4) + r, column 16 bj + (l & 15) of the tile.  Sentence
 // lengths come from the lane that owns that row / column index.
-static __device__ __forceinline__ void score_epilogue_regs(const f32x4 (&acc)[4][4], const PlanDev &P,
+static __device__ __forceinline__ void score_epilogue_regs(const f32x4 (&acc)[4][4],
                                                            const int64_t *__restrict__ src_off,
                                                            const int64_t *__restrict__ tgt_off, const nwm_scorer &sc,
-                                                           float *__restrict__ S, float *__restrict__ S_raw, int pair,
-                                                           int row0, int rows, int col0, int cols, int64_t s_first,
+                                                           float *__restrict__ Sb, float *__restrict__ Rb, int row0,
+                                                           int rows, int col0, int cols, int64_t s_first,
                                                            int64_t t_first, int m, int lane) {
+  // Sb, Rb: the pair's S and S_raw blocks (Rb may be null)
   const float my_ls = lane < rows ? (float)(src_off[s_first + lane + 1] - src_off[s_first + lane]) : 0.0f;
   const float my_lt = lane < cols ? (float)(tgt_off[t_first + lane + 1] - tgt_off[t_first + lane]) : 0.0f;
-  float *Sp = S + P.s_off[pair] + (int64_t)row0 * m + col0;
-  float *Rp = S_raw ? S_raw + P.s_off[pair] + (int64_t)row0 * m + col0 : nullptr;
+  float *Sp = Sb + (int64_t)row0 * m + col0;
+  float *Rp = Rb ? Rb + (int64_t)row0 * m + col0 : nullptr;
   const float LOG2E = 1.4426950408889634f;
   const int r16 = lane & 15, rq = lane >> 4;
 #pragma unroll
@@ -590,49 +591,45 @@ __global__ __launch_bounds__(64) void k_score_c(PlanDev P, const int64_t *__rest
                                                 const uint2 *__restrict__ a_list, const int32_t *__restrict__ a_choff,
                                                 const uint32_t *__restrict__ b_list,
                                                 const int32_t *__restrict__ b_choff, const uint2 *__restrict__ mt,
-                                                const int32_t *__restrict__ kcn, nwm_scorer sc,
+                                                const int32_t *__restrict__ kcn, const int2 *__restrict__ krng,
+                                                const int64_t *__restrict__ a_base,
+                                                const int64_t *__restrict__ b_base, nwm_scorer sc,
                                                 float *__restrict__ S, float *__restrict__ S_raw, int xcd_map) {
   constexpr int TB = ScoreLds<BF16>::TILE;
   __shared__ __align__(16) char smem[ScoreLdsC<BF16>::BYTES];   // [A tile, B tile]
-  extern __shared__ __align__(16) uint2 dyn[];                  // chunk table [nch], chunk ranges [nch]
+  extern __shared__ __align__(16) uint2 dyn[];                  // chunk table [nch]
   char *At = smem, *Bt = smem + TB;
 
   const int G = P.n_gt;
   const int per = (G + 7) >> 3;
   const int gt = xcd_map ? (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
   if (gt >= G) return;
-  const int rt = P.gt_rt[gt], ct = P.gt_ct[gt];
-  const int pair = P.rt_pair[rt];
-  const int row0 = P.rt_row0[rt], rows = P.rt_rows[rt];
-  const int col0 = P.ct_col0[ct], cols = P.ct_cols[ct];
-  const int64_t s_first = P.sfirst[pair] + row0;
-  const int64_t t_first = P.tfirst[pair] + col0;
-  const int m = P.m[pair];
+  // the tile's metadata in one record; everything else it needs is at most
+  // two dependent loads away
+  const GtMeta g = P.gt_meta[gt];
+  const int rt = g.rt, ct = g.ct;
   const int nch = P.nch;
   const int lane = threadIdx.x;
   const int Kc = kcn[ct];
   uint2 *mtl = dyn;
-  int2 *rng = reinterpret_cast<int2 *>(dyn + nch);
 
-  // stage the column tile's chunk table; compacted chunk -> global chunk range
-  for (int c = lane; c < nch; c += 64) rng[c] = make_int2(0x7fffffff, -1);
+  const uint2 *mtg = mt + (int64_t)ct * nch;
+  const int2 *rng = krng + (int64_t)ct * nch;
+  const int32_t *chA = a_choff + (int64_t)rt * (nch + 1);
+  const int32_t *chB = b_choff + (int64_t)ct * (nch + 1);
+  const uint2 *pa = a_list + a_base[rt];
+  const uint32_t *pb = b_list + b_base[ct];
+  CChunk X, Y, Z;
+  // the first window of chunk ranges and the entries of the first two
+  // chunks go out first (the longest chain of dependent loads); the chunk
+  // table is staged in LDS meanwhile
+  CWin W;
+  cwin_load(W, 0, Kc, rng, chA, chB, lane);
+  cload(X, pa, pb, W, 0, lane);
+  cload(Y, pa, pb, W, 1, lane);
   for (int e = lane; e < ScoreLdsC<BF16>::OPS / 16; e += 64)
     reinterpret_cast<uint4 *>(smem)[e] = make_uint4(0u, 0u, 0u, 0u);
-  wave_sync();
-  const uint2 *mtg = mt + (int64_t)ct * nch;
-  for (int c = lane; c < nch; c += 64) {
-    const uint2 mm = mtg[c];
-    mtl[c] = mm;
-    if (mm.x) {
-      const int k1 = (int)(mm.y >> 5), k2 = (int)((mm.y + (uint32_t)__popc(mm.x) - 1u) >> 5);
-      atomicMin(&rng[k1].x, c);
-      atomicMax(&rng[k1].y, c);
-      if (k2 != k1) {
-        atomicMin(&rng[k2].x, c);
-        atomicMax(&rng[k2].y, c);
-      }
-    }
-  }
+  for (int c = lane; c < nch; c += 64) mtl[c] = mtg[c];
   wave_sync();
 
   f32x4 acc[4][4];
@@ -641,17 +638,12 @@ __global__ __launch_bounds__(64) void k_score_c(PlanDev P, const int64_t *__rest
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  const int32_t *chA = a_choff + (int64_t)rt * (nch + 1);
-  const int32_t *chB = b_choff + (int64_t)ct * (nch + 1);
-  const uint2 *pa = a_list + src_off[s_first] * (int64_t)P.max_deg;
-  const uint32_t *pb = b_list + tgt_off[t_first];
   // padding element (row 0, column KC) no fragment reads: where lanes with
   // nothing to write go, all to one address
   const uint32_t junk = (uint32_t)(KC * (int)sizeof(typename Op<BF16>::T));
   constexpr int NCLR = ScoreLdsC<BF16>::OPS / 16 / 64;
   static_assert(ScoreLdsC<BF16>::OPS % (16 * 64) == 0, "tile clear");
   Frags<BF16> F;
-  CChunk X, Y, Z;
 
   // chunk kc from register set Cur while the chunk after next (of the same
   // window of 64) loads into Nxt; the tiles are cleared whole after their
@@ -669,11 +661,12 @@ __global__ __launch_bounds__(64) void k_score_c(PlanDev P, const int64_t *__rest
   // windows of 64 compacted chunks (one almost always covers the tile); the
   // loads past the window's last chunk read an empty range
   for (int wb = 0; wb < Kc; wb += 64) {
-    CWin W;
-    cwin_load(W, wb, Kc, rng, chA, chB, lane);
+    if (wb > 0) {
+      cwin_load(W, wb, Kc, rng, chA, chB, lane);
+      cload(X, pa, pb, W, wb, lane);
+      cload(Y, pa, pb, W, wb + 1, lane);
+    }
     const int we = min(Kc, wb + 64) - wb;   // chunks in this window
-    cload(X, pa, pb, W, wb, lane);
-    cload(Y, pa, pb, W, wb + 1, lane);
     int k = 0;
     for (; k + 3 <= we; k += 3) {
       NWM_SCORE_CCHUNK(wb + k, X, Z)
@@ -684,8 +677,8 @@ __global__ __launch_bounds__(64) void k_score_c(PlanDev P, const int64_t *__rest
     if (k + 1 < we) NWM_SCORE_CCHUNK(wb + k + 1, Y, X)
   }
 #undef NWM_SCORE_CCHUNK
-  score_epilogue_regs(acc, P, src_off, tgt_off, sc, S, S_raw, pair, row0, rows, col0, cols, s_first, t_first, m,
-                      lane);
+  score_epilogue_regs(acc, src_off, tgt_off, sc, S + g.s_off, S_raw ? S_raw + g.s_off : nullptr, g.row0, g.rows,
+                      g.col0, g.cols, g.s_first, g.t_first, g.m, lane);
 }
 
 size_t score_lds_bytes(int, bool bf16) {
@@ -695,17 +688,18 @@ size_t score_lds_bytes(int, bool bf16) {
 hipError_t launch_score(const PlanDev &P, bool bf16, const int64_t *src_off, const int64_t *tgt_off,
                         const uint2 *a_list, const int32_t *a_choff, const uint32_t *b_list,
                         const int32_t *b_choff, nwm_scorer sc, float *S, float *S_raw, int xcd_map, int compact,
-                        const uint2 *mt, const int32_t *kcn, hipStream_t st) {
+                        const uint2 *mt, const int32_t *kcn, const int2 *krng, const int64_t *a_base,
+                        const int64_t *b_base, hipStream_t st) {
   if (P.n_gt <= 0) return hipSuccess;
   const int grid = xcd_map ? 8 * ((P.n_gt + 7) / 8) : P.n_gt;
   if (compact) {
-    const size_t dyn = 2 * sizeof(uint2) * (size_t)P.nch;
+    const size_t dyn = sizeof(uint2) * (size_t)P.nch;
     if (bf16)
       hipLaunchKernelGGL(k_score_c<true>, dim3(grid), dim3(64), dyn, st, P, src_off, tgt_off, a_list, a_choff,
-                         b_list, b_choff, mt, kcn, sc, S, S_raw, xcd_map);
+                         b_list, b_choff, mt, kcn, krng, a_base, b_base, sc, S, S_raw, xcd_map);
     else
       hipLaunchKernelGGL(k_score_c<false>, dim3(grid), dim3(64), dyn, st, P, src_off, tgt_off, a_list, a_choff,
-                         b_list, b_choff, mt, kcn, sc, S, S_raw, xcd_map);
+                         b_list, b_choff, mt, kcn, krng, a_base, b_base, sc, S, S_raw, xcd_map);
     return hipGetLastError();
   }
   if (bf16)

@@ -18,13 +18,13 @@ namespace nwm {
 hipError_t launch_merge_src(int64_t, const int64_t *, const int32_t *, const int32_t *, const int32_t *,
                             const float *, int, int, int, uint2 *, int32_t *, int, hipStream_t);
 hipError_t launch_build_a(const PlanDev &, const int64_t *, const uint2 *, const int32_t *, uint2 *, int32_t *,
-                          int, int, int, hipStream_t);
+                          int, int, int, int64_t *, hipStream_t);
 hipError_t launch_build_b(const PlanDev &, const int64_t *, const int32_t *, uint32_t *, int32_t *, int, int, int,
-                          uint2 *, int32_t *, hipStream_t);
+                          uint2 *, int32_t *, int2 *, int64_t *, hipStream_t);
 hipError_t build_set_attrs(int nch, int V);
 hipError_t launch_score(const PlanDev &, bool, const int64_t *, const int64_t *, const uint2 *, const int32_t *,
                         const uint32_t *, const int32_t *, nwm_scorer, float *, float *, int, int, const uint2 *,
-                        const int32_t *, hipStream_t);
+                        const int32_t *, const int2 *, const int64_t *, const int64_t *, hipStream_t);
 size_t score_lds_bytes(int nch, bool bf16);
 hipError_t score_set_attrs(int nch_max);
 hipError_t launch_nw_fill(const PlanDev &, const float *, float, float *, char *, uint64_t *, int64_t, int32_t *,
@@ -253,6 +253,22 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   }
   p->n_src = sfirst[B];
   p->n_tgt = tfirst[B];
+  std::vector<GtMeta> gt_meta(gt_rt.size());
+  for (size_t g = 0; g < gt_rt.size(); ++g) {
+    GtMeta &x = gt_meta[g];
+    x.rt = gt_rt[g];
+    x.ct = gt_ct[g];
+    x.pair = rt_pair[x.rt];
+    x.m = p->m[x.pair];
+    x.row0 = rt_row0[x.rt];
+    x.rows = rt_rows[x.rt];
+    x.col0 = ct_col0[x.ct];
+    x.cols = ct_cols[x.ct];
+    x.s_first = sfirst[x.pair] + x.row0;
+    x.t_first = tfirst[x.pair] + x.col0;
+    x.s_off = s_off[x.pair];
+    x.pad = 0;
+  }
   std::vector<int32_t> order(B);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
@@ -307,6 +323,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   size_t i_cp = add(ct_pair.data(), 4 * ct_pair.size()), i_cc = add(ct_col0.data(), 4 * ct_col0.size());
   size_t i_cn = add(ct_cols.data(), 4 * ct_cols.size());
   size_t i_gr = add(gt_rt.data(), 4 * gt_rt.size()), i_gc = add(gt_ct.data(), 4 * gt_ct.size());
+  size_t i_gm = add(gt_meta.data(), sizeof(GtMeta) * gt_meta.size());
   size_t i_do = add(order.data(), 4 * order.size());
   size_t i_ip = add(it_pair.data(), 4 * it_pair.size()), i_is = add(it_strip.data(), 4 * it_strip.size());
   size_t i_bo = add(bnd_off.data(), 8 * (size_t)(B + 1));
@@ -351,6 +368,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   D.n_gt = (int)gt_rt.size();
   D.gt_rt = (const int32_t *)at(i_gr);
   D.gt_ct = (const int32_t *)at(i_gc);
+  D.gt_meta = (const GtMeta *)at(i_gm);
   D.dp_order = (const int32_t *)at(i_do);
   D.n_items = (int)it_pair.size();
   D.it_pair = (const int32_t *)at(i_ip);
@@ -374,6 +392,9 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   W.b_choff = carve(4 * (size_t)D.n_ct * (size_t)(nch + 1));
   W.b_mt = carve(8 * (size_t)D.n_ct * (size_t)nch);
   W.b_kcn = carve(4 * (size_t)D.n_ct);
+  W.b_rng = carve(8 * (size_t)D.n_ct * (size_t)nch);
+  W.a_base = carve(8 * (size_t)D.n_rt);
+  W.b_base = carve(8 * (size_t)D.n_ct);
   W.bwd = carve(16 * ((size_t)B + (size_t)D.n_rt));
   // published rows, + 2 entries (cleared in 16-byte units), + the sink
   W.bnd = carve(8 * ((size_t)bnd_off[B] + 2 + FILL_SINK_SLOTS));
@@ -441,6 +462,9 @@ nwm_status nwm_score_pairs(nwm_plan *p, const nwm_batch *batch, const nwm_dict *
   int32_t *b_choff = (int32_t *)(w + p->ws.b_choff);
   uint2 *b_mt = (uint2 *)(w + p->ws.b_mt);
   int32_t *b_kcn = (int32_t *)(w + p->ws.b_kcn);
+  int2 *b_rng = (int2 *)(w + p->ws.b_rng);
+  int64_t *a_base = (int64_t *)(w + p->ws.a_base);
+  int64_t *b_base = (int64_t *)(w + p->ws.b_base);
   const int compact = p->param[NWM_PARAM_SCORE_COMPACT];
   const bool bf16 = p->prec == NWM_BF16;
   // list entries are LDS byte offsets inside the operand tiles
@@ -460,21 +484,22 @@ nwm_status nwm_score_pairs(nwm_plan *p, const nwm_batch *batch, const nwm_dict *
     if (e == hipSuccess) e = hipStreamWaitEvent(p->aux_stream, p->ev_fork, 0);
     if (e == hipSuccess)
       e = launch_build_b(p->dev, batch->tgt_off, batch->tgt_tok, b_list, b_choff, pitch, esize, compact, b_mt, b_kcn,
-                         p->aux_stream);
+                         b_rng, b_base, p->aux_stream);
     if (e == hipSuccess) e = hipEventRecord(p->ev_join, p->aux_stream);
     Mark mk(p, K_EXPAND, st);
     if (e == hipSuccess)
       e = launch_merge_src(p->n_src, batch->src_off, batch->src_tok, dict->row_off, dict->col, dict->val, p->V,
                            p->max_deg, p->max_entries, merged, cnt, p->param[NWM_PARAM_MERGE_WAVES_PER_CU], st);
     if (e == hipSuccess)
-      e = launch_build_a(p->dev, batch->src_off, merged, cnt, a_list, a_choff, pitch, esize, compact, st);
+      e = launch_build_a(p->dev, batch->src_off, merged, cnt, a_list, a_choff, pitch, esize, compact, a_base, st);
     mk.done();
     if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_join, 0);
     if (e != hipSuccess) return NWM_EDEVICE;
   }
   Mark mk(p, K_SCORE, st);
   hipError_t e = launch_score(p->dev, bf16, batch->src_off, batch->tgt_off, a_list, a_choff, b_list, b_choff, sc,
-                              S, S_raw, p->param[NWM_PARAM_SCORE_XCD_MAP], compact, b_mt, b_kcn, st);
+                              S, S_raw, p->param[NWM_PARAM_SCORE_XCD_MAP], compact, b_mt, b_kcn, b_rng, a_base,
+                              b_base, st);
   mk.done();
   return dev_err(e);
 }

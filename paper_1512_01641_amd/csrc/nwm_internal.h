@@ -28,7 +28,7 @@ constexpr int REG_B = 2;
 // The compacted contraction (K restricted to the column tile's words) holds
 // up to 64 * CREG_A entries of a compacted chunk's A range in registers, for
 // three chunks at a time.
-constexpr int CREG_A = 6;
+constexpr int CREG_A = 5;
 constexpr int CREG_B = 2;
 constexpr int LIST_SLACK_A = 64 * (CREG_A > REG_A ? CREG_A : REG_A);
 constexpr int LIST_SLACK_B = 64 * (CREG_B > REG_B ? CREG_B : REG_B);
@@ -60,6 +60,15 @@ constexpr int DIR_DIAG = 0, DIR_UP = 1, DIR_LEFT = 2;
 // (row) one uint4 = four 32-bit words of 16 steps x 2 bits (first step in the
 // high bits).  ceil((m + 63) / 64) blocks per strip, 1 KiB per block.
 
+// Everything the contraction needs about one tile, in one 64-byte record.
+struct GtMeta {
+  int32_t rt, ct, pair, m;
+  int32_t row0, rows, col0, cols;
+  int64_t s_first, t_first;   // first source / target sentence of the tile
+  int64_t s_off;              // element offset of the pair's S block
+  int64_t pad;
+};
+
 // Device-resident per-pair metadata of a plan.
 struct PlanDev {
   int B;
@@ -80,6 +89,7 @@ struct PlanDev {
   // contraction tiles: (row tile, column tile)
   int n_gt;
   const int32_t *gt_rt, *gt_ct;
+  const GtMeta *gt_meta;
   // DP order (longest first) and DP work items (pair, strip), longest pair first
   const int32_t *dp_order;
   int n_items;
@@ -97,6 +107,9 @@ struct WsLayout {
   size_t b_choff;    // int32 [n_ct * (nch + 1)]
   size_t b_mt;       // uint2 {word mask, words before} [n_ct * nch] (compacted contraction)
   size_t b_kcn;      // int32 [n_ct] compacted chunks per column tile
+  size_t b_rng;      // int32 [n_ct * nch][2] first / last global chunk of each compacted chunk
+  size_t a_base;     // int64 [n_rt] first A-list entry of each row tile
+  size_t b_base;     // int64 [n_ct] first B-list entry of each column tile
   size_t bwd;        // float [B * 4] per-pair partials + float [n_blocks * 4]
   size_t bnd;        // uint64 (value, epoch) boundary rows between strips
   size_t ctl;        // int32 [2]: DP queue head, error flag
