@@ -181,6 +181,7 @@ static __device__ __forceinline__ void run16(StripState &st, const float *ring, 
 
 struct FillArgs {
   int n_items, B;
+  int item0;   // first work item of this launch (its queue counts from 0)
   const int32_t *it_pair, *it_strip, *n, *m;
   const int64_t *s_off, *tb_off, *bnd_off;
 };
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(256) void k_nw_reset(FillArgs A, uint4 *__restrict_
   // published boundary values carry tag 1; clearing them every launch means a
   // value left by an earlier launch is never taken as ready
   for (int64_t k = tid; k < n_bnd16; k += nthr) bnd16[k] = make_uint4(0u, 0u, 0u, 0u);
-  if (tid < 2) ctl[tid] = 0;   // [0] queue head, [1] error flag
+  if (tid < 4) ctl[tid] = 0;   // [0] queue head, [1] error flag, [2] queue head of a second launch
   for (int64_t b = tid; b < A.B; b += nthr) {
     const int n = A.n[b], m = A.m[b];
     // H[n][0] = fl32(n*g), H[0][m] = fl32(m*g), H[0][0] = +0
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(256) void k_nw_reset(FillArgs A, uint4 *__restrict_
 __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restrict__ S, float g,
                                                 float *__restrict__ score, char *__restrict__ tb,
                                                 uint64_t *__restrict__ bnd, uint64_t *__restrict__ sink,
-                                                int32_t *__restrict__ ctl) {
+                                                int32_t *__restrict__ head, int32_t *__restrict__ err) {
   constexpr uint32_t epoch = 1u;   // tag of a published value (the reset clears to 0)
   __shared__ __align__(16) float ring[2 * HALF];
   __shared__ __align__(16) uint64_t winbufA[64], winbufB[64];   // boundary windows (LDS-direct loads)
@@ -211,9 +212,10 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
   uint64_t *my_sink = sink + (int64_t)(blockIdx.x & (FILL_SINK_WAVES - 1)) * 16;   // this wave's line
   for (;;) {
     int item = 0;
-    if (lane == 0) item = atomicAdd(&ctl[0], 1);
+    if (lane == 0) item = atomicAdd(head, 1);
     item = uniform(item);
     if (item >= A.n_items) break;
+    item += A.item0;
     const int b = uniform(A.it_pair[item]);
     const int s_tag = uniform(A.it_strip[item]);
     const int s = s_tag & ~ITEM_HOT;
@@ -380,7 +382,7 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
       const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(st.H), r_last));
       if (lane == 0 && !failed) score[b] = v;
     }
-    if (failed && lane == 0) __hip_atomic_store(&ctl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (failed && lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (hot) __builtin_amdgcn_s_setprio(0);
   }
 }
@@ -422,9 +424,9 @@ static __device__ __forceinline__ uint32_t code_at(uint32_t w0, uint32_t w1, uin
 // it waits for itself at the next block change.  Path cells reach memory in
 // coalesced stores.
 __global__ __launch_bounds__(64) void k_nw_walk(PlanDev P, const char *__restrict__ tb_bits,
-                                                int2 *__restrict__ path, int32_t *__restrict__ n_diag) {
+                                                int2 *__restrict__ path, int32_t *__restrict__ n_diag, int o0) {
   __shared__ int2 lbuf[WALK_LDS];
-  const int b = P.dp_order[blockIdx.x];
+  const int b = P.dp_order[o0 + blockIdx.x];
   const int n = P.n[b], m = P.m[b];
   const int lane = threadIdx.x;
   const int cap = min(n, m);
@@ -536,8 +538,8 @@ __global__ __launch_bounds__(64) void k_nw_walk(PlanDev P, const char *__restric
 
 __global__ __launch_bounds__(64) void k_keep(PlanDev P, const float *__restrict__ S, float thr,
                                              const int2 *__restrict__ path, const int32_t *__restrict__ n_diag,
-                                             int2 *__restrict__ kept, int32_t *__restrict__ n_kept) {
-  const int b = blockIdx.x;
+                                             int2 *__restrict__ kept, int32_t *__restrict__ n_kept, int o0) {
+  const int b = P.dp_order[o0 + blockIdx.x];
   const int n = P.n[b], m = P.m[b];
   const int lane = threadIdx.x;
   const int cap = min(n, m);
@@ -576,12 +578,11 @@ hipError_t fill_set_attrs(int) {
   return hipSuccess;
 }
 
-hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *score, char *tb, uint64_t *bnd,
-                          int64_t n_bnd, int32_t *ctl, int waves_per_cu, hipStream_t st) {
-  if (P.B <= 0) return hipSuccess;
+static FillArgs fill_args(const PlanDev &P) {
   FillArgs A;
   A.n_items = P.n_items;
   A.B = P.B;
+  A.item0 = 0;
   A.it_pair = P.it_pair;
   A.it_strip = P.it_strip;
   A.n = P.n;
@@ -589,37 +590,63 @@ hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *scor
   A.s_off = P.s_off;
   A.tb_off = P.tb_off;
   A.bnd_off = P.bnd_off;
+  return A;
+}
+
+// Clears the published-row region and the queue heads; scores of empty pairs.
+hipError_t launch_nw_reset(const PlanDev &P, float g, float *score, uint64_t *bnd, int64_t n_bnd, int32_t *ctl,
+                           hipStream_t st) {
+  if (P.B <= 0) return hipSuccess;
   const int64_t n16 = (n_bnd + 1) / 2;   // the region is 256-byte aligned and padded
   const int64_t rb = (n16 + 255) / 256;
-  hipLaunchKernelGGL(k_nw_reset, dim3((unsigned)(rb < 2048 ? (rb > 0 ? rb : 1) : 2048)), dim3(256), 0, st, A,
-                     reinterpret_cast<uint4 *>(bnd), n16, ctl, g, score);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || P.n_items <= 0) return e;
+  hipLaunchKernelGGL(k_nw_reset, dim3((unsigned)(rb < 2048 ? (rb > 0 ? rb : 1) : 2048)), dim3(256), 0, st,
+                     fill_args(P), reinterpret_cast<uint4 *>(bnd), n16, ctl, g, score);
+  return hipGetLastError();
+}
+
+// DP items [item0, item0 + n) of the plan, popped from the queue head `head`
+// (cleared by the reset).  Strips of one pair must all be in one launch.
+hipError_t launch_nw_fill_items(const PlanDev &P, const float *S, float g, float *score, char *tb, uint64_t *bnd,
+                                int64_t n_bnd, int32_t *head, int32_t *err, int item0, int n, int waves_per_cu,
+                                hipStream_t st) {
+  if (P.B <= 0 || n <= 0) return hipSuccess;
   if (g_fill_cus == 0) {
-    e = fill_set_attrs(0);
+    hipError_t e = fill_set_attrs(0);
     if (e != hipSuccess) return e;
   }
+  FillArgs A = fill_args(P);
+  A.item0 = item0;
+  A.n_items = n;
   // every wave of the grid is resident at once (the hand-off between strips
   // waits on other waves), so the grid never exceeds the occupancy
   const int per = (waves_per_cu > 0 && waves_per_cu < g_fill_per) ? waves_per_cu : g_fill_per;
   const int full = g_fill_cus * per;
-  const int grid = P.n_items < full ? P.n_items : full;
+  const int grid = n < full ? n : full;
   // the sink: FILL_SINK_WAVES 128-byte lines after the published rows
   uint64_t *sink = reinterpret_cast<uint64_t *>((reinterpret_cast<uintptr_t>(bnd + n_bnd) + 127) & ~(uintptr_t)127);
-  hipLaunchKernelGGL(k_nw_fill, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, sink, ctl);
+  hipLaunchKernelGGL(k_nw_fill, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, sink, head, err);
   return hipGetLastError();
 }
 
-hipError_t launch_nw_walk(const PlanDev &P, const char *tb, int2 *path, int32_t *n_diag, hipStream_t st) {
-  if (P.B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_nw_walk, dim3(P.B), dim3(64), 0, st, P, tb, path, n_diag);
+hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *score, char *tb, uint64_t *bnd,
+                          int64_t n_bnd, int32_t *ctl, int waves_per_cu, hipStream_t st) {
+  hipError_t e = launch_nw_reset(P, g, score, bnd, n_bnd, ctl, st);
+  if (e != hipSuccess) return e;
+  return launch_nw_fill_items(P, S, g, score, tb, bnd, n_bnd, ctl, ctl + 1, 0, P.n_items, waves_per_cu, st);
+}
+
+// pairs dp_order[o0 .. o0 + n)
+hipError_t launch_nw_walk(const PlanDev &P, const char *tb, int2 *path, int32_t *n_diag, int o0, int n,
+                          hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_nw_walk, dim3(n), dim3(64), 0, st, P, tb, path, n_diag, o0);
   return hipGetLastError();
 }
 
 hipError_t launch_keep(const PlanDev &P, const float *S, float thr, const int2 *path, const int32_t *n_diag,
-                       int2 *kept, int32_t *n_kept, hipStream_t st) {
-  if (P.B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_keep, dim3(P.B), dim3(64), 0, st, P, S, thr, path, n_diag, kept, n_kept);
+                       int2 *kept, int32_t *n_kept, int o0, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_keep, dim3(n), dim3(64), 0, st, P, S, thr, path, n_diag, kept, n_kept, o0);
   return hipGetLastError();
 }
 

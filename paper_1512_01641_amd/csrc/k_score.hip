@@ -366,7 +366,8 @@ __global__ __launch_bounds__(64) void k_score(PlanDev P, const int64_t *__restri
                                               const int32_t *__restrict__ a_choff,
                                               const uint32_t *__restrict__ b_list,
                                               const int32_t *__restrict__ b_choff, nwm_scorer sc,
-                                              float *__restrict__ S, float *__restrict__ S_raw, int xcd_map) {
+                                              float *__restrict__ S, float *__restrict__ S_raw, int xcd_map, int g0,
+                                              int G) {
   typedef typename Op<BF16>::T T;
   constexpr int TB = ScoreLds<BF16>::TILE;
   // static LDS: tile addresses are compile-time constants folded into the
@@ -376,10 +377,11 @@ __global__ __launch_bounds__(64) void k_score(PlanDev P, const int64_t *__restri
 
   // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin, so
   // consecutive tiles (same pair, shared lists) go to one XCD and its L2
-  const int G = P.n_gt;
+  // tiles [g0, g0 + G) of the plan
   const int per = (G + 7) >> 3;
-  const int gt = xcd_map ? (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
-  if (gt >= G) return;
+  const int gl = xcd_map ? (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
+  if (gl >= G) return;
+  const int gt = g0 + gl;
   const int rt = P.gt_rt[gt], ct = P.gt_ct[gt];
   const int pair = P.rt_pair[rt];
   const int row0 = P.rt_row0[rt], rows = P.rt_rows[rt];
@@ -594,16 +596,18 @@ __global__ __launch_bounds__(64) void k_score_c(PlanDev P, const int64_t *__rest
                                                 const int32_t *__restrict__ kcn, const int2 *__restrict__ krng,
                                                 const int64_t *__restrict__ a_base,
                                                 const int64_t *__restrict__ b_base, nwm_scorer sc,
-                                                float *__restrict__ S, float *__restrict__ S_raw, int xcd_map) {
+                                                float *__restrict__ S, float *__restrict__ S_raw, int xcd_map,
+                                                int g0, int G) {
   constexpr int TB = ScoreLds<BF16>::TILE;
   __shared__ __align__(16) char smem[ScoreLdsC<BF16>::BYTES];   // [A tile, B tile]
   extern __shared__ __align__(16) uint2 dyn[];                  // chunk table [nch]
   char *At = smem, *Bt = smem + TB;
 
-  const int G = P.n_gt;
+  // tiles [g0, g0 + G) of the plan
   const int per = (G + 7) >> 3;
-  const int gt = xcd_map ? (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
-  if (gt >= G) return;
+  const int gl = xcd_map ? (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
+  if (gl >= G) return;
+  const int gt = g0 + gl;
   // the tile's metadata in one record; everything else it needs is at most
   // two dependent loads away
   const GtMeta g = P.gt_meta[gt];
@@ -689,25 +693,25 @@ hipError_t launch_score(const PlanDev &P, bool bf16, const int64_t *src_off, con
                         const uint2 *a_list, const int32_t *a_choff, const uint32_t *b_list,
                         const int32_t *b_choff, nwm_scorer sc, float *S, float *S_raw, int xcd_map, int compact,
                         const uint2 *mt, const int32_t *kcn, const int2 *krng, const int64_t *a_base,
-                        const int64_t *b_base, hipStream_t st) {
-  if (P.n_gt <= 0) return hipSuccess;
-  const int grid = xcd_map ? 8 * ((P.n_gt + 7) / 8) : P.n_gt;
+                        const int64_t *b_base, int g0, int G, hipStream_t st) {
+  if (G <= 0) return hipSuccess;
+  const int grid = xcd_map ? 8 * ((G + 7) / 8) : G;
   if (compact) {
     const size_t dyn = sizeof(uint2) * (size_t)P.nch;
     if (bf16)
       hipLaunchKernelGGL(k_score_c<true>, dim3(grid), dim3(64), dyn, st, P, src_off, tgt_off, a_list, a_choff,
-                         b_list, b_choff, mt, kcn, krng, a_base, b_base, sc, S, S_raw, xcd_map);
+                         b_list, b_choff, mt, kcn, krng, a_base, b_base, sc, S, S_raw, xcd_map, g0, G);
     else
       hipLaunchKernelGGL(k_score_c<false>, dim3(grid), dim3(64), dyn, st, P, src_off, tgt_off, a_list, a_choff,
-                         b_list, b_choff, mt, kcn, krng, a_base, b_base, sc, S, S_raw, xcd_map);
+                         b_list, b_choff, mt, kcn, krng, a_base, b_base, sc, S, S_raw, xcd_map, g0, G);
     return hipGetLastError();
   }
   if (bf16)
     hipLaunchKernelGGL(k_score<true>, dim3(grid), dim3(64), 0, st, P, src_off, tgt_off, a_list, a_choff, b_list,
-                       b_choff, sc, S, S_raw, xcd_map);
+                       b_choff, sc, S, S_raw, xcd_map, g0, G);
   else
     hipLaunchKernelGGL(k_score<false>, dim3(grid), dim3(64), 0, st, P, src_off, tgt_off, a_list, a_choff, b_list,
-                       b_choff, sc, S, S_raw, xcd_map);
+                       b_choff, sc, S, S_raw, xcd_map, g0, G);
   return hipGetLastError();
 }
 

@@ -24,15 +24,18 @@ hipError_t launch_build_b(const PlanDev &, const int64_t *, const int32_t *, uin
 hipError_t build_set_attrs(int nch, int V);
 hipError_t launch_score(const PlanDev &, bool, const int64_t *, const int64_t *, const uint2 *, const int32_t *,
                         const uint32_t *, const int32_t *, nwm_scorer, float *, float *, int, int, const uint2 *,
-                        const int32_t *, const int2 *, const int64_t *, const int64_t *, hipStream_t);
+                        const int32_t *, const int2 *, const int64_t *, const int64_t *, int, int, hipStream_t);
 size_t score_lds_bytes(int nch, bool bf16);
 hipError_t score_set_attrs(int nch_max);
 hipError_t launch_nw_fill(const PlanDev &, const float *, float, float *, char *, uint64_t *, int64_t, int32_t *,
                           int, hipStream_t);
 hipError_t fill_set_attrs(int);
-hipError_t launch_nw_walk(const PlanDev &, const char *, int2 *, int32_t *, hipStream_t);
-hipError_t launch_keep(const PlanDev &, const float *, float, const int2 *, const int32_t *, int2 *, int32_t *,
-                       hipStream_t);
+hipError_t launch_nw_reset(const PlanDev &, float, float *, uint64_t *, int64_t, int32_t *, hipStream_t);
+hipError_t launch_nw_fill_items(const PlanDev &, const float *, float, float *, char *, uint64_t *, int64_t,
+                                int32_t *, int32_t *, int, int, int, hipStream_t);
+hipError_t launch_nw_walk(const PlanDev &, const char *, int2 *, int32_t *, int, int, hipStream_t);
+hipError_t launch_keep(const PlanDev &, const float *, float, const int2 *, const int32_t *, int2 *, int32_t *, int,
+                       int, hipStream_t);
 hipError_t merge_set_attrs(int max_entries);
 hipError_t launch_union_kept(int, const int64_t *, const int2 *, const int32_t *, const int2 *, const int32_t *,
                              int2 *, int32_t *, hipStream_t);
@@ -92,6 +95,11 @@ struct nwm_plan {
   std::vector<int64_t> it_chain;   // dependency chain of the item's pair
   int64_t max_chain = 0;
   int max_m = 0;
+  // the pairs whose DP dependency chain is at least half the longest come
+  // first in every order (tiles, DP items, pairs); nwm_mine runs their DP on
+  // a second stream while the main stream scores and aligns the others
+  int n_gt_long = 0, n_items_long = 0, n_pairs_long = 0;
+  hipEvent_t ev_long = nullptr, ev_long_done = nullptr;
   std::vector<int32_t> n, m;
   void *dmeta = nullptr;
   PlanDev dev{};
@@ -251,6 +259,31 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
         gt_ct.push_back(ct0 + ci);
       }
   }
+  // dependency chain of a pair's DP: one hand-off of ~80 steps per strip
+  // plus the m + 63 steps of the last strip
+  auto chain = [&](int b) { return (int64_t)((p->n[b] + 63) / 64 - 1) * 80 + p->m[b] + 63; };
+  p->max_chain = 0;
+  for (int b = 0; b < B; ++b)
+    if (p->n[b] > 0 && p->m[b] > 0) p->max_chain = std::max(p->max_chain, chain(b));
+  std::vector<char> is_long(B, 0);
+  for (int b = 0; b < B; ++b)
+    is_long[b] = p->n[b] > 0 && p->m[b] > 0 && p->max_chain > 0 && 2 * chain(b) >= p->max_chain;
+  {
+    // tiles of the long pairs first (stable)
+    std::vector<int32_t> r2, c2;
+    r2.reserve(gt_rt.size());
+    c2.reserve(gt_ct.size());
+    for (int pass = 0; pass < 2; ++pass)
+      for (size_t g = 0; g < gt_rt.size(); ++g)
+        if ((is_long[rt_pair[gt_rt[g]]] != 0) == (pass == 0)) {
+          r2.push_back(gt_rt[g]);
+          c2.push_back(gt_ct[g]);
+        }
+    gt_rt.swap(r2);
+    gt_ct.swap(c2);
+    p->n_gt_long = 0;
+    for (size_t g = 0; g < gt_rt.size(); ++g) p->n_gt_long += is_long[rt_pair[gt_rt[g]]] ? 1 : 0;
+  }
   p->n_src = sfirst[B];
   p->n_tgt = tfirst[B];
   std::vector<GtMeta> gt_meta(gt_rt.size());
@@ -269,11 +302,17 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
     x.s_off = s_off[x.pair];
     x.pad = 0;
   }
+  // pair order of the DP, the walk and the keep: long pairs first (longest
+  // chain first), then the others by cells, largest first
   std::vector<int32_t> order(B);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    if (is_long[a] != is_long[c]) return is_long[a] > is_long[c];
+    if (is_long[a]) return chain(a) > chain(c);
     return (int64_t)p->n[a] * p->m[a] > (int64_t)p->n[c] * p->m[c];
   });
+  p->n_pairs_long = 0;
+  for (int b = 0; b < B; ++b) p->n_pairs_long += is_long[b] ? 1 : 0;
   // DP work items: every strip of every non-empty pair, longest pair first;
   // boundary rows between consecutive strips
   std::vector<int32_t> it_pair, it_strip;
@@ -283,14 +322,8 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
     const int64_t links = ns > 0 ? ns - 1 : 0;
     bnd_off[b + 1] = bnd_off[b] + links * bnd_stride(p->m[b]);
   }
-  // the pairs whose strip chain is within 2x of the longest one run their
-  // strips at raised wave priority: that chain bounds the DP's duration
-  // (chain ~ one hand-off of ~80 steps per strip + the m + 63 steps of the
-  // last strip)
-  auto chain = [&](int b) { return (int64_t)((p->n[b] + 63) / 64 - 1) * 80 + p->m[b] + 63; };
-  p->max_chain = 0;
-  for (int b = 0; b < B; ++b)
-    if (p->n[b] > 0 && p->m[b] > 0) p->max_chain = std::max(p->max_chain, chain(b));
+  // DP items in pair order (so the long pairs' strips come first); strips
+  // of pairs on the longest chains run at raised wave priority (hot_flags)
   for (int q = 0; q < B; ++q) {
     const int b = order[q];
     if (p->n[b] <= 0 || p->m[b] <= 0) continue;
@@ -299,6 +332,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
       p->it_strip.push_back(s);
       p->it_chain.push_back(chain(b));
     }
+    if (is_long[b]) p->n_items_long = (int)it_pair.size();
   }
   hot_flags(p, it_strip);
   // ---- device metadata: one allocation -----------------------------------------
@@ -399,7 +433,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   // published rows, + 2 entries (cleared in 16-byte units), + the sink
   W.bnd = carve(8 * ((size_t)bnd_off[B] + 2 + FILL_SINK_SLOTS));
   p->n_bnd = bnd_off[B] + 2;
-  W.ctl = carve(8);
+  W.ctl = carve(16);
   W.total = o;
   p->sizes.S_elems = (size_t)s_off[B];
   p->sizes.kept_cap = (size_t)p_off[B];
@@ -430,6 +464,8 @@ void nwm_plan_destroy(nwm_plan *plan) {
   if (plan->aux_stream) (void)hipStreamDestroy(plan->aux_stream);
   if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
   if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
+  if (plan->ev_long) (void)hipEventDestroy(plan->ev_long);
+  if (plan->ev_long_done) (void)hipEventDestroy(plan->ev_long_done);
   if (plan->dmeta) (void)hipFree(plan->dmeta);
   delete plan;
 }
@@ -443,8 +479,10 @@ static nwm_status check_batch(const nwm_plan *p, const nwm_batch *b) {
   return NWM_OK;
 }
 
-nwm_status nwm_score_pairs(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, nwm_scorer sc, float *S,
-                           float *S_raw, void *ws, void *stream) {
+// Merged dictionary rows and tile lists of a batch (the expansion), then the
+// contraction of tiles [g0, g0 + G).
+static nwm_status check_score_args(const nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, nwm_scorer sc,
+                                   const float *S, const void *ws) {
   if (!p || !dict) return NWM_EINVAL;
   nwm_status s = check_batch(p, batch);
   if (s != NWM_OK) return s;
@@ -452,7 +490,10 @@ nwm_status nwm_score_pairs(nwm_plan *p, const nwm_batch *batch, const nwm_dict *
   if (!finite(sc.w0) || !finite(sc.w1) || !finite(sc.b)) return NWM_EINVAL;
   if (p->sizes.S_elems == 0) return NWM_OK;
   if (!S || !ws || !dict->row_off || !dict->col || !dict->val) return NWM_EINVAL;
-  hipStream_t st = (hipStream_t)stream;
+  return NWM_OK;
+}
+
+static hipError_t expand_lists(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, void *ws, hipStream_t st) {
   char *w = static_cast<char *>(ws);
   uint2 *merged = (uint2 *)(w + p->ws.a_merged);
   int32_t *cnt = (int32_t *)(w + p->ws.a_cnt);
@@ -470,37 +511,58 @@ nwm_status nwm_score_pairs(nwm_plan *p, const nwm_batch *batch, const nwm_dict *
   // list entries are LDS byte offsets inside the operand tiles
   const int pitch = bf16 ? PITCH_BF16 : PITCH_F32;
   const int esize = bf16 ? 2 : 4;
-  {
-    // The target-side lists do not depend on the source side: they are built
-    // on the plan's second stream, forked from and joined back to `st` by
-    // events (under graph capture: a parallel branch of the graph).
-    if (!p->aux_stream) {
-      if (hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking) != hipSuccess ||
-          hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
-          hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess)
-        return NWM_EDEVICE;
-    }
-    hipError_t e = hipEventRecord(p->ev_fork, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(p->aux_stream, p->ev_fork, 0);
-    if (e == hipSuccess)
-      e = launch_build_b(p->dev, batch->tgt_off, batch->tgt_tok, b_list, b_choff, pitch, esize, compact, b_mt, b_kcn,
-                         b_rng, b_base, p->aux_stream);
-    if (e == hipSuccess) e = hipEventRecord(p->ev_join, p->aux_stream);
-    Mark mk(p, K_EXPAND, st);
-    if (e == hipSuccess)
-      e = launch_merge_src(p->n_src, batch->src_off, batch->src_tok, dict->row_off, dict->col, dict->val, p->V,
-                           p->max_deg, p->max_entries, merged, cnt, p->param[NWM_PARAM_MERGE_WAVES_PER_CU], st);
-    if (e == hipSuccess)
-      e = launch_build_a(p->dev, batch->src_off, merged, cnt, a_list, a_choff, pitch, esize, compact, a_base, st);
-    mk.done();
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_join, 0);
-    if (e != hipSuccess) return NWM_EDEVICE;
-  }
-  Mark mk(p, K_SCORE, st);
-  hipError_t e = launch_score(p->dev, bf16, batch->src_off, batch->tgt_off, a_list, a_choff, b_list, b_choff, sc,
-                              S, S_raw, p->param[NWM_PARAM_SCORE_XCD_MAP], compact, b_mt, b_kcn, b_rng, a_base,
-                              b_base, st);
+  // The target-side lists do not depend on the source side: they are built
+  // on the plan's second stream, forked from and joined back to `st` by
+  // events (under graph capture: a parallel branch of the graph).
+  hipError_t e = hipEventRecord(p->ev_fork, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(p->aux_stream, p->ev_fork, 0);
+  if (e == hipSuccess)
+    e = launch_build_b(p->dev, batch->tgt_off, batch->tgt_tok, b_list, b_choff, pitch, esize, compact, b_mt, b_kcn,
+                       b_rng, b_base, p->aux_stream);
+  if (e == hipSuccess) e = hipEventRecord(p->ev_join, p->aux_stream);
+  Mark mk(p, K_EXPAND, st);
+  if (e == hipSuccess)
+    e = launch_merge_src(p->n_src, batch->src_off, batch->src_tok, dict->row_off, dict->col, dict->val, p->V,
+                         p->max_deg, p->max_entries, merged, cnt, p->param[NWM_PARAM_MERGE_WAVES_PER_CU], st);
+  if (e == hipSuccess)
+    e = launch_build_a(p->dev, batch->src_off, merged, cnt, a_list, a_choff, pitch, esize, compact, a_base, st);
   mk.done();
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_join, 0);
+  return e;
+}
+
+static hipError_t score_tiles(nwm_plan *p, const nwm_batch *batch, nwm_scorer sc, float *S, float *S_raw, void *ws,
+                              int g0, int G, hipStream_t st) {
+  char *w = static_cast<char *>(ws);
+  Mark mk(p, K_SCORE, st);
+  hipError_t e = launch_score(p->dev, p->prec == NWM_BF16, batch->src_off, batch->tgt_off, (uint2 *)(w + p->ws.a_list),
+                              (int32_t *)(w + p->ws.a_choff), (uint32_t *)(w + p->ws.b_list),
+                              (int32_t *)(w + p->ws.b_choff), sc, S, S_raw, p->param[NWM_PARAM_SCORE_XCD_MAP],
+                              p->param[NWM_PARAM_SCORE_COMPACT], (uint2 *)(w + p->ws.b_mt),
+                              (int32_t *)(w + p->ws.b_kcn), (int2 *)(w + p->ws.b_rng), (int64_t *)(w + p->ws.a_base),
+                              (int64_t *)(w + p->ws.b_base), g0, G, st);
+  mk.done();
+  return e;
+}
+
+static hipError_t ensure_streams(nwm_plan *p) {
+  if (p->aux_stream) return hipSuccess;
+  hipError_t e = hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_long, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_long_done, hipEventDisableTiming);
+  return e;
+}
+
+nwm_status nwm_score_pairs(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, nwm_scorer sc, float *S,
+                           float *S_raw, void *ws, void *stream) {
+  nwm_status s = check_score_args(p, batch, dict, sc, S, ws);
+  if (s != NWM_OK || p->sizes.S_elems == 0) return s;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = ensure_streams(p);
+  if (e == hipSuccess) e = expand_lists(p, batch, dict, ws, st);
+  if (e == hipSuccess) e = score_tiles(p, batch, sc, S, S_raw, ws, 0, p->dev.n_gt, st);
   return dev_err(e);
 }
 
@@ -527,8 +589,8 @@ nwm_status nwm_align_batch(nwm_plan *p, const float *S, float gap, float thresho
   if (e != hipSuccess) return NWM_EDEVICE;
   {
     Mark mk(p, K_WALK, st);
-    e = launch_nw_walk(p->dev, tbc, path, n_diag, st);
-    if (e == hipSuccess) e = launch_keep(p->dev, S, threshold, path, n_diag, (int2 *)kept, n_kept, st);
+    e = launch_nw_walk(p->dev, tbc, path, n_diag, 0, p->B, st);
+    if (e == hipSuccess) e = launch_keep(p->dev, S, threshold, path, n_diag, (int2 *)kept, n_kept, 0, p->B, st);
     mk.done();
   }
   return dev_err(e);
@@ -618,14 +680,64 @@ nwm_status nwm_plan_set_graph(nwm_plan *p, int on) {
   return NWM_OK;
 }
 
+// The whole path for nwm_mine.  The pairs with the longest DP dependency
+// chains (first in every order of the plan) are scored first; their fill,
+// walk and keep then run on the plan's second stream while the main stream
+// scores and aligns the other pairs, so the long chains overlap the rest of
+// the batch instead of running alone at the end.  Every kernel computes the
+// same values as in nwm_score_pairs + nwm_align_batch.
+static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, nwm_scorer sc, float gap,
+                            float threshold, float *S, float *S_raw, float *score, int32_t *n_diag, int32_t *kept,
+                            int32_t *n_kept, void *tb, void *ws, hipStream_t st) {
+  nwm_status s = check_score_args(p, batch, dict, sc, S, ws);
+  if (s != NWM_OK) return s;
+  if (!finite(gap) || !finite(threshold)) return NWM_EINVAL;
+  if (p->B == 0) return NWM_OK;
+  if (!score || !n_diag || !n_kept || !ws) return NWM_EINVAL;
+  if (p->sizes.kept_cap > 0 && (!kept || !tb)) return NWM_EINVAL;
+  char *w = static_cast<char *>(ws);
+  char *tbc = static_cast<char *>(tb);
+  int2 *path = tbc ? (int2 *)(tbc + p->dev.path_base) : nullptr;
+  uint64_t *bnd = (uint64_t *)(w + p->ws.bnd);
+  int32_t *ctl = (int32_t *)(w + p->ws.ctl);
+  const int wpc = p->param[NWM_PARAM_FILL_WAVES_PER_CU];
+  const PlanDev &D = p->dev;
+  hipError_t e = ensure_streams(p);
+  if (e == hipSuccess && p->sizes.S_elems > 0) e = expand_lists(p, batch, dict, ws, st);
+  if (e == hipSuccess) e = launch_nw_reset(D, gap, score, bnd, p->n_bnd, ctl, st);
+  const int gl = p->n_gt_long, il = p->n_items_long, ol = p->n_pairs_long;
+  if (e == hipSuccess && ol > 0) {
+    if (p->sizes.S_elems > 0) e = score_tiles(p, batch, sc, S, S_raw, ws, 0, gl, st);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_long, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->aux_stream, p->ev_long, 0);
+    if (e == hipSuccess)
+      e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl + 2, ctl + 1, 0, il, wpc, p->aux_stream);
+    if (e == hipSuccess) e = launch_nw_walk(D, tbc, path, n_diag, 0, ol, p->aux_stream);
+    if (e == hipSuccess) e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, 0, ol, p->aux_stream);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_long_done, p->aux_stream);
+  }
+  if (e == hipSuccess && p->sizes.S_elems > 0) e = score_tiles(p, batch, sc, S, S_raw, ws, gl, D.n_gt - gl, st);
+  if (e == hipSuccess)
+    e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl, ctl + 1, il, D.n_items - il, wpc, st);
+  if (e == hipSuccess) e = launch_nw_walk(D, tbc, path, n_diag, ol, p->B - ol, st);
+  if (e == hipSuccess) e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, ol, p->B - ol, st);
+  if (e == hipSuccess && ol > 0) e = hipStreamWaitEvent(st, p->ev_long_done, 0);
+  return dev_err(e);
+}
+
 nwm_status nwm_mine(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, nwm_scorer sc, float gap,
                     float threshold, float *S, float *S_raw, float *score, int32_t *n_diag, int32_t *kept,
                     int32_t *n_kept, void *tb, void *ws, void *stream) {
   if (!p) return NWM_EINVAL;
   if (!p->graph_on) {
-    nwm_status s = nwm_score_pairs(p, batch, dict, sc, S, S_raw, ws, stream);
-    if (s != NWM_OK) return s;
-    return nwm_align_batch(p, S, gap, threshold, score, n_diag, kept, n_kept, tb, ws, stream);
+    if (p->timer.on) {
+      // per-kernel timing: one kernel at a time on the caller's stream
+      nwm_status s = nwm_score_pairs(p, batch, dict, sc, S, S_raw, ws, stream);
+      if (s != NWM_OK) return s;
+      return nwm_align_batch(p, S, gap, threshold, score, n_diag, kept, n_kept, tb, ws, stream);
+    }
+    return mine_path(p, batch, dict, sc, gap, threshold, S, S_raw, score, n_diag, kept, n_kept, tb, ws,
+                     (hipStream_t)stream);
   }
   if (!batch || !dict) return NWM_EINVAL;
   uint32_t w0b, w1b, bb, gb, tb_;
@@ -649,10 +761,11 @@ nwm_status nwm_mine(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, n
     }
     if (!p->cap_stream && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
       return NWM_EDEVICE;
+    if (ensure_streams(p) != hipSuccess) return NWM_EDEVICE;
     if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return NWM_EDEVICE;
     p->capturing = true;
-    nwm_status s = nwm_score_pairs(p, batch, dict, sc, S, S_raw, ws, p->cap_stream);
-    if (s == NWM_OK) s = nwm_align_batch(p, S, gap, threshold, score, n_diag, kept, n_kept, tb, ws, p->cap_stream);
+    nwm_status s = mine_path(p, batch, dict, sc, gap, threshold, S, S_raw, score, n_diag, kept, n_kept, tb, ws,
+                             p->cap_stream);
     p->capturing = false;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(p->cap_stream, &g);

@@ -90,3 +90,31 @@ def test_graph_replay_reads_current_inputs():
     torch.cuda.synchronize()
     _assert_same(r2, _snapshot(e, b1.B), e.p_off, b1.B, "after token update")
     assert not np.array_equal(r1["S"], r2["S"])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_overlapped_mine_matches_separate_entry_points(prec):
+    # nwm_mine without graphs runs the long-chain pairs' DP on a second
+    # stream, overlapped with the other pairs; the results equal
+    # nwm_score_pairs + nwm_align_batch bit for bit.  The batch mixes a few
+    # long pairs (several strips) with many short ones, and empty sides.
+    import torch
+    import paper_1512_01641_amd as nw
+    n = [700, 40, 0, 65, 650, 30, 128, 7, 20, 300] * 6
+    m = [690, 35, 9, 70, 600, 0, 129, 8, 25, 310] * 6
+    b = corpus.make_batch(2, sizes=(n, m))
+    ctx = nw.Context(0)
+    db = nw.DeviceBatch.from_host(b, "cuda:0")
+    dd = nw.DeviceDict.from_host(b, "cuda:0")
+    eager = nw.Miner(ctx, db, dd, prec)
+    eager.mine(b.scorer, b.gap, b.threshold, want_raw=True)
+    torch.cuda.synchronize()
+    ref = _snapshot(eager, b.B)
+    o = nw.Miner(ctx, db, dd, prec)
+    for rep in range(3):
+        for t in (o.S, o.S_raw, o.score, o.n_diag, o.n_kept, o.kept):
+            t.fill_(-5)
+        nw.mine(o.plan, db, dd, b.scorer, b.gap, b.threshold, o.S, o.S_raw, o.score, o.n_diag, o.kept, o.n_kept,
+                o.tb, o.ws)
+        torch.cuda.synchronize()
+        _assert_same(_snapshot(o, b.B), ref, eager.p_off, b.B, "overlapped %d" % rep)
