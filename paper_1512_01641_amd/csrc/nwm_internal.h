@@ -7,22 +7,20 @@
 namespace nwm {
 
 // ---- tiling of the similarity contraction --------------------------------
-// One workgroup computes a TM x TN tile of S for one document pair; the K
-// dimension (the vocabulary) is walked in chunks of KC words.  Each of the
-// four waves owns every fourth chunk and keeps private LDS operand tiles, so
-// the K loop needs no workgroup barrier.
+// One wave computes a TM x TN tile of S for one document pair; the K
+// dimension (the vocabulary, or the tile's target-side vocabulary) is walked
+// in chunks of KC words.
 constexpr int TM = 64;
 constexpr int TN = 64;
 constexpr int KC = 32;
-constexpr int GEMM_WAVES = 4;
-constexpr int GEMM_THREADS = 64 * GEMM_WAVES;
 // LDS row pitch (elements) of the dense operand tiles.
 constexpr int PITCH_BF16 = KC + 8;   // 80 B rows: conflict-free ds_read_b128
 constexpr int PITCH_F32 = KC + 4;    // 144 B rows
 
 // List entries of one K chunk held in registers per lane by the contraction
-// (A: 128 entries, B: 128).  Every chunk load reads that many entries from
-// the chunk start, so the lists carry that much slack at their end.
+// over the whole vocabulary (A: 128 entries, B: 128).  Every chunk load reads
+// that many entries from the chunk start, so the lists carry that much slack
+// at their end.
 constexpr int REG_A = 2;
 constexpr int REG_B = 2;
 // The compacted contraction (K restricted to the column tile's words) holds
@@ -32,14 +30,11 @@ constexpr int CREG_A = 5;
 constexpr int CREG_B = 2;
 constexpr int LIST_SLACK_A = 64 * (CREG_A > REG_A ? CREG_A : REG_A);
 constexpr int LIST_SLACK_B = 64 * (CREG_B > REG_B ? CREG_B : REG_B);
-// LDS staging capacity of tile lists (entries) per K segment.
-constexpr int CAP_A = 2048;
-constexpr int CAP_B = 2048;
 
 // ---- dictionary-row merge ---------------------------------------------------
-constexpr int MERGE_SLOTS = 1024;     // tokens * max_deg per sentence
-constexpr int MAX_V = 32768;          // u16 owner table in LDS
-constexpr int MAX_DEG = 64;
+constexpr int MERGE_SLOTS = 1024;     // bound on tokens x max_deg per source sentence
+constexpr int MAX_V = 32768;          // vocabulary bound (LDS tables of V / 32 words per tile)
+constexpr int MAX_DEG = 64;           // dictionary entries per word
 
 // ---- NW wavefront -----------------------------------------------------------
 constexpr int BND_PAD = 192;          // slack slots after each published boundary row
@@ -50,8 +45,8 @@ __host__ __device__ inline int64_t bnd_stride(int m) { return ((int64_t)m + BND_
 // lines.  The sink follows the published rows, 128-byte aligned.
 constexpr int FILL_SINK_WAVES = 1024;
 constexpr int64_t FILL_SINK_SLOTS = (int64_t)FILL_SINK_WAVES * 16 + 16;   // uint64 entries, incl. alignment slack
-constexpr int MAX_M = 1 << 22;
-constexpr int32_t ITEM_HOT = 1 << 30;   // DP item flag: strip of a critical-chain pair        // per-pair target sentences (64-row strip of S < 1 GiB)
+constexpr int MAX_M = 1 << 22;           // target sentences per pair (a 64-row strip of S stays below 1 GiB)
+constexpr int32_t ITEM_HOT = 1 << 30;   // DP item flag: strip of a critical-chain pair
 
 // Direction codes of the traceback.
 constexpr int DIR_DIAG = 0, DIR_UP = 1, DIR_LEFT = 2;
