@@ -38,19 +38,20 @@ constexpr uint32_t HEMPTY = 0xFFFFFFFFu;
 // read 0), so the wait counts stay exact; validity is applied when a value
 // is used.
 struct MergeOff {
+  int64_t id;       // the sentence
   int64_t t0, t1;   // as loaded; the length is formed where it is used
   bool ok;
 };
 struct MergeTok {
-  int64_t t0;
+  int64_t id, t0;
   int len, tok;
 };
 struct MergeRow {
-  int64_t t0;
+  int64_t id, t0;
   int len, e0, e1;   // row [e0, e1) of the lane's token (e1 = e0 if none)
 };
 struct MergeEnt {
-  int64_t t0;
+  int64_t id, t0;
   int len, e0, deg;
   uint32_t u[4];
   float v[4];
@@ -69,7 +70,8 @@ static __device__ __forceinline__ uint32_t buf_u32(__amdgpu_buffer_rsrc_t r, uin
 // rounded to FP32 once on the way out.  A sentence longer than the caller's
 // max_sent_tokens (a contract violation) cannot hang or write out of bounds:
 // a full table or slot list drops entries.
-__global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t *__restrict__ src_off,
+__global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t *__restrict__ sent_ids,
+                                                  const int64_t *__restrict__ src_off,
                                                   const int32_t *__restrict__ src_tok,
                                                   const int32_t *__restrict__ d_row_off,
                                                   const int32_t *__restrict__ d_col, const float *__restrict__ d_val,
@@ -96,16 +98,19 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
 
   // unconditional (clamped) scalar loads: nothing waits on them before the
   // next sentence uses them
+  // sentence number `sent` of this launch is sentence sent_ids[sent]
   auto load_off = [&](int64_t sent) {
     MergeOff O;
-    const int64_t k = sent < n_sent ? sent : n_sent - 1;
-    O.t0 = src_off[k];
-    O.t1 = src_off[k + 1];
+    const int64_t id = sent_ids[sent < n_sent ? sent : n_sent - 1];
+    O.id = id;
+    O.t0 = src_off[id];
+    O.t1 = src_off[id + 1];
     O.ok = sent < n_sent;
     return O;
   };
   auto load_tok = [&](const MergeOff &O) {
     MergeTok T;
+    T.id = O.id;
     T.t0 = O.t0;
     T.len = O.ok ? (int)(O.t1 - O.t0) : 0;
     // a buffer over this sentence's first 64 tokens
@@ -116,6 +121,7 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
   };
   auto load_row = [&](const MergeTok &T) {
     MergeRow R;
+    R.id = T.id;
     R.t0 = T.t0;
     R.len = T.len;
     const bool ok = lane < T.len && (unsigned)T.tok < (unsigned)V;
@@ -126,6 +132,7 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
   };
   auto load_ent = [&](const MergeRow &R) {
     MergeEnt E;
+    E.id = R.id;
     E.t0 = R.t0;
     E.len = R.len;
     E.e0 = R.e0;
@@ -271,7 +278,7 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
       key[h] = HEMPTY;
       acc[h] = 0.0;
     }
-    if (lane == 0) cnt[sent] = nuniq;
+    if (lane == 0) cnt[cur.id] = nuniq;
     wave_sync();
   }
 }
@@ -318,11 +325,11 @@ __global__ __launch_bounds__(256) void k_build_a(PlanDev P, const int64_t *__res
                                                  const uint2 *__restrict__ merged,
                                                  const int32_t *__restrict__ cnt, uint2 *__restrict__ a_list,
                                                  int32_t *__restrict__ a_choff, int pitch, int esize, int compact,
-                                                 int64_t *__restrict__ a_base) {
+                                                 int64_t *__restrict__ a_base, int r0) {
   extern __shared__ __align__(16) char smem[];
   int *off = reinterpret_cast<int *>(smem);  // [nch + 1]
   int *tmp = off + P.nch + 1;                // [256]
-  const int rt = blockIdx.x;
+  const int rt = r0 + (int)blockIdx.x;
   const int pair = P.rt_pair[rt];
   const int rows = P.rt_rows[rt];
   const int64_t s0 = P.sfirst[pair] + P.rt_row0[rt];
@@ -391,7 +398,7 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
                                                  uint32_t *__restrict__ b_list, int32_t *__restrict__ b_choff,
                                                  int pitch, int esize, int compact, uint2 *__restrict__ mt,
                                                  int32_t *__restrict__ kcn, int2 *__restrict__ krng,
-                                                 int64_t *__restrict__ b_base) {
+                                                 int64_t *__restrict__ b_base, int c0) {
   extern __shared__ __align__(16) char smem[];
   int *off = reinterpret_cast<int *>(smem);        // [nch + 1]
   int *tmp = off + P.nch + 1;                      // [256]
@@ -399,7 +406,7 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
   const int words = (P.V + 31) / 32;
   int *ubase = reinterpret_cast<int *>(bits + 4 * words);    // [words + 1] (compact)
   uint32_t *ubits = reinterpret_cast<uint32_t *>(ubase + words + 1);   // [words] (compact)
-  const int ct = blockIdx.x;
+  const int ct = c0 + (int)blockIdx.x;
   const int pair = P.ct_pair[ct];
   const int cols = P.ct_cols[ct];
   const int64_t t0 = P.tfirst[pair] + P.ct_col0[ct];
@@ -555,10 +562,11 @@ size_t merge_lds_bytes(int hbits) {
   return hs * (sizeof(double) + sizeof(uint32_t)) + (hs / 2) * sizeof(int);
 }
 
-hipError_t launch_merge_src(int64_t n_sent, const int64_t *src_off, const int32_t *src_tok,
-                            const int32_t *d_row_off, const int32_t *d_col, const float *d_val, int V,
-                            int max_deg, int max_entries, uint2 *merged, int32_t *cnt, int waves_per_cu,
-                            hipStream_t st) {
+// Sentences sent_ids[k0 .. k0 + n_sent).
+hipError_t launch_merge_src(int64_t n_sent, const int64_t *sent_ids, int64_t k0, const int64_t *src_off,
+                            const int32_t *src_tok, const int32_t *d_row_off, const int32_t *d_col,
+                            const float *d_val, int V, int max_deg, int max_entries, uint2 *merged, int32_t *cnt,
+                            int waves_per_cu, hipStream_t st) {
   if (n_sent <= 0) return hipSuccess;
   const int hb = merge_hbits(max_entries);
   const size_t lds = merge_lds_bytes(hb);
@@ -575,18 +583,19 @@ hipError_t launch_merge_src(int64_t n_sent, const int64_t *src_off, const int32_
   if (waves_per_cu > 0 && waves_per_cu < per) per = waves_per_cu;
   const int64_t want = (int64_t)cus * per;
   const int grid = (int)(n_sent < want ? n_sent : want);
-  hipLaunchKernelGGL(k_merge_src, dim3(grid), dim3(64), lds, st, n_sent, src_off, src_tok, d_row_off, d_col, d_val,
-                     V, max_deg, hb, merged, cnt);
+  hipLaunchKernelGGL(k_merge_src, dim3(grid), dim3(64), lds, st, n_sent, sent_ids + k0, src_off, src_tok, d_row_off,
+                     d_col, d_val, V, max_deg, hb, merged, cnt);
   return hipGetLastError();
 }
 
+// Row tiles [r0, r0 + n).
 hipError_t launch_build_a(const PlanDev &P, const int64_t *src_off, const uint2 *merged, const int32_t *cnt,
                           uint2 *a_list, int32_t *a_choff, int pitch, int esize, int compact, int64_t *a_base,
-                          hipStream_t st) {
-  if (P.n_rt <= 0) return hipSuccess;
+                          int r0, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
   const size_t lds = sizeof(int) * (size_t)(P.nch + 1 + 256);
-  hipLaunchKernelGGL(k_build_a, dim3(P.n_rt), dim3(256), lds, st, P, src_off, merged, cnt, a_list, a_choff,
-                     pitch, esize, compact, a_base);
+  hipLaunchKernelGGL(k_build_a, dim3(n), dim3(256), lds, st, P, src_off, merged, cnt, a_list, a_choff, pitch, esize,
+                     compact, a_base, r0);
   return hipGetLastError();
 }
 
@@ -595,12 +604,13 @@ size_t build_b_lds_bytes(int nch, int V) {
   return sizeof(int) * (size_t)(nch + 1 + 256) + sizeof(uint32_t) * (4 * words + 2 * words + 1);
 }
 
+// Column tiles [c0, c0 + n).
 hipError_t launch_build_b(const PlanDev &P, const int64_t *tgt_off, const int32_t *tgt_tok, uint32_t *b_list,
                           int32_t *b_choff, int pitch, int esize, int compact, uint2 *mt, int32_t *kcn,
-                          int2 *krng, int64_t *b_base, hipStream_t st) {
-  if (P.n_ct <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_build_b, dim3(P.n_ct), dim3(256), build_b_lds_bytes(P.nch, P.V), st, P, tgt_off, tgt_tok,
-                     b_list, b_choff, pitch, esize, compact, mt, kcn, krng, b_base);
+                          int2 *krng, int64_t *b_base, int c0, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_build_b, dim3(n), dim3(256), build_b_lds_bytes(P.nch, P.V), st, P, tgt_off, tgt_tok, b_list,
+                     b_choff, pitch, esize, compact, mt, kcn, krng, b_base, c0);
   return hipGetLastError();
 }
 

@@ -15,12 +15,12 @@
 #include "nwm_internal.h"
 
 namespace nwm {
-hipError_t launch_merge_src(int64_t, const int64_t *, const int32_t *, const int32_t *, const int32_t *,
-                            const float *, int, int, int, uint2 *, int32_t *, int, hipStream_t);
+hipError_t launch_merge_src(int64_t, const int64_t *, int64_t, const int64_t *, const int32_t *, const int32_t *,
+                            const int32_t *, const float *, int, int, int, uint2 *, int32_t *, int, hipStream_t);
 hipError_t launch_build_a(const PlanDev &, const int64_t *, const uint2 *, const int32_t *, uint2 *, int32_t *,
-                          int, int, int, int64_t *, hipStream_t);
+                          int, int, int, int64_t *, int, int, hipStream_t);
 hipError_t launch_build_b(const PlanDev &, const int64_t *, const int32_t *, uint32_t *, int32_t *, int, int, int,
-                          uint2 *, int32_t *, int2 *, int64_t *, hipStream_t);
+                          uint2 *, int32_t *, int2 *, int64_t *, int, int, hipStream_t);
 hipError_t build_set_attrs(int nch, int V);
 hipError_t launch_score(const PlanDev &, bool, const int64_t *, const int64_t *, const uint2 *, const int32_t *,
                         const uint32_t *, const int32_t *, nwm_scorer, float *, float *, int, int, const uint2 *,
@@ -95,11 +95,15 @@ struct nwm_plan {
   std::vector<int64_t> it_chain;   // dependency chain of the item's pair
   int64_t max_chain = 0;
   int max_m = 0;
-  // the pairs whose DP dependency chain is at least half the longest come
-  // first in every order (tiles, DP items, pairs); nwm_mine runs their DP on
-  // a second stream while the main stream scores and aligns the others
-  int n_gt_long = 0, n_items_long = 0, n_pairs_long = 0;
-  hipEvent_t ev_long = nullptr, ev_long_done = nullptr;
+  // the pairs whose DP dependency chain is at least LONG_CHAIN_PERCENT of
+  // the longest come first in every order (sentences, tiles, DP items,
+  // pairs); nwm_mine prepares and scores them first and runs their DP on a
+  // stream of its own while the main stream prepares, scores and aligns the
+  // others
+  int n_gt_long = 0, n_items_long = 0, n_pairs_long = 0, n_rt_long = 0, n_ct_long = 0;
+  int64_t n_sent_long = 0;
+  hipStream_t lane_stream = nullptr;   // the long pairs' DP
+  hipEvent_t ev_long = nullptr, ev_long_done = nullptr, ev_b_long = nullptr, ev_b_rest = nullptr;
   std::vector<int32_t> n, m;
   void *dmeta = nullptr;
   PlanDev dev{};
@@ -241,23 +245,6 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
     int64_t bits = 0;
     if (nb > 0 && mb > 0) bits = ((nb + 63) / 64) * ((mb + 63 + 63) / 64) * 1024;
     tb_off[b + 1] = tb_off[b] + bits;
-    const int rt0 = (int)rt_pair.size(), ct0 = (int)ct_pair.size();
-    for (int r = 0; r < nb; r += TM) {
-      rt_pair.push_back(b);
-      rt_row0.push_back(r);
-      rt_rows.push_back((int)std::min<int64_t>(TM, nb - r));
-    }
-    for (int c = 0; c < mb; c += TN) {
-      ct_pair.push_back(b);
-      ct_col0.push_back(c);
-      ct_cols.push_back((int)std::min<int64_t>(TN, mb - c));
-    }
-    const int nrt = (int)rt_pair.size() - rt0, nct = (int)ct_pair.size() - ct0;
-    for (int ri = 0; ri < nrt; ++ri)
-      for (int ci = 0; ci < nct; ++ci) {
-        gt_rt.push_back(rt0 + ri);
-        gt_ct.push_back(ct0 + ci);
-      }
   }
   // dependency chain of a pair's DP: one hand-off of ~80 steps per strip
   // plus the m + 63 steps of the last strip
@@ -265,24 +252,46 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   p->max_chain = 0;
   for (int b = 0; b < B; ++b)
     if (p->n[b] > 0 && p->m[b] > 0) p->max_chain = std::max(p->max_chain, chain(b));
+  // the long pairs: dependency chain at least LONG_CHAIN_PERCENT of the longest
   std::vector<char> is_long(B, 0);
   for (int b = 0; b < B; ++b)
-    is_long[b] = p->n[b] > 0 && p->m[b] > 0 && p->max_chain > 0 && 2 * chain(b) >= p->max_chain;
-  {
-    // tiles of the long pairs first (stable)
-    std::vector<int32_t> r2, c2;
-    r2.reserve(gt_rt.size());
-    c2.reserve(gt_ct.size());
-    for (int pass = 0; pass < 2; ++pass)
-      for (size_t g = 0; g < gt_rt.size(); ++g)
-        if ((is_long[rt_pair[gt_rt[g]]] != 0) == (pass == 0)) {
-          r2.push_back(gt_rt[g]);
-          c2.push_back(gt_ct[g]);
+    is_long[b] = p->n[b] > 0 && p->m[b] > 0 && p->max_chain > 0 &&
+                 100 * chain(b) >= (int64_t)LONG_CHAIN_PERCENT * p->max_chain;
+  // tiles and source sentences in lane order: the long pairs first, then the
+  // others (each group in pair order)
+  std::vector<int64_t> sent_ids;
+  sent_ids.reserve((size_t)sfirst[B]);
+  p->n_rt_long = p->n_ct_long = p->n_gt_long = 0;
+  p->n_sent_long = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int b = 0; b < B; ++b) {
+      if ((is_long[b] != 0) != (pass == 0)) continue;
+      const int64_t nb = p->n[b], mb = p->m[b];
+      for (int64_t i = sfirst[b]; i < sfirst[b + 1]; ++i) sent_ids.push_back(i);
+      const int rt0 = (int)rt_pair.size(), ct0 = (int)ct_pair.size();
+      for (int r = 0; r < nb; r += TM) {
+        rt_pair.push_back(b);
+        rt_row0.push_back(r);
+        rt_rows.push_back((int)std::min<int64_t>(TM, nb - r));
+      }
+      for (int c = 0; c < mb; c += TN) {
+        ct_pair.push_back(b);
+        ct_col0.push_back(c);
+        ct_cols.push_back((int)std::min<int64_t>(TN, mb - c));
+      }
+      const int nrt = (int)rt_pair.size() - rt0, nct = (int)ct_pair.size() - ct0;
+      for (int ri = 0; ri < nrt; ++ri)
+        for (int ci = 0; ci < nct; ++ci) {
+          gt_rt.push_back(rt0 + ri);
+          gt_ct.push_back(ct0 + ci);
         }
-    gt_rt.swap(r2);
-    gt_ct.swap(c2);
-    p->n_gt_long = 0;
-    for (size_t g = 0; g < gt_rt.size(); ++g) p->n_gt_long += is_long[rt_pair[gt_rt[g]]] ? 1 : 0;
+    }
+    if (pass == 0) {
+      p->n_rt_long = (int)rt_pair.size();
+      p->n_ct_long = (int)ct_pair.size();
+      p->n_gt_long = (int)gt_rt.size();
+      p->n_sent_long = (int64_t)sent_ids.size();
+    }
   }
   p->n_src = sfirst[B];
   p->n_tgt = tfirst[B];
@@ -359,6 +368,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   size_t i_gr = add(gt_rt.data(), 4 * gt_rt.size()), i_gc = add(gt_ct.data(), 4 * gt_ct.size());
   size_t i_gm = add(gt_meta.data(), sizeof(GtMeta) * gt_meta.size());
   size_t i_do = add(order.data(), 4 * order.size());
+  size_t i_si = add(sent_ids.data(), 8 * sent_ids.size());
   size_t i_ip = add(it_pair.data(), 4 * it_pair.size()), i_is = add(it_strip.data(), 4 * it_strip.size());
   size_t i_bo = add(bnd_off.data(), 8 * (size_t)(B + 1));
   if (hipSetDevice(ctx->device) != hipSuccess) {
@@ -404,6 +414,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   D.gt_ct = (const int32_t *)at(i_gc);
   D.gt_meta = (const GtMeta *)at(i_gm);
   D.dp_order = (const int32_t *)at(i_do);
+  D.sent_ids = (const int64_t *)at(i_si);
   D.n_items = (int)it_pair.size();
   D.it_pair = (const int32_t *)at(i_ip);
   D.it_strip = (const int32_t *)at(i_is);
@@ -465,6 +476,9 @@ void nwm_plan_destroy(nwm_plan *plan) {
   if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
   if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
   if (plan->ev_long) (void)hipEventDestroy(plan->ev_long);
+  if (plan->ev_b_long) (void)hipEventDestroy(plan->ev_b_long);
+  if (plan->ev_b_rest) (void)hipEventDestroy(plan->ev_b_rest);
+  if (plan->lane_stream) (void)hipStreamDestroy(plan->lane_stream);
   if (plan->ev_long_done) (void)hipEventDestroy(plan->ev_long_done);
   if (plan->dmeta) (void)hipFree(plan->dmeta);
   delete plan;
@@ -493,40 +507,50 @@ static nwm_status check_score_args(const nwm_plan *p, const nwm_batch *batch, co
   return NWM_OK;
 }
 
-static hipError_t expand_lists(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, void *ws, hipStream_t st) {
+// The expansion for part of the batch: merged dictionary rows of source
+// sentences sent_ids[k0, k0 + ns) and the lists of row tiles [r0, r0 + nr)
+// (which hold exactly those sentences) on `st`; the lists of column tiles
+// [c0, c0 + nc) on `tst`.
+static hipError_t expand_src(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, void *ws, int64_t k0,
+                             int64_t ns, int r0, int nr, hipStream_t st) {
   char *w = static_cast<char *>(ws);
   uint2 *merged = (uint2 *)(w + p->ws.a_merged);
   int32_t *cnt = (int32_t *)(w + p->ws.a_cnt);
-  uint2 *a_list = (uint2 *)(w + p->ws.a_list);
-  int32_t *a_choff = (int32_t *)(w + p->ws.a_choff);
-  uint32_t *b_list = (uint32_t *)(w + p->ws.b_list);
-  int32_t *b_choff = (int32_t *)(w + p->ws.b_choff);
-  uint2 *b_mt = (uint2 *)(w + p->ws.b_mt);
-  int32_t *b_kcn = (int32_t *)(w + p->ws.b_kcn);
-  int2 *b_rng = (int2 *)(w + p->ws.b_rng);
-  int64_t *a_base = (int64_t *)(w + p->ws.a_base);
-  int64_t *b_base = (int64_t *)(w + p->ws.b_base);
-  const int compact = p->param[NWM_PARAM_SCORE_COMPACT];
   const bool bf16 = p->prec == NWM_BF16;
-  // list entries are LDS byte offsets inside the operand tiles
+  // list entries of the dense contraction are LDS byte offsets inside the
+  // operand tiles
   const int pitch = bf16 ? PITCH_BF16 : PITCH_F32;
   const int esize = bf16 ? 2 : 4;
-  // The target-side lists do not depend on the source side: they are built
-  // on the plan's second stream, forked from and joined back to `st` by
-  // events (under graph capture: a parallel branch of the graph).
+  Mark mk(p, K_EXPAND, st);
+  hipError_t e = launch_merge_src(ns, p->dev.sent_ids, k0, batch->src_off, batch->src_tok, dict->row_off, dict->col,
+                                  dict->val, p->V, p->max_deg, p->max_entries, merged, cnt,
+                                  p->param[NWM_PARAM_MERGE_WAVES_PER_CU], st);
+  if (e == hipSuccess)
+    e = launch_build_a(p->dev, batch->src_off, merged, cnt, (uint2 *)(w + p->ws.a_list),
+                       (int32_t *)(w + p->ws.a_choff), pitch, esize, p->param[NWM_PARAM_SCORE_COMPACT],
+                       (int64_t *)(w + p->ws.a_base), r0, nr, st);
+  mk.done();
+  return e;
+}
+
+static hipError_t expand_tgt(nwm_plan *p, const nwm_batch *batch, void *ws, int c0, int nc, hipStream_t st) {
+  char *w = static_cast<char *>(ws);
+  const bool bf16 = p->prec == NWM_BF16;
+  return launch_build_b(p->dev, batch->tgt_off, batch->tgt_tok, (uint32_t *)(w + p->ws.b_list),
+                        (int32_t *)(w + p->ws.b_choff), bf16 ? PITCH_BF16 : PITCH_F32, bf16 ? 2 : 4,
+                        p->param[NWM_PARAM_SCORE_COMPACT], (uint2 *)(w + p->ws.b_mt), (int32_t *)(w + p->ws.b_kcn),
+                        (int2 *)(w + p->ws.b_rng), (int64_t *)(w + p->ws.b_base), c0, nc, st);
+}
+
+// The whole expansion.  The target-side lists do not depend on the source
+// side: they are built on the plan's second stream, forked from and joined
+// back to `st` by events (under graph capture: a parallel branch of the graph).
+static hipError_t expand_lists(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, void *ws, hipStream_t st) {
   hipError_t e = hipEventRecord(p->ev_fork, st);
   if (e == hipSuccess) e = hipStreamWaitEvent(p->aux_stream, p->ev_fork, 0);
-  if (e == hipSuccess)
-    e = launch_build_b(p->dev, batch->tgt_off, batch->tgt_tok, b_list, b_choff, pitch, esize, compact, b_mt, b_kcn,
-                       b_rng, b_base, p->aux_stream);
+  if (e == hipSuccess) e = expand_tgt(p, batch, ws, 0, p->dev.n_ct, p->aux_stream);
   if (e == hipSuccess) e = hipEventRecord(p->ev_join, p->aux_stream);
-  Mark mk(p, K_EXPAND, st);
-  if (e == hipSuccess)
-    e = launch_merge_src(p->n_src, batch->src_off, batch->src_tok, dict->row_off, dict->col, dict->val, p->V,
-                         p->max_deg, p->max_entries, merged, cnt, p->param[NWM_PARAM_MERGE_WAVES_PER_CU], st);
-  if (e == hipSuccess)
-    e = launch_build_a(p->dev, batch->src_off, merged, cnt, a_list, a_choff, pitch, esize, compact, a_base, st);
-  mk.done();
+  if (e == hipSuccess) e = expand_src(p, batch, dict, ws, 0, p->n_src, 0, p->dev.n_rt, st);
   if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_join, 0);
   return e;
 }
@@ -550,8 +574,11 @@ static hipError_t ensure_streams(nwm_plan *p) {
   hipError_t e = hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->lane_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_long, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_long_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_b_long, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_b_rest, hipEventDisableTiming);
   return e;
 }
 
@@ -702,21 +729,47 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
   int32_t *ctl = (int32_t *)(w + p->ws.ctl);
   const int wpc = p->param[NWM_PARAM_FILL_WAVES_PER_CU];
   const PlanDev &D = p->dev;
-  hipError_t e = ensure_streams(p);
-  if (e == hipSuccess && p->sizes.S_elems > 0) e = expand_lists(p, batch, dict, ws, st);
-  if (e == hipSuccess) e = launch_nw_reset(D, gap, score, bnd, p->n_bnd, ctl, st);
+  const bool scored = p->sizes.S_elems > 0;
   const int gl = p->n_gt_long, il = p->n_items_long, ol = p->n_pairs_long;
-  if (e == hipSuccess && ol > 0) {
-    if (p->sizes.S_elems > 0) e = score_tiles(p, batch, sc, S, S_raw, ws, 0, gl, st);
-    if (e == hipSuccess) e = hipEventRecord(p->ev_long, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(p->aux_stream, p->ev_long, 0);
-    if (e == hipSuccess)
-      e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl + 2, ctl + 1, 0, il, wpc, p->aux_stream);
-    if (e == hipSuccess) e = launch_nw_walk(D, tbc, path, n_diag, 0, ol, p->aux_stream);
-    if (e == hipSuccess) e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, 0, ol, p->aux_stream);
-    if (e == hipSuccess) e = hipEventRecord(p->ev_long_done, p->aux_stream);
+  const int rl = p->n_rt_long, cl = p->n_ct_long;
+  const int64_t kl = p->n_sent_long;
+  hipStream_t aux = p->aux_stream, lane = p->lane_stream;
+  hipError_t e = ensure_streams(p);
+  aux = p->aux_stream;
+  lane = p->lane_stream;
+  // target-side lists: the long pairs' first, each part announced by an event
+  if (e == hipSuccess) e = hipEventRecord(p->ev_fork, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(aux, p->ev_fork, 0);
+  if (scored) {
+    if (e == hipSuccess) e = expand_tgt(p, batch, ws, 0, cl, aux);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_b_long, aux);
+    if (e == hipSuccess) e = expand_tgt(p, batch, ws, cl, D.n_ct - cl, aux);
   }
-  if (e == hipSuccess && p->sizes.S_elems > 0) e = score_tiles(p, batch, sc, S, S_raw, ws, gl, D.n_gt - gl, st);
+  if (e == hipSuccess) e = hipEventRecord(p->ev_b_rest, aux);
+  if (e == hipSuccess) e = launch_nw_reset(D, gap, score, bnd, p->n_bnd, ctl, st);
+  if (ol > 0) {
+    // the long pairs: expand and score on the main stream, then their DP on
+    // the lane stream while the main stream goes on with the rest
+    if (scored) {
+      if (e == hipSuccess) e = expand_src(p, batch, dict, ws, 0, kl, 0, rl, st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_b_long, 0);
+      if (e == hipSuccess) e = score_tiles(p, batch, sc, S, S_raw, ws, 0, gl, st);
+    }
+    if (e == hipSuccess) e = hipEventRecord(p->ev_long, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(lane, p->ev_long, 0);
+    if (e == hipSuccess)
+      e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl + 2, ctl + 1, 0, il, wpc, lane);
+    if (e == hipSuccess) e = launch_nw_walk(D, tbc, path, n_diag, 0, ol, lane);
+    if (e == hipSuccess) e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, 0, ol, lane);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_long_done, lane);
+  }
+  if (scored) {
+    if (e == hipSuccess) e = expand_src(p, batch, dict, ws, kl, p->n_src - kl, rl, D.n_rt - rl, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_b_rest, 0);
+    if (e == hipSuccess) e = score_tiles(p, batch, sc, S, S_raw, ws, gl, D.n_gt - gl, st);
+  } else if (e == hipSuccess) {
+    e = hipStreamWaitEvent(st, p->ev_b_rest, 0);
+  }
   if (e == hipSuccess)
     e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl, ctl + 1, il, D.n_items - il, wpc, st);
   if (e == hipSuccess) e = launch_nw_walk(D, tbc, path, n_diag, ol, p->B - ol, st);

@@ -47,6 +47,9 @@ constexpr int FILL_SINK_WAVES = 1024;
 constexpr int64_t FILL_SINK_SLOTS = (int64_t)FILL_SINK_WAVES * 16 + 16;   // uint64 entries, incl. alignment slack
 constexpr int MAX_M = 1 << 22;           // target sentences per pair (a 64-row strip of S stays below 1 GiB)
 constexpr int32_t ITEM_HOT = 1 << 30;   // DP item flag: strip of a critical-chain pair
+// Pairs whose DP dependency chain is at least this percent of the longest are
+// the "long" pairs: prepared, scored and aligned ahead of the others.
+constexpr int LONG_CHAIN_PERCENT = 25;
 
 // Direction codes of the traceback.
 constexpr int DIR_DIAG = 0, DIR_UP = 1, DIR_LEFT = 2;
@@ -87,6 +90,7 @@ struct PlanDev {
   const GtMeta *gt_meta;
   // DP order (longest first) and DP work items (pair, strip), longest pair first
   const int32_t *dp_order;
+  const int64_t *sent_ids;   // [sum n] source sentences, long pairs' first
   int n_items;
   const int32_t *it_pair, *it_strip;
   const int64_t *bnd_off;   // [B+1] offset of a pair's published boundary rows (uint64 units)
