@@ -103,7 +103,9 @@ struct nwm_plan {
   int n_gt_long = 0, n_items_long = 0, n_pairs_long = 0, n_rt_long = 0, n_ct_long = 0;
   int64_t n_sent_long = 0;
   hipStream_t lane_stream = nullptr;   // the long pairs' DP
+  hipStream_t exp_stream = nullptr;    // the other pairs' source-side expansion
   hipEvent_t ev_long = nullptr, ev_long_done = nullptr, ev_b_long = nullptr, ev_b_rest = nullptr;
+  hipEvent_t ev_a_rest = nullptr;
   std::vector<int32_t> n, m;
   void *dmeta = nullptr;
   PlanDev dev{};
@@ -479,6 +481,8 @@ void nwm_plan_destroy(nwm_plan *plan) {
   if (plan->ev_b_long) (void)hipEventDestroy(plan->ev_b_long);
   if (plan->ev_b_rest) (void)hipEventDestroy(plan->ev_b_rest);
   if (plan->lane_stream) (void)hipStreamDestroy(plan->lane_stream);
+  if (plan->exp_stream) (void)hipStreamDestroy(plan->exp_stream);
+  if (plan->ev_a_rest) (void)hipEventDestroy(plan->ev_a_rest);
   if (plan->ev_long_done) (void)hipEventDestroy(plan->ev_long_done);
   if (plan->dmeta) (void)hipFree(plan->dmeta);
   delete plan;
@@ -575,6 +579,8 @@ static hipError_t ensure_streams(nwm_plan *p) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->lane_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->exp_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_a_rest, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_long, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_long_done, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_b_long, hipEventDisableTiming);
@@ -733,13 +739,14 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
   const int gl = p->n_gt_long, il = p->n_items_long, ol = p->n_pairs_long;
   const int rl = p->n_rt_long, cl = p->n_ct_long;
   const int64_t kl = p->n_sent_long;
-  hipStream_t aux = p->aux_stream, lane = p->lane_stream;
   hipError_t e = ensure_streams(p);
-  aux = p->aux_stream;
-  lane = p->lane_stream;
-  // target-side lists: the long pairs' first, each part announced by an event
+  hipStream_t aux = p->aux_stream, lane = p->lane_stream, xs = p->exp_stream;
+  // target-side lists on one side stream (the long pairs' first, each part
+  // announced by an event), the other pairs' source-side expansion on a
+  // second one, both from the start
   if (e == hipSuccess) e = hipEventRecord(p->ev_fork, st);
   if (e == hipSuccess) e = hipStreamWaitEvent(aux, p->ev_fork, 0);
+  if (e == hipSuccess) e = hipStreamWaitEvent(xs, p->ev_fork, 0);
   if (scored) {
     if (e == hipSuccess) e = expand_tgt(p, batch, ws, 0, cl, aux);
     if (e == hipSuccess) e = hipEventRecord(p->ev_b_long, aux);
@@ -755,6 +762,8 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
       if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_b_long, 0);
       if (e == hipSuccess) e = score_tiles(p, batch, sc, S, S_raw, ws, 0, gl, st);
     }
+    if (e == hipSuccess && scored) e = expand_src(p, batch, dict, ws, kl, p->n_src - kl, rl, D.n_rt - rl, xs);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_a_rest, xs);
     if (e == hipSuccess) e = hipEventRecord(p->ev_long, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(lane, p->ev_long, 0);
     if (e == hipSuccess)
@@ -763,13 +772,13 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
     if (e == hipSuccess) e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, 0, ol, lane);
     if (e == hipSuccess) e = hipEventRecord(p->ev_long_done, lane);
   }
-  if (scored) {
-    if (e == hipSuccess) e = expand_src(p, batch, dict, ws, kl, p->n_src - kl, rl, D.n_rt - rl, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_b_rest, 0);
-    if (e == hipSuccess) e = score_tiles(p, batch, sc, S, S_raw, ws, gl, D.n_gt - gl, st);
-  } else if (e == hipSuccess) {
-    e = hipStreamWaitEvent(st, p->ev_b_rest, 0);
+  if (ol == 0) {
+    if (e == hipSuccess && scored) e = expand_src(p, batch, dict, ws, 0, p->n_src, 0, D.n_rt, xs);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_a_rest, xs);
   }
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_a_rest, 0);
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_b_rest, 0);
+  if (e == hipSuccess && scored) e = score_tiles(p, batch, sc, S, S_raw, ws, gl, D.n_gt - gl, st);
   if (e == hipSuccess)
     e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl, ctl + 1, il, D.n_items - il, wpc, st);
   if (e == hipSuccess) e = launch_nw_walk(D, tbc, path, n_diag, ol, p->B - ol, st);
