@@ -283,31 +283,33 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
   }
 }
 
-// Exclusive scan of cnt[0..len) into off[0..len] by one 256-thread block.
-// `tmp` holds 256 ints of LDS.
+// Exclusive scan of vals[0..len) in place, total in vals[len], by the first
+// wave of a 256-thread block (each lane sums a run of consecutive entries,
+// a wave-wide scan of the run sums, each lane writes its run back); the
+// caller has synchronised the block after writing vals.  `tmp` is unused.
 static __device__ void block_exclusive_scan(int *vals, int len, int *tmp) {
-  const int tid = threadIdx.x;
-  const int per = (len + 255) / 256;
-  const int lo = tid * per;
-  const int hi = min(lo + per, len);
-  int s = 0;
-  for (int k = lo; k < hi; ++k) s += vals[k];
-  tmp[tid] = s;
-  __syncthreads();
-  for (int d = 1; d < 256; d <<= 1) {
-    int x = (tid >= d) ? tmp[tid - d] : 0;
-    __syncthreads();
-    tmp[tid] += x;
-    __syncthreads();
+  (void)tmp;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const int per = (len + 63) / 64;
+    const int lo = min(lane * per, len);
+    const int hi = min(lo + per, len);
+    int sum = 0;
+    for (int k = lo; k < hi; ++k) sum += vals[k];
+    int incl = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int x = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += x;
+    }
+    int run = incl - sum;
+    for (int k = lo; k < hi; ++k) {
+      const int c = vals[k];
+      vals[k] = run;
+      run += c;
+    }
+    if (lane == 63) vals[len] = incl;
   }
-  int run = tmp[tid] - s;
-  __syncthreads();
-  for (int k = lo; k < hi; ++k) {
-    int c = vals[k];
-    vals[k] = run;
-    run += c;
-  }
-  if (tid == 255) vals[len] = tmp[255];
   __syncthreads();
 }
 
