@@ -571,8 +571,7 @@ static __device__ __forceinline__ void cscatter(const CChunk &C, char *At, char 
     const uint32_t x = C.a[q].x, u = x >> 6, bit = u & 31u;
     const uint32_t pos = mm[q].y + (uint32_t)__popc(mm[q].x & ((1u << bit) - 1u));
     const bool hit = lane + 64 * q < C.na && ((mm[q].x >> bit) & 1u) && (pos >> 5) == (uint32_t)kc;
-    const uint32_t o = hit ? ((x & 63u) * P + (pos & 31u)) * (uint32_t)sizeof(T) : junk;
-    lds_put<T>(At, o, T(__uint_as_float(C.a[q].y)));
+    if (hit) lds_put<T>(At, ((x & 63u) * P + (pos & 31u)) * (uint32_t)sizeof(T), T(__uint_as_float(C.a[q].y)));
   }
   for (int e = CREG_A * 64 + lane; e < C.na; e += 64) {
     const uint2 v = pa[C.a0 + e];
