@@ -175,7 +175,7 @@ def main():
         mn = nw.Miner(ctx, db, dd, prec)
         if not args.no_autotune:
             from paper_1512_01641_amd import autotune
-            tuned[prec_name] = autotune.autotune(mn, w, gap, thr, reps=3)["params"]
+            tuned[prec_name] = autotune.autotune(mn, w, gap, thr, reps=5)["params"]
             _log("autotuned %s: %s" % (prec_name, tuned[prec_name]))
         step = lambda mn=mn: mn.mine(w, gap, thr)
         for _ in range(args.warmup):

@@ -59,12 +59,15 @@ def _load(path):
 
 
 def autotune(miner, scorer, gap: float, threshold: float, space=None, reps: int = 5, cache_path=None,
-             min_gain: float = 0.01) -> dict:
+             min_gain: float = 0.01, graph: bool = True) -> dict:
     """Pick and apply the fastest launch parameters for this miner's plan.
 
-    Returns {"params": {...}, "ms": best time, "cached": bool}.  A value
-    replaces the current best only when it is faster by more than min_gain
-    (relative), so timing noise does not move the choice."""
+    Times the path the way it is run: by default as the captured graph of
+    nwm_mine (its overlapped multi-stream schedule; every parameter change
+    recaptures), graph=False for eager launches.  Returns {"params": {...},
+    "ms": best time, "cached": bool}.  A value replaces the current best only
+    when it is faster by more than min_gain (relative), so timing noise does
+    not move the choice."""
     space = SPACE if space is None else space
     plan = miner.plan
     sig = signature(miner)
@@ -74,13 +77,13 @@ def autotune(miner, scorer, gap: float, threshold: float, space=None, reps: int 
             plan.set_param(k, v)
         return {"params": dict(cache[sig]["params"]), "ms": cache[sig]["ms"], "cached": True}
     best = {k: plan.get_param(k) for k in space}
-    best_ms = time_mine(miner, scorer, gap, threshold, reps)
+    best_ms = time_mine(miner, scorer, gap, threshold, reps, graph=graph)
     for k, values in space.items():
         for v in values:
             if v == best[k]:
                 continue
             plan.set_param(k, v)
-            ms = time_mine(miner, scorer, gap, threshold, reps)
+            ms = time_mine(miner, scorer, gap, threshold, reps, graph=graph)
             if ms < best_ms * (1.0 - min_gain):
                 best_ms, best[k] = ms, v
         plan.set_param(k, best[k])
