@@ -266,15 +266,12 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
       }
     }
     wave_sync();
+    // write the merged row and clear every slot this sentence claimed (a
+    // dropped entry claimed none); each claimed slot belongs to one lane
     const int64_t base = cur.t0 * (int64_t)max_deg;
     for (int e = lane; e < nuniq; e += 64) {
       const int h = slots[e];
       merged[base + e] = make_uint2(key[h], __float_as_uint((float)acc[h]));
-    }
-    wave_sync();
-    // clear every slot this sentence claimed (a dropped entry claimed none)
-    for (int e = lane; e < nuniq; e += 64) {
-      const int h = slots[e];
       key[h] = HEMPTY;
       acc[h] = 0.0;
     }
