@@ -29,18 +29,30 @@ static __device__ __forceinline__ void wave_sync() {
 
 constexpr uint32_t HEMPTY = 0xFFFFFFFFu;
 
-// Software pipeline of the merge over a wave's sentences: the token range of
-// a sentence is loaded four sentences ahead, its tokens three ahead, their
-// dictionary row offsets two ahead and the first four entries of every row
-// one ahead, so each load has a whole sentence of merging to land.  Lane l holds token l of the
-// sentence's first 64 tokens.  Every pipelined load is an unconditional raw
-// buffer load (lanes with nothing to load use an offset past the buffer and
-// read 0), so the wait counts stay exact; validity is applied when a value
-// is used.
+// Software pipeline of the merge over a wave's sentences.  Every load is a
+// vector load issued ahead of the sentence that needs it: the sentence id
+// five sentences ahead, its token range four ahead, its tokens three ahead
+// (lane l holds token l of the first 64), their dictionary row offsets two
+// ahead and the first four entries of every row one ahead, so each load has
+// a whole sentence of merging to land.  (Scalar loads would share their wait
+// counter with the LDS atomics of the merge and be waited for at the first
+// of them.)  The pipelined loads are unconditional: raw buffer loads with an
+// offset past the buffer for lanes with nothing to load (they read 0), or
+// loads at an in-range address, so the wait counts stay exact; validity is
+// applied when a value is used.  A merged row leaves the LDS table into
+// registers and is stored at the start of the next sentence by unconditional
+// buffer stores whose range check drops the lanes past the row's end, so the
+// next wait for the pipelined loads never waits for these stores.
+constexpr int MERGE_OUT_REGS = 4;   // merged entries per lane held for the deferred store
+typedef unsigned int m_u32x2 __attribute__((ext_vector_type(2)));
+
+struct MergeId {
+  int64_t sent;   // sentence number within the launch (>= n_sent: none)
+  m_u32x2 id;     // sent_ids[sent] as loaded
+};
 struct MergeOff {
-  int64_t id;       // the sentence
-  int64_t t0, t1;   // as loaded; the length is formed where it is used
-  bool ok;
+  int64_t sent, id;
+  m_u32x2 t0, t1;   // the sentence's token range, as loaded
 };
 struct MergeTok {
   int64_t id, t0;
@@ -56,10 +68,21 @@ struct MergeEnt {
   uint32_t u[4];
   float v[4];
 };
+struct MergeOut {
+  int64_t base, id;
+  int n;   // merged entries (-1: nothing to store)
+  uint2 v[MERGE_OUT_REGS];
+};
 constexpr uint32_t BUF_OOB = 0xFFFFFFF0u;
 
 static __device__ __forceinline__ uint32_t buf_u32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+
+static __device__ __forceinline__ int64_t first_lane64(int64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // One wave per source sentence (grid-stride): T'[i][u] = sum over the
@@ -91,28 +114,38 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
   wave_sync();
 
   const int nnz = d_row_off[V];   // dictionary entries
+  const __amdgpu_buffer_rsrc_t r_ids =
+      __builtin_amdgcn_make_buffer_rsrc((void *)sent_ids, (short)0, (int)(n_sent * 8), 0x00020000);
   const __amdgpu_buffer_rsrc_t r_row =
       __builtin_amdgcn_make_buffer_rsrc((void *)d_row_off, (short)0, (V + 1) * 4, 0x00020000);
   const __amdgpu_buffer_rsrc_t r_col = __builtin_amdgcn_make_buffer_rsrc((void *)d_col, (short)0, nnz * 4, 0x00020000);
   const __amdgpu_buffer_rsrc_t r_val = __builtin_amdgcn_make_buffer_rsrc((void *)d_val, (short)0, nnz * 4, 0x00020000);
 
-  // unconditional (clamped) scalar loads: nothing waits on them before the
-  // next sentence uses them
   // sentence number `sent` of this launch is sentence sent_ids[sent]
-  auto load_off = [&](int64_t sent) {
+  auto load_id = [&](int64_t sent) {
+    MergeId I;
+    I.sent = sent;
+    I.id = __builtin_amdgcn_raw_buffer_load_b64(r_ids, sent < n_sent ? (uint32_t)sent * 8u : BUF_OOB, 0, 0);
+    return I;
+  };
+  // (a buffer load, not a plain one: the compiler would turn a load at a
+  // wave-uniform address into a scalar load)
+  auto load_off = [&](const MergeId &I) {
     MergeOff O;
-    const int64_t id = sent_ids[sent < n_sent ? sent : n_sent - 1];
-    O.id = id;
-    O.t0 = src_off[id];
-    O.t1 = src_off[id + 1];
-    O.ok = sent < n_sent;
+    O.sent = I.sent;
+    O.id = first_lane64((int64_t)(((uint64_t)I.id.y << 32) | I.id.x));   // 0 past the launch: a valid index
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(src_off + O.id), (short)0, 16, 0x00020000);
+    O.t0 = __builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0, 0);
+    O.t1 = __builtin_amdgcn_raw_buffer_load_b64(r, 8u, 0, 0);
     return O;
   };
   auto load_tok = [&](const MergeOff &O) {
     MergeTok T;
     T.id = O.id;
-    T.t0 = O.t0;
-    T.len = O.ok ? (int)(O.t1 - O.t0) : 0;
+    T.t0 = first_lane64((int64_t)(((uint64_t)O.t0.y << 32) | O.t0.x));
+    const int64_t t1 = first_lane64((int64_t)(((uint64_t)O.t1.y << 32) | O.t1.x));
+    T.len = O.sent < n_sent ? (int)max(t1 - T.t0, (int64_t)0) : 0;
     // a buffer over this sentence's first 64 tokens
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(src_tok + T.t0), (short)0, min(T.len, 64) * 4, 0x00020000);
@@ -144,6 +177,20 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
       E.v[d] = __uint_as_float(buf_u32(r_val, off));
     }
     return E;
+  };
+  // the merged row held in registers and the count; lanes past the row's end
+  // (and every lane of an empty record) fall outside the buffer ranges
+  auto store_out = [&](const MergeOut &M) {
+    const int n = max(M.n, 0);
+    const __amdgpu_buffer_rsrc_t r_m =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(merged + M.base), (short)0, n * 8, 0x00020000);
+#pragma unroll
+    for (int r = 0; r < MERGE_OUT_REGS; ++r)
+      __builtin_amdgcn_raw_buffer_store_b64((m_u32x2){M.v[r].x, M.v[r].y}, r_m, (uint32_t)(lane + 64 * r) * 8u, 0,
+                                            0);
+    const __amdgpu_buffer_rsrc_t r_c =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(cnt + M.id), (short)0, M.n >= 0 ? 4 : 0, 0x00020000);
+    __builtin_amdgcn_raw_buffer_store_b32(M.n, r_c, (uint32_t)lane * 4u, 0, 0);
   };
 
   int nuniq = 0;
@@ -220,16 +267,24 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
 
   const int64_t G = gridDim.x;
   int64_t sent = blockIdx.x;
-  MergeEnt E = load_ent(load_row(load_tok(load_off(sent))));
-  MergeRow R = load_row(load_tok(load_off(sent + G)));
-  MergeTok T = load_tok(load_off(sent + 2 * G));
-  MergeOff O = load_off(sent + 3 * G);
+  MergeEnt E = load_ent(load_row(load_tok(load_off(load_id(sent)))));
+  MergeRow R = load_row(load_tok(load_off(load_id(sent + G))));
+  MergeTok T = load_tok(load_off(load_id(sent + 2 * G)));
+  MergeOff O = load_off(load_id(sent + 3 * G));
+  MergeId I = load_id(sent + 4 * G);
+  MergeOut out;
+  out.base = out.id = 0;
+  out.n = -1;
+#pragma unroll
+  for (int r = 0; r < MERGE_OUT_REGS; ++r) out.v[r] = make_uint2(0u, 0u);
   for (; sent < n_sent; sent += G) {
     const MergeEnt cur = E;
     E = load_ent(R);
     R = load_row(T);
     T = load_tok(O);
-    O = load_off(sent + 4 * G);
+    O = load_off(I);
+    I = load_id(sent + 5 * G);
+    store_out(out);   // the previous sentence's row
 
     nuniq = 0;
     // first 64 tokens: entries 0..3 loaded ahead, further entries here
@@ -266,18 +321,33 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
       }
     }
     wave_sync();
-    // write the merged row and clear every slot this sentence claimed (a
-    // dropped entry claimed none); each claimed slot belongs to one lane
-    const int64_t base = cur.t0 * (int64_t)max_deg;
-    for (int e = lane; e < nuniq; e += 64) {
+    // take the merged row out of the table and clear every slot this
+    // sentence claimed (a dropped entry claimed none); each claimed slot
+    // belongs to one lane.  Entries past the registers' share are stored here.
+    out.base = cur.t0 * (int64_t)max_deg;
+    out.id = cur.id;
+    out.n = nuniq;
+#pragma unroll
+    for (int r = 0; r < MERGE_OUT_REGS; ++r) {
+      const int e = lane + 64 * r;
+      uint2 v = make_uint2(0u, 0u);
+      if (e < nuniq) {
+        const int h = slots[e];
+        v = make_uint2(key[h], __float_as_uint((float)acc[h]));
+        key[h] = HEMPTY;
+        acc[h] = 0.0;
+      }
+      out.v[r] = v;
+    }
+    for (int e = 64 * MERGE_OUT_REGS + lane; e < nuniq; e += 64) {
       const int h = slots[e];
-      merged[base + e] = make_uint2(key[h], __float_as_uint((float)acc[h]));
+      merged[out.base + e] = make_uint2(key[h], __float_as_uint((float)acc[h]));
       key[h] = HEMPTY;
       acc[h] = 0.0;
     }
-    if (lane == 0) cnt[cur.id] = nuniq;
     wave_sync();
   }
+  store_out(out);
 }
 
 // Exclusive scan of vals[0..len) in place, total in vals[len], by the first
@@ -567,6 +637,7 @@ hipError_t launch_merge_src(int64_t n_sent, const int64_t *sent_ids, int64_t k0,
                             const float *d_val, int V, int max_deg, int max_entries, uint2 *merged, int32_t *cnt,
                             int waves_per_cu, hipStream_t st) {
   if (n_sent <= 0) return hipSuccess;
+  if (n_sent >= ((int64_t)1 << 28)) return hipErrorInvalidValue;   // byte offsets of sent_ids stay 32-bit
   const int hb = merge_hbits(max_entries);
   const size_t lds = merge_lds_bytes(hb);
   static int cus = 0;
