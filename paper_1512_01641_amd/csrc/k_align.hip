@@ -36,6 +36,8 @@
 // k_keep      keeps the aligned pairs with S >= threshold, ascending.
 #include "nwm_internal.h"
 
+#include <cmath>
+
 namespace nwm {
 
 constexpr int PAIR_PITCH = 68;        // ring floats per row pair: 2 x 32 steps + 4 padding
@@ -135,7 +137,14 @@ struct StripState {
 // lane keeps H[i][0] until its column starts and keeps H[i][m] after it ends;
 // in between every lane is active.  Every step also shifts the last-row
 // collector (lane 63 enters), used by strips that have a successor.
-template <bool MASKED>
+//
+// MAX3: the new H is max(up, left, diag) in one instruction, and the
+// direction (the first of up, left, diag equal to it) is found off the
+// dependency chain from one step to the next.  This is the first maximum
+// with '>' bit for bit whenever no operand is NaN or -0: a finite S and a gap
+// that is not -0 never produce either (H starts at +0 or i*gap != 0, and a
+// sum is -0 only when both terms are).  A gap of -0 takes the compare chain.
+template <bool MASKED, bool MAX3>
 static __device__ __forceinline__ void run16(StripState &st, const float *ring, int t0, int m, float g,
                                              int lane) {
   float4 sv[4];
@@ -146,6 +155,11 @@ static __device__ __forceinline__ void run16(StripState &st, const float *ring, 
   float H = st.H, diag = st.diag, pw = st.pw, col = st.col;
   uint32_t bits = 0;
   int d = t0 - lane;   // column - 1 of this lane at the current step
+  // MAX3: the direction of a step is packed during the next one
+  float up_p = 0.0f, left_p = 0.0f, best_p = 0.0f;
+  auto code3 = [](float up, float left, float best) -> uint32_t {
+    return up == best ? (uint32_t)DIR_UP : (left == best ? (uint32_t)DIR_LEFT : (uint32_t)DIR_DIAG);
+  };
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const float4 v4 = sv[u >> 2];
@@ -154,11 +168,24 @@ static __device__ __forceinline__ void run16(StripState &st, const float *ring, 
     const float up = x + g;
     const float left = H + g;
     const float dg = diag + s;
-    const bool c1 = left > up;
-    const float b1 = c1 ? left : up;
-    const bool c2 = dg > b1;
-    const float best = c2 ? dg : b1;
-    const uint32_t code = c2 ? (uint32_t)DIR_DIAG : (c1 ? (uint32_t)DIR_LEFT : (uint32_t)DIR_UP);
+    float best;
+    if (MAX3) {
+      best = __builtin_fmaxf(__builtin_fmaxf(up, left), dg);
+      if (u > 0) {
+        bits = (bits << 2) | code3(up_p, left_p, best_p);
+        asm volatile("" : "+v"(bits));
+      }
+      up_p = up;
+      left_p = left;
+      best_p = best;
+    } else {
+      const bool c1 = left > up;
+      const float b1 = c1 ? left : up;
+      const bool c2 = dg > b1;
+      best = c2 ? dg : b1;
+      bits = (bits << 2) | (c2 ? (uint32_t)DIR_DIAG : (c1 ? (uint32_t)DIR_LEFT : (uint32_t)DIR_UP));
+      asm volatile("" : "+v"(bits));   // pack now: do not keep 16 steps of compare masks alive
+    }
     if (MASKED) {
       H = ((unsigned)d < (unsigned)m) ? best : H;
       ++d;
@@ -166,12 +193,11 @@ static __device__ __forceinline__ void run16(StripState &st, const float *ring, 
       H = best;
     }
     diag = x;
-    bits = (bits << 2) | code;
-    asm volatile("" : "+v"(bits));   // pack now: do not keep 16 steps of compare masks alive
     pw = dpp_shl1(pw, pw);
     col = dpp_shl1(H, col);
-    __builtin_amdgcn_sched_barrier(0);
+    if (!MAX3) __builtin_amdgcn_sched_barrier(0);   // one step at a time
   }
+  if (MAX3) bits = (bits << 2) | code3(up_p, left_p, best_p);
   st.H = H;
   st.diag = diag;
   st.pw = pw;
@@ -201,6 +227,7 @@ __global__ __launch_bounds__(256) void k_nw_reset(FillArgs A, uint4 *__restrict_
   }
 }
 
+template <bool MAX3>
 __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restrict__ S, float g,
                                                 float *__restrict__ score, char *__restrict__ tb,
                                                 uint64_t *__restrict__ bnd, uint64_t *__restrict__ sink,
@@ -298,8 +325,8 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     // memory operations and the explicit wait counts stay exact.
     auto chunk = [&](int t0, uint64_t win) {
       st.pw = s > 0 ? __uint_as_float((uint32_t)win) : (float)(t0 + 1 + lane) * g;
-      if (t0 < 64 || t0 + 16 > m) run16<true>(st, ring, t0, m, g, lane);
-      else run16<false>(st, ring, t0, m, g, lane);
+      if (t0 < 64 || t0 + 16 > m) run16<true, MAX3>(st, ring, t0, m, g, lane);
+      else run16<false, MAX3>(st, ring, t0, m, g, lane);
       // lane l of the collector holds H of row 64 at step t0 + 15 - 63 + l,
       // i.e. column t0 - 110 + l; lanes 48.. publish
       const int j = t0 - 110 + lane;
@@ -567,11 +594,13 @@ static int g_fill_cus = 0, g_fill_per = 0;   // compute units, resident fill wav
 
 hipError_t fill_set_attrs(int) {
   if (g_fill_cus == 0) {
-    int dev = 0, cus = 0, per = 0;
+    int dev = 0, cus = 0, per = 0, per3 = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_nw_fill, 64, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_nw_fill<false>, 64, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per3, k_nw_fill<true>, 64, 0);
     if (e != hipSuccess) return e;
+    per = per < per3 ? per : per3;   // either variant's grid is resident at once
     g_fill_per = per > 0 ? per : 1;
     g_fill_cus = cus > 0 ? cus : 1;
   }
@@ -624,7 +653,11 @@ hipError_t launch_nw_fill_items(const PlanDev &P, const float *S, float g, float
   const int grid = n < full ? n : full;
   // the sink: FILL_SINK_WAVES 128-byte lines after the published rows
   uint64_t *sink = reinterpret_cast<uint64_t *>((reinterpret_cast<uintptr_t>(bnd + n_bnd) + 127) & ~(uintptr_t)127);
-  hipLaunchKernelGGL(k_nw_fill, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, sink, head, err);
+  // a gap of -0 keeps the compare chain (see run16)
+  if (g == 0.0f && std::signbit(g))
+    hipLaunchKernelGGL(k_nw_fill<false>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, sink, head, err);
+  else
+    hipLaunchKernelGGL(k_nw_fill<true>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, sink, head, err);
   return hipGetLastError();
 }
 

@@ -67,6 +67,25 @@ def test_dp_ragged_strips_and_ties():
             H.assert_align_equal(gpu, ora, ns, ms, check_path_as_kept=thr < -1e29)
 
 
+@pytest.mark.parametrize("g", [0.0, -0.0, 0.25])
+def test_dp_zero_and_positive_gaps_signed_zero_similarities(g):
+    # a gap of -0 makes H[i][0] = -0 (the fill keeps its compare chain there);
+    # S holds -0 entries and coarse values with many exact ties
+    rng = np.random.default_rng(5)
+    sizes = [(3, 4), (64, 65), (130, 70), (7, 1), (1, 9), (70, 130)]
+    ns = [a for a, _ in sizes]
+    ms = [b for _, b in sizes]
+    blocks = []
+    for n, m in sizes:
+        blk = (rng.integers(0, 3, n * m) / 2.0).astype(np.float32)
+        blk[(blk == 0.0) & (rng.random(n * m) < 0.5)] = np.float32(-0.0)
+        blocks.append(blk)
+    S = np.concatenate(blocks)
+    gpu = H.gpu_align_only(ns, ms, S, g, 0.5)
+    ora = oracle.align(ns, ms, S, g, 0.5)
+    H.assert_align_equal(gpu, ora, ns, ms)
+
+
 def test_dp_empty_sides():
     ns = [0, 5, 0, 3, 7]
     ms = [4, 0, 0, 3, 1]
