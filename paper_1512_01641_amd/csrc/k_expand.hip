@@ -399,58 +399,100 @@ __global__ __launch_bounds__(256) void k_build_a(PlanDev P, const int64_t *__res
   int *off = reinterpret_cast<int *>(smem);  // [nch + 1]
   int *tmp = off + P.nch + 1;                // [256]
   const int rt = r0 + (int)blockIdx.x;
-  const int pair = P.rt_pair[rt];
-  const int rows = P.rt_rows[rt];
-  const int64_t s0 = P.sfirst[pair] + P.rt_row0[rt];
+  const TileMeta tm = P.rt_meta[rt];
+  const int rows = tm.count;
+  const int64_t s0 = tm.first;
+  // issued with the rows' counts, used for the placement
+  const int64_t tile_base = src_off[s0] * (int64_t)P.max_deg;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int c = threadIdx.x; c <= P.nch; c += 256) off[c] = 0;
   // every row of this wave at once: lane k fetches row wave + 4k's count and
-  // base, then the first 128 entries of every row are loaded together
+  // base (rows past the tile read row 0 and count 0), then the first 128
+  // entries of every row are loaded together by unconditional buffer loads
+  // (entries past a row's count fall outside its buffer range)
   const int myrow = wave + 4 * lane;
-  const int rc = (lane < ROWS_PER_WAVE && myrow < rows) ? cnt[s0 + myrow] : 0;
-  const int64_t rb = (lane < ROWS_PER_WAVE && myrow < rows) ? src_off[s0 + myrow] * (int64_t)P.max_deg : 0;
+  const bool vrow = lane < ROWS_PER_WAVE && myrow < rows;
+  const int64_t srow = s0 + (vrow ? myrow : 0);
+  const int rc_ld = cnt[srow];
+  const int64_t rb = src_off[srow] * (int64_t)P.max_deg;
+  const int rc = vrow ? rc_ld : 0;
+  auto row_cnt = [&](int k) { return __builtin_amdgcn_readlane(rc, k); };
+  auto row_base = [&](int k) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)rb, k);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)rb >> 32), k);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+  };
   uint2 e[ROWS_PER_WAVE][2];
 #pragma unroll
   for (int k = 0; k < ROWS_PER_WAVE; ++k) {
-    const int c = __shfl(rc, k, 64);
-    const int64_t base = __shfl(rb, k, 64);
-    e[k][0] = lane < c ? merged[base + lane] : make_uint2(0xFFFFFFFFu, 0u);
-    e[k][1] = 64 + lane < c ? merged[base + 64 + lane] : make_uint2(0xFFFFFFFFu, 0u);
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(merged + row_base(k)), (short)0, min(row_cnt(k), 128) * 8, 0x00020000);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const m_u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (uint32_t)(64 * q + lane) * 8u, 0, 0);
+      e[k][q] = make_uint2(v.x, v.y);
+    }
   }
+#pragma unroll
+  for (int k = 0; k < ROWS_PER_WAVE; ++k)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      if (64 * q + lane >= row_cnt(k)) e[k][q].x = 0xFFFFFFFFu;
   __syncthreads();
+  // masked-off entries count into the lane's own slot past the table
+  // (tmp[lane]: never read), so the atomics need no branches
+  const int junk = P.nch + 1 + lane;
 #pragma unroll
   for (int k = 0; k < ROWS_PER_WAVE; ++k) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-      if (e[k][q].x != 0xFFFFFFFFu) atomicAdd(&off[e[k][q].x / KC], 1);
-    const int c = __shfl(rc, k, 64);
-    const int64_t base = __shfl(rb, k, 64);
+    for (int q = 0; q < 2; ++q) {
+      const uint32_t u = e[k][q].x;
+      atomicAdd(&off[u != 0xFFFFFFFFu ? (int)(u / KC) : junk], 1);
+    }
+    const int c = row_cnt(k);
+    const int64_t base = row_base(k);
     for (int x = 128 + lane; x < c; x += 64) atomicAdd(&off[merged[base + x].x / KC], 1);
   }
   __syncthreads();
   block_exclusive_scan(off, P.nch, tmp);
   int32_t *choff = a_choff + (int64_t)rt * (P.nch + 1);
   for (int c = threadIdx.x; c <= P.nch; c += 256) choff[c] = off[c];
+  const int total = off[P.nch];   // entries of the tile
   __syncthreads();
-  const int64_t tile_base = src_off[s0] * (int64_t)P.max_deg;
   if (threadIdx.x == 0) a_base[rt] = tile_base;
+  // placement: every position is taken first, then every entry is stored by
+  // an unconditional buffer store (masked-off entries at an offset past the
+  // tile's range)
+  const __amdgpu_buffer_rsrc_t r_out =
+      __builtin_amdgcn_make_buffer_rsrc((void *)(a_list + tile_base), (short)0, total * 8, 0x00020000);
+  int pos[ROWS_PER_WAVE][2];
+#pragma unroll
+  for (int k = 0; k < ROWS_PER_WAVE; ++k)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const uint32_t u = e[k][q].x;
+      pos[k][q] = atomicAdd(&off[u != 0xFFFFFFFFu ? (int)(u / KC) : junk], 1);
+    }
 #pragma unroll
   for (int k = 0; k < ROWS_PER_WAVE; ++k) {
     const int r = wave + 4 * k;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const uint2 ent = e[k][q];
-      if (ent.x != 0xFFFFFFFFu) {
-        const int pos = atomicAdd(&off[ent.x / KC], 1);
-        a_list[tile_base + pos] = make_uint2(a_code(ent.x, r, pitch, esize, compact), ent.y);
-      }
+      const bool ok = ent.x != 0xFFFFFFFFu;
+      __builtin_amdgcn_raw_buffer_store_b64((m_u32x2){a_code(ok ? ent.x : 0u, r, pitch, esize, compact), ent.y},
+                                            r_out, ok ? (uint32_t)pos[k][q] * 8u : BUF_OOB, 0, 0);
     }
-    const int c = __shfl(rc, k, 64);
-    const int64_t base = __shfl(rb, k, 64);
+  }
+#pragma unroll
+  for (int k = 0; k < ROWS_PER_WAVE; ++k) {
+    const int r = wave + 4 * k;
+    const int c = row_cnt(k);
+    const int64_t base = row_base(k);
     for (int x = 128 + lane; x < c; x += 64) {
       const uint2 ent = merged[base + x];
-      const int pos = atomicAdd(&off[ent.x / KC], 1);
-      a_list[tile_base + pos] = make_uint2(a_code(ent.x, r, pitch, esize, compact), ent.y);
+      const int p = atomicAdd(&off[ent.x / KC], 1);
+      a_list[tile_base + p] = make_uint2(a_code(ent.x, r, pitch, esize, compact), ent.y);
     }
   }
 }
@@ -476,9 +518,10 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
   int *ubase = reinterpret_cast<int *>(bits + 4 * words);    // [words + 1] (compact)
   uint32_t *ubits = reinterpret_cast<uint32_t *>(ubase + words + 1);   // [words] (compact)
   const int ct = c0 + (int)blockIdx.x;
-  const int pair = P.ct_pair[ct];
-  const int cols = P.ct_cols[ct];
-  const int64_t t0 = P.tfirst[pair] + P.ct_col0[ct];
+  const TileMeta tm = P.ct_meta[ct];
+  const int cols = tm.count;
+  const int64_t t0 = tm.first;
+  const int64_t tile_base = tgt_off[t0];   // issued with the sentences' ranges
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   uint32_t *mybits = bits + wave * words;
   for (int c = threadIdx.x; c <= P.nch; c += 256) off[c] = 0;
@@ -537,7 +580,7 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
     if (threadIdx.x == 0) kcn[ct] = (K + KC - 1) / KC;
     __syncthreads();
   }
-  if (threadIdx.x == 0) b_base[ct] = tgt_off[t0];
+  if (threadIdx.x == 0) b_base[ct] = tile_base;
   // K chunk and position inside it of word u
   auto kchunk = [&](uint32_t u) -> int {
     if (!compact) return (int)(u / KC);
@@ -584,7 +627,6 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
   int32_t *choff = b_choff + (int64_t)ct * (P.nch + 1);
   for (int c = threadIdx.x; c <= P.nch; c += 256) choff[c] = off[c];
   __syncthreads();
-  const int64_t tile_base = tgt_off[t0];
   for (int k = 0; k < ROWS_PER_WAVE; ++k) {
     const int r = wave + 4 * k;
     if (first & (1u << k)) {

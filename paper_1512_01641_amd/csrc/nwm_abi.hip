@@ -297,6 +297,11 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   }
   p->n_src = sfirst[B];
   p->n_tgt = tfirst[B];
+  std::vector<TileMeta> rt_meta(rt_pair.size()), ct_meta(ct_pair.size());
+  for (size_t k = 0; k < rt_pair.size(); ++k)
+    rt_meta[k] = TileMeta{sfirst[rt_pair[k]] + rt_row0[k], rt_rows[k], rt_pair[k]};
+  for (size_t k = 0; k < ct_pair.size(); ++k)
+    ct_meta[k] = TileMeta{tfirst[ct_pair[k]] + ct_col0[k], ct_cols[k], ct_pair[k]};
   std::vector<GtMeta> gt_meta(gt_rt.size());
   for (size_t g = 0; g < gt_rt.size(); ++g) {
     GtMeta &x = gt_meta[g];
@@ -369,6 +374,8 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   size_t i_cn = add(ct_cols.data(), 4 * ct_cols.size());
   size_t i_gr = add(gt_rt.data(), 4 * gt_rt.size()), i_gc = add(gt_ct.data(), 4 * gt_ct.size());
   size_t i_gm = add(gt_meta.data(), sizeof(GtMeta) * gt_meta.size());
+  size_t i_rm = add(rt_meta.data(), sizeof(TileMeta) * rt_meta.size());
+  size_t i_cm = add(ct_meta.data(), sizeof(TileMeta) * ct_meta.size());
   size_t i_do = add(order.data(), 4 * order.size());
   size_t i_si = add(sent_ids.data(), 8 * sent_ids.size());
   size_t i_ip = add(it_pair.data(), 4 * it_pair.size()), i_is = add(it_strip.data(), 4 * it_strip.size());
@@ -415,6 +422,8 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   D.gt_rt = (const int32_t *)at(i_gr);
   D.gt_ct = (const int32_t *)at(i_gc);
   D.gt_meta = (const GtMeta *)at(i_gm);
+  D.rt_meta = (const TileMeta *)at(i_rm);
+  D.ct_meta = (const TileMeta *)at(i_cm);
   D.dp_order = (const int32_t *)at(i_do);
   D.sent_ids = (const int64_t *)at(i_si);
   D.n_items = (int)it_pair.size();

@@ -67,6 +67,13 @@ struct GtMeta {
   int64_t pad;
 };
 
+// A row tile (source side) or column tile (target side) in one 16-byte
+// record: its first sentence (batch-wide index), sentence count and pair.
+struct TileMeta {
+  int64_t first;
+  int32_t count, pair;
+};
+
 // Device-resident per-pair metadata of a plan.
 struct PlanDev {
   int B;
@@ -84,6 +91,7 @@ struct PlanDev {
   int n_rt, n_ct;
   const int32_t *rt_pair, *rt_row0, *rt_rows;
   const int32_t *ct_pair, *ct_col0, *ct_cols;
+  const TileMeta *rt_meta, *ct_meta;
   // contraction tiles: (row tile, column tile)
   int n_gt;
   const int32_t *gt_rt, *gt_ct;
