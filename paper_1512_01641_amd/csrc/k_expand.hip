@@ -29,12 +29,14 @@ static __device__ __forceinline__ void wave_sync() {
 
 constexpr uint32_t HEMPTY = 0xFFFFFFFFu;
 
-// Software pipeline of the merge over a wave's sentences.  Every load is a
-// vector load issued ahead of the sentence that needs it: the sentence id
-// five sentences ahead, its token range four ahead, its tokens three ahead
-// (lane l holds token l of the first 64), their dictionary row offsets two
-// ahead and the first four entries of every row one ahead, so each load has
-// a whole sentence of merging to land.  (Scalar loads would share their wait
+// Software pipeline of the merge over a wave's sentences.  A sentence's
+// first 16 * MERGE_ROUNDS tokens are merged in rounds of 16 tokens x 4
+// dictionary entries, one entry per lane: lane l of round q takes entry l % 4
+// of the row of token 16 q + l / 4 (its four lanes load the same token and row
+// offsets).  Every load is a vector load issued ahead of the sentence that
+// needs it: the sentence id five sentences ahead, its token range four ahead,
+// its tokens three ahead, their dictionary row offsets two ahead and the
+// entries one ahead, so each load has a whole sentence of merging to land.  (Scalar loads would share their wait
 // counter with the LDS atomics of the merge and be waited for at the first
 // of them.)  The pipelined loads are unconditional: raw buffer loads with an
 // offset past the buffer for lanes with nothing to load (they read 0), or
@@ -44,6 +46,7 @@ constexpr uint32_t HEMPTY = 0xFFFFFFFFu;
 // buffer stores whose range check drops the lanes past the row's end, so the
 // next wait for the pipelined loads never waits for these stores.
 constexpr int MERGE_OUT_REGS = 4;   // merged entries per lane held for the deferred store
+constexpr int MERGE_ROUNDS = 3;     // pipelined rounds of 16 tokens
 typedef unsigned int m_u32x2 __attribute__((ext_vector_type(2)));
 
 struct MergeId {
@@ -56,17 +59,20 @@ struct MergeOff {
 };
 struct MergeTok {
   int64_t id, t0;
-  int len, tok;
+  int len;
+  int tok[MERGE_ROUNDS];   // the lane's token in each round
 };
 struct MergeRow {
   int64_t id, t0;
-  int len, e0, e1;   // row [e0, e1) of the lane's token (e1 = e0 if none)
+  int len;
+  int e0[MERGE_ROUNDS], e1[MERGE_ROUNDS];   // its row [e0, e1) (e1 = e0 if none)
 };
 struct MergeEnt {
   int64_t id, t0;
-  int len, e0, deg;
-  uint32_t u[4];
-  float v[4];
+  int len;
+  int e0[MERGE_ROUNDS], deg[MERGE_ROUNDS];
+  uint32_t u[MERGE_ROUNDS];   // the lane's entry (valid if lane % 4 < deg)
+  float v[MERGE_ROUNDS];
 };
 struct MergeOut {
   int64_t base, id;
@@ -146,10 +152,11 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
     T.t0 = first_lane64((int64_t)(((uint64_t)O.t0.y << 32) | O.t0.x));
     const int64_t t1 = first_lane64((int64_t)(((uint64_t)O.t1.y << 32) | O.t1.x));
     T.len = O.sent < n_sent ? (int)max(t1 - T.t0, (int64_t)0) : 0;
-    // a buffer over this sentence's first 64 tokens
+    // a buffer over this sentence's first 16 * MERGE_ROUNDS tokens
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(src_tok + T.t0), (short)0, min(T.len, 64) * 4, 0x00020000);
-    T.tok = (int)buf_u32(r, (uint32_t)lane * 4u);
+        (void *)(src_tok + T.t0), (short)0, min(T.len, 16 * MERGE_ROUNDS) * 4, 0x00020000);
+#pragma unroll
+    for (int q = 0; q < MERGE_ROUNDS; ++q) T.tok[q] = (int)buf_u32(r, (uint32_t)(16 * q + (lane >> 2)) * 4u);
     return T;
   };
   auto load_row = [&](const MergeTok &T) {
@@ -157,10 +164,13 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
     R.id = T.id;
     R.t0 = T.t0;
     R.len = T.len;
-    const bool ok = lane < T.len && (unsigned)T.tok < (unsigned)V;
-    const uint32_t off = ok ? (uint32_t)T.tok * 4u : BUF_OOB;
-    R.e0 = (int)buf_u32(r_row, off);
-    R.e1 = (int)buf_u32(r_row, ok ? off + 4u : BUF_OOB);
+#pragma unroll
+    for (int q = 0; q < MERGE_ROUNDS; ++q) {
+      const bool ok = 16 * q + (lane >> 2) < T.len && (unsigned)T.tok[q] < (unsigned)V;
+      const uint32_t off = ok ? (uint32_t)T.tok[q] * 4u : BUF_OOB;
+      R.e0[q] = (int)buf_u32(r_row, off);
+      R.e1[q] = (int)buf_u32(r_row, ok ? off + 4u : BUF_OOB);
+    }
     return R;
   };
   auto load_ent = [&](const MergeRow &R) {
@@ -168,29 +178,32 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
     E.id = R.id;
     E.t0 = R.t0;
     E.len = R.len;
-    E.e0 = R.e0;
-    E.deg = max(0, min(R.e1 - R.e0, max_deg));
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const uint32_t off = d < E.deg ? (uint32_t)(E.e0 + d) * 4u : BUF_OOB;
-      E.u[d] = buf_u32(r_col, off);
-      E.v[d] = __uint_as_float(buf_u32(r_val, off));
+    for (int q = 0; q < MERGE_ROUNDS; ++q) {
+      E.e0[q] = R.e0[q];
+      E.deg[q] = max(0, min(R.e1[q] - R.e0[q], max_deg));
+      const uint32_t off = (lane & 3) < E.deg[q] ? (uint32_t)(E.e0[q] + (lane & 3)) * 4u : BUF_OOB;
+      E.u[q] = buf_u32(r_col, off);
+      E.v[q] = __uint_as_float(buf_u32(r_val, off));
     }
     return E;
   };
   // the merged row held in registers and the count; lanes past the row's end
   // (and every lane of an empty record) fall outside the buffer ranges
+  // (base, id and n are wave-uniform; stating it keeps the resources scalar)
   auto store_out = [&](const MergeOut &M) {
-    const int n = max(M.n, 0);
+    const int n_rec = __builtin_amdgcn_readfirstlane(M.n);
+    const int n = max(n_rec, 0);
+    const int64_t id = first_lane64(M.id);
     const __amdgpu_buffer_rsrc_t r_m =
-        __builtin_amdgcn_make_buffer_rsrc((void *)(merged + M.base), (short)0, n * 8, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc((void *)(merged + first_lane64(M.base)), (short)0, n * 8, 0x00020000);
 #pragma unroll
     for (int r = 0; r < MERGE_OUT_REGS; ++r)
       __builtin_amdgcn_raw_buffer_store_b64((m_u32x2){M.v[r].x, M.v[r].y}, r_m, (uint32_t)(lane + 64 * r) * 8u, 0,
                                             0);
     const __amdgpu_buffer_rsrc_t r_c =
-        __builtin_amdgcn_make_buffer_rsrc((void *)(cnt + M.id), (short)0, M.n >= 0 ? 4 : 0, 0x00020000);
-    __builtin_amdgcn_raw_buffer_store_b32(M.n, r_c, (uint32_t)lane * 4u, 0, 0);
+        __builtin_amdgcn_make_buffer_rsrc((void *)(cnt + id), (short)0, n_rec >= 0 ? 4 : 0, 0x00020000);
+    __builtin_amdgcn_raw_buffer_store_b32(n_rec, r_c, (uint32_t)lane * 4u, 0, 0);
   };
 
   int nuniq = 0;
@@ -221,50 +234,6 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
     nuniq = min(nuniq + __popcll(cm), CAPU);
   };
 
-  // the (up to) four entries of every lane at once: their CAS probes are
-  // issued together, so one LDS round trip serves four entries
-  auto insert4 = [&](const MergeEnt &E) {
-    uint32_t h[4];
-    bool pend[4], claimed[4], placed[4];
-    int probes[4];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const bool act = d < E.deg && E.u[d] < (uint32_t)V;
-      h[d] = act ? (E.u[d] * 0x9E3779B1u) >> (32 - hbits) : 0u;
-      pend[d] = act;
-      claimed[d] = placed[d] = false;
-      probes[d] = 0;
-    }
-    while (__ballot(pend[0] || pend[1] || pend[2] || pend[3]) != 0) {
-      uint32_t old[4];
-#pragma unroll
-      for (int d = 0; d < 4; ++d) old[d] = pend[d] ? atomicCAS(&key[h[d]], HEMPTY, E.u[d]) : HEMPTY;
-#pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        if (!pend[d]) continue;
-        if (old[d] == HEMPTY || old[d] == E.u[d]) {
-          claimed[d] = old[d] == HEMPTY;
-          placed[d] = true;
-          pend[d] = false;
-        } else if (++probes[d] >= HS) {
-          pend[d] = false;   // table full: drop
-        } else {
-          h[d] = (h[d] + 1) & (uint32_t)(HS - 1);
-        }
-      }
-    }
-#pragma unroll
-    for (int d = 0; d < 4; ++d)
-      if (placed[d]) atomicAdd(&acc[h[d]], (double)E.v[d]);
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const uint64_t cm = __ballot(claimed[d]);
-      const int rank = nuniq + __popcll(cm & ((1ull << lane) - 1ull));
-      if (claimed[d] && rank < CAPU) slots[rank] = (int)h[d];
-      nuniq = min(nuniq + __popcll(cm), CAPU);
-    }
-  };
-
   const int64_t G = gridDim.x;
   int64_t sent = blockIdx.x;
   MergeEnt E = load_ent(load_row(load_tok(load_off(load_id(sent)))));
@@ -287,20 +256,28 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
     store_out(out);   // the previous sentence's row
 
     nuniq = 0;
-    // first 64 tokens: entries 0..3 loaded ahead, further entries here
-    insert4(cur);
-    for (int q = 4; q < max_deg; ++q) {
-      if (__ballot(q < cur.deg) == 0) break;
-      uint32_t u = HEMPTY;
-      float v = 0.0f;
-      if (q < cur.deg) {
-        u = (uint32_t)d_col[cur.e0 + q];
-        v = d_val[cur.e0 + q];
+    // first 16 * MERGE_ROUNDS tokens: four entries of every row loaded ahead,
+    // further entries (rows longer than four) here
+    const int rounds = min((cur.len + 15) >> 4, MERGE_ROUNDS);
+#pragma unroll
+    for (int q = 0; q < MERGE_ROUNDS; ++q) {
+      if (q >= rounds) break;
+      insert((lane & 3) < cur.deg[q] ? cur.u[q] : HEMPTY, cur.v[q]);
+      if (max_deg > 4) {
+        for (int d = 4 + (lane & 3);; d += 4) {
+          if (__ballot(d < cur.deg[q]) == 0) break;
+          uint32_t u = HEMPTY;
+          float v = 0.0f;
+          if (d < cur.deg[q]) {
+            u = (uint32_t)d_col[cur.e0[q] + d];
+            v = d_val[cur.e0[q] + d];
+          }
+          insert(u, v);
+        }
       }
-      insert(u, v);
     }
-    // tokens past the first 64 (long sentences)
-    for (int c0 = 64; c0 < cur.len; c0 += 64) {
+    // tokens past those (long sentences), one per lane
+    for (int c0 = 16 * MERGE_ROUNDS; c0 < cur.len; c0 += 64) {
       int e0 = 0, deg = 0;
       if (c0 + lane < cur.len) {
         const int tok = src_tok[cur.t0 + c0 + lane];

@@ -166,6 +166,40 @@ def _wide_vocabulary_batch():
         tgt_tok=rng.integers(0, 4096, size=int(t_len.sum())).astype(np.int32))
 
 
+def _varying_degree_batch():
+    """Six pairs over a dictionary whose rows hold 0 to 11 entries (rows
+    longer than four take the merge's extra passes), with source sentences of
+    0 to 90 tokens (past the first 48 the merge goes one token per lane) and
+    repeated tokens inside a sentence."""
+    import dataclasses
+    b = corpus.make_batch(2, pairs=6, sizes=([5, 70, 64, 1, 130, 33], [9, 66, 64, 40, 20, 1]))
+    rng = np.random.default_rng(12)
+    V = b.V
+    deg = rng.integers(0, 12, size=V)
+    deg[:8] = [0, 11, 5, 4, 3, 8, 1, 0]
+    cols = [np.sort(rng.choice(V, int(k), replace=False)) for k in deg]
+    d_row_off = np.concatenate([[0], np.cumsum(deg)]).astype(np.int32)
+    d_col = np.concatenate(cols).astype(np.int32)
+    d_val = rng.random(int(deg.sum())).astype(np.float32)
+    n_src = int(b.n.sum())
+    s_len = rng.integers(0, 91, size=n_src)
+    s_len[:6] = [0, 1, 47, 48, 49, 90]
+    src_tok = rng.integers(0, 64, size=int(s_len.sum())).astype(np.int32)   # few words: repeats
+    src_tok[: int(s_len[:8].sum())] = rng.integers(0, 8, size=int(s_len[:8].sum()))   # the chosen rows
+    return dataclasses.replace(b, src_off=np.concatenate([[0], np.cumsum(s_len)]).astype(np.int64),
+                               src_tok=src_tok, d_row_off=d_row_off, d_col=d_col, d_val=d_val,
+                               d_deg=int(deg.max()))
+
+
+def test_scores_varying_dictionary_degree_and_long_sentences():
+    w = _varying_degree_batch()
+    for compact in (1, 0):
+        p = {"score_compact": compact}
+        gpu, ora = _check_scores(w, 0, tol_rel=1e-5, params=p)
+        np.testing.assert_allclose(gpu["S_raw"], ora["S_raw"], rtol=1e-5, atol=1e-7)
+        _check_scores(w, 1, tol_abs=2e-2, params=p)
+
+
 @pytest.mark.parametrize("compact", [1, 0])
 def test_scores_compacted_and_dense_contraction(compact):
     # both contraction modes against the oracle: the ragged 40-pair batch and
