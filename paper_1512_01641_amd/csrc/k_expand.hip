@@ -371,14 +371,21 @@ __global__ __launch_bounds__(256) void k_build_a(PlanDev P, const int64_t *__res
                                                  const uint2 *__restrict__ merged,
                                                  const int32_t *__restrict__ cnt, uint2 *__restrict__ a_list,
                                                  int32_t *__restrict__ a_choff, int pitch, int esize, int compact,
-                                                 int64_t *__restrict__ a_base, int r0) {
+                                                 int64_t *__restrict__ a_base, const uint32_t *__restrict__ p_voc,
+                                                 int r0) {
   extern __shared__ __align__(16) char smem[];
   int *off = reinterpret_cast<int *>(smem);  // [nch + 1]
   int *tmp = off + P.nch + 1;                // [256]
+  uint32_t *voc = reinterpret_cast<uint32_t *>(tmp + 256);   // [nch] (with p_voc)
   const int rt = r0 + (int)blockIdx.x;
   const TileMeta tm = P.rt_meta[rt];
   const int rows = tm.count;
   const int64_t s0 = tm.first;
+  // with p_voc: the pair's target vocabulary (one bit per word, KC words per
+  // chunk); an entry whose word no target sentence of the pair holds meets a
+  // zero in every column of every tile of the pair and is left out
+  if (p_voc)
+    for (int w = threadIdx.x; w < P.nch; w += 256) voc[w] = p_voc[(int64_t)tm.pair * P.nch + w];
   // issued with the rows' counts, used for the placement
   const int64_t tile_base = src_off[s0] * (int64_t)P.max_deg;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -416,6 +423,16 @@ __global__ __launch_bounds__(256) void k_build_a(PlanDev P, const int64_t *__res
     for (int q = 0; q < 2; ++q)
       if (64 * q + lane >= row_cnt(k)) e[k][q].x = 0xFFFFFFFFu;
   __syncthreads();
+  auto in_voc = [&](uint32_t u) { return p_voc == nullptr || ((voc[u / KC] >> (u % KC)) & 1u) != 0u; };
+  if (p_voc) {
+#pragma unroll
+    for (int k = 0; k < ROWS_PER_WAVE; ++k)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const uint32_t u = e[k][q].x;
+        if (u != 0xFFFFFFFFu && !in_voc(u)) e[k][q].x = 0xFFFFFFFFu;
+      }
+  }
   // masked-off entries count into the lane's own slot past the table
   // (tmp[lane]: never read), so the atomics need no branches
   const int junk = P.nch + 1 + lane;
@@ -428,7 +445,10 @@ __global__ __launch_bounds__(256) void k_build_a(PlanDev P, const int64_t *__res
     }
     const int c = row_cnt(k);
     const int64_t base = row_base(k);
-    for (int x = 128 + lane; x < c; x += 64) atomicAdd(&off[merged[base + x].x / KC], 1);
+    for (int x = 128 + lane; x < c; x += 64) {
+      const uint32_t u = merged[base + x].x;
+      if (in_voc(u)) atomicAdd(&off[u / KC], 1);
+    }
   }
   __syncthreads();
   block_exclusive_scan(off, P.nch, tmp);
@@ -468,8 +488,10 @@ __global__ __launch_bounds__(256) void k_build_a(PlanDev P, const int64_t *__res
     const int64_t base = row_base(k);
     for (int x = 128 + lane; x < c; x += 64) {
       const uint2 ent = merged[base + x];
-      const int p = atomicAdd(&off[ent.x / KC], 1);
-      a_list[tile_base + p] = make_uint2(a_code(ent.x, r, pitch, esize, compact), ent.y);
+      if (in_voc(ent.x)) {
+        const int p = atomicAdd(&off[ent.x / KC], 1);
+        a_list[tile_base + p] = make_uint2(a_code(ent.x, r, pitch, esize, compact), ent.y);
+      }
     }
   }
 }
@@ -486,7 +508,8 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
                                                  uint32_t *__restrict__ b_list, int32_t *__restrict__ b_choff,
                                                  int pitch, int esize, int compact, uint2 *__restrict__ mt,
                                                  int32_t *__restrict__ kcn, int2 *__restrict__ krng,
-                                                 int64_t *__restrict__ b_base, int c0) {
+                                                 int64_t *__restrict__ b_base, uint32_t *__restrict__ p_voc,
+                                                 int c0) {
   extern __shared__ __align__(16) char smem[];
   int *off = reinterpret_cast<int *>(smem);        // [nch + 1]
   int *tmp = off + P.nch + 1;                      // [256]
@@ -534,6 +557,10 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
       }
     }
     __syncthreads();
+    // the pair's vocabulary is the union of its tiles' (cleared beforehand)
+    if (p_voc)
+      for (int w = threadIdx.x; w < words; w += 256)
+        if (ubits[w]) atomicOr(&p_voc[(int64_t)tm.pair * words + w], ubits[w]);
     for (int w = threadIdx.x; w < words; w += 256) ubase[w] = __popc(ubits[w]);
     __syncthreads();
     block_exclusive_scan(ubase, words, tmp);
@@ -680,11 +707,23 @@ hipError_t launch_merge_src(int64_t n_sent, const int64_t *sent_ids, int64_t k0,
 // Row tiles [r0, r0 + n).
 hipError_t launch_build_a(const PlanDev &P, const int64_t *src_off, const uint2 *merged, const int32_t *cnt,
                           uint2 *a_list, int32_t *a_choff, int pitch, int esize, int compact, int64_t *a_base,
-                          int r0, int n, hipStream_t st) {
+                          const uint32_t *p_voc, int r0, int n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const size_t lds = sizeof(int) * (size_t)(P.nch + 1 + 256);
+  const size_t lds = sizeof(int) * (size_t)(2 * P.nch + 1 + 256);
   hipLaunchKernelGGL(k_build_a, dim3(n), dim3(256), lds, st, P, src_off, merged, cnt, a_list, a_choff, pitch, esize,
-                     compact, a_base, r0);
+                     compact, a_base, p_voc, r0);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_clear_u32(uint32_t *__restrict__ p, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) p[k] = 0u;
+}
+
+// A fill kernel, not a memset: the clear may be captured into a graph.
+hipError_t launch_clear_u32(uint32_t *p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_clear_u32, dim3((unsigned)(blocks < 2048 ? blocks : 2048)), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 
@@ -696,10 +735,10 @@ size_t build_b_lds_bytes(int nch, int V) {
 // Column tiles [c0, c0 + n).
 hipError_t launch_build_b(const PlanDev &P, const int64_t *tgt_off, const int32_t *tgt_tok, uint32_t *b_list,
                           int32_t *b_choff, int pitch, int esize, int compact, uint2 *mt, int32_t *kcn,
-                          int2 *krng, int64_t *b_base, int c0, int n, hipStream_t st) {
+                          int2 *krng, int64_t *b_base, uint32_t *p_voc, int c0, int n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_build_b, dim3(n), dim3(256), build_b_lds_bytes(P.nch, P.V), st, P, tgt_off, tgt_tok, b_list,
-                     b_choff, pitch, esize, compact, mt, kcn, krng, b_base, c0);
+                     b_choff, pitch, esize, compact, mt, kcn, krng, b_base, p_voc, c0);
   return hipGetLastError();
 }
 

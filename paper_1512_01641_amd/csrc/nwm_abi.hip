@@ -18,9 +18,10 @@ namespace nwm {
 hipError_t launch_merge_src(int64_t, const int64_t *, int64_t, const int64_t *, const int32_t *, const int32_t *,
                             const int32_t *, const float *, int, int, int, uint2 *, int32_t *, int, hipStream_t);
 hipError_t launch_build_a(const PlanDev &, const int64_t *, const uint2 *, const int32_t *, uint2 *, int32_t *,
-                          int, int, int, int64_t *, int, int, hipStream_t);
+                          int, int, int, int64_t *, const uint32_t *, int, int, hipStream_t);
 hipError_t launch_build_b(const PlanDev &, const int64_t *, const int32_t *, uint32_t *, int32_t *, int, int, int,
-                          uint2 *, int32_t *, int2 *, int64_t *, int, int, hipStream_t);
+                          uint2 *, int32_t *, int2 *, int64_t *, uint32_t *, int, int, hipStream_t);
+hipError_t launch_clear_u32(uint32_t *, int64_t, hipStream_t);
 hipError_t build_set_attrs(int nch, int V);
 hipError_t launch_score(const PlanDev &, bool, const int64_t *, const int64_t *, const uint2 *, const int32_t *,
                         const uint32_t *, const int32_t *, nwm_scorer, float *, float *, int, int, const uint2 *,
@@ -451,6 +452,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   W.b_rng = carve(8 * (size_t)D.n_ct * (size_t)nch);
   W.a_base = carve(8 * (size_t)D.n_rt);
   W.b_base = carve(8 * (size_t)D.n_ct);
+  W.p_voc = carve(4 * (size_t)B * (size_t)nch);
   W.bwd = carve(16 * ((size_t)B + (size_t)D.n_rt));
   // published rows, + 2 entries (cleared in 16-byte units), + the sink
   W.bnd = carve(8 * ((size_t)bnd_off[B] + 2 + FILL_SINK_SLOTS));
@@ -520,12 +522,19 @@ static nwm_status check_score_args(const nwm_plan *p, const nwm_batch *batch, co
   return NWM_OK;
 }
 
-// The expansion for part of the batch: merged dictionary rows of source
-// sentences sent_ids[k0, k0 + ns) and the lists of row tiles [r0, r0 + nr)
-// (which hold exactly those sentences) on `st`; the lists of column tiles
-// [c0, c0 + nc) on `tst`.
+// The compacted contraction leaves out source entries whose word no target
+// sentence of the pair holds: the column-tile builders form each pair's
+// vocabulary, the row-tile builders of a pair wait for them.
+static uint32_t *pair_vocab(nwm_plan *p, void *ws) {
+  return p->param[NWM_PARAM_SCORE_COMPACT] ? (uint32_t *)(static_cast<char *>(ws) + p->ws.p_voc) : nullptr;
+}
+
+// The source-side expansion of part of the batch on `st`: merged dictionary
+// rows of source sentences sent_ids[k0, k0 + ns), then (once `tgt_done` has
+// been reached, when given: the column tiles of the same pairs are built) the
+// lists of row tiles [r0, r0 + nr), which hold exactly those sentences.
 static hipError_t expand_src(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, void *ws, int64_t k0,
-                             int64_t ns, int r0, int nr, hipStream_t st) {
+                             int64_t ns, int r0, int nr, hipEvent_t tgt_done, hipStream_t st) {
   char *w = static_cast<char *>(ws);
   uint2 *merged = (uint2 *)(w + p->ws.a_merged);
   int32_t *cnt = (int32_t *)(w + p->ws.a_cnt);
@@ -538,33 +547,41 @@ static hipError_t expand_src(nwm_plan *p, const nwm_batch *batch, const nwm_dict
   hipError_t e = launch_merge_src(ns, p->dev.sent_ids, k0, batch->src_off, batch->src_tok, dict->row_off, dict->col,
                                   dict->val, p->V, p->max_deg, p->max_entries, merged, cnt,
                                   p->param[NWM_PARAM_MERGE_WAVES_PER_CU], st);
+  if (e == hipSuccess && tgt_done) e = hipStreamWaitEvent(st, tgt_done, 0);
   if (e == hipSuccess)
     e = launch_build_a(p->dev, batch->src_off, merged, cnt, (uint2 *)(w + p->ws.a_list),
                        (int32_t *)(w + p->ws.a_choff), pitch, esize, p->param[NWM_PARAM_SCORE_COMPACT],
-                       (int64_t *)(w + p->ws.a_base), r0, nr, st);
+                       (int64_t *)(w + p->ws.a_base), pair_vocab(p, ws), r0, nr, st);
   mk.done();
   return e;
 }
 
-static hipError_t expand_tgt(nwm_plan *p, const nwm_batch *batch, void *ws, int c0, int nc, hipStream_t st) {
+// The lists of column tiles [c0, c0 + nc) on `st`; `first` clears the pair
+// vocabularies beforehand (once per pass over the batch).
+static hipError_t expand_tgt(nwm_plan *p, const nwm_batch *batch, void *ws, int c0, int nc, bool first,
+                             hipStream_t st) {
   char *w = static_cast<char *>(ws);
   const bool bf16 = p->prec == NWM_BF16;
+  uint32_t *voc = pair_vocab(p, ws);
+  hipError_t e = hipSuccess;
+  if (first && voc) e = launch_clear_u32(voc, (int64_t)p->B * p->dev.nch, st);
+  if (e != hipSuccess) return e;
   return launch_build_b(p->dev, batch->tgt_off, batch->tgt_tok, (uint32_t *)(w + p->ws.b_list),
                         (int32_t *)(w + p->ws.b_choff), bf16 ? PITCH_BF16 : PITCH_F32, bf16 ? 2 : 4,
                         p->param[NWM_PARAM_SCORE_COMPACT], (uint2 *)(w + p->ws.b_mt), (int32_t *)(w + p->ws.b_kcn),
-                        (int2 *)(w + p->ws.b_rng), (int64_t *)(w + p->ws.b_base), c0, nc, st);
+                        (int2 *)(w + p->ws.b_rng), (int64_t *)(w + p->ws.b_base), voc, c0, nc, st);
 }
 
 // The whole expansion.  The target-side lists do not depend on the source
-// side: they are built on the plan's second stream, forked from and joined
-// back to `st` by events (under graph capture: a parallel branch of the graph).
+// side: they are built on the plan's second stream, forked from `st` by an
+// event, while `st` merges the source rows; the row-tile lists wait for them
+// (under graph capture: a parallel branch of the graph joined there).
 static hipError_t expand_lists(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, void *ws, hipStream_t st) {
   hipError_t e = hipEventRecord(p->ev_fork, st);
   if (e == hipSuccess) e = hipStreamWaitEvent(p->aux_stream, p->ev_fork, 0);
-  if (e == hipSuccess) e = expand_tgt(p, batch, ws, 0, p->dev.n_ct, p->aux_stream);
+  if (e == hipSuccess) e = expand_tgt(p, batch, ws, 0, p->dev.n_ct, true, p->aux_stream);
   if (e == hipSuccess) e = hipEventRecord(p->ev_join, p->aux_stream);
-  if (e == hipSuccess) e = expand_src(p, batch, dict, ws, 0, p->n_src, 0, p->dev.n_rt, st);
-  if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_join, 0);
+  if (e == hipSuccess) e = expand_src(p, batch, dict, ws, 0, p->n_src, 0, p->dev.n_rt, p->ev_join, st);
   return e;
 }
 
@@ -757,9 +774,9 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
   if (e == hipSuccess) e = hipStreamWaitEvent(aux, p->ev_fork, 0);
   if (e == hipSuccess) e = hipStreamWaitEvent(xs, p->ev_fork, 0);
   if (scored) {
-    if (e == hipSuccess) e = expand_tgt(p, batch, ws, 0, cl, aux);
+    if (e == hipSuccess) e = expand_tgt(p, batch, ws, 0, cl, true, aux);
     if (e == hipSuccess) e = hipEventRecord(p->ev_b_long, aux);
-    if (e == hipSuccess) e = expand_tgt(p, batch, ws, cl, D.n_ct - cl, aux);
+    if (e == hipSuccess) e = expand_tgt(p, batch, ws, cl, D.n_ct - cl, false, aux);
   }
   if (e == hipSuccess) e = hipEventRecord(p->ev_b_rest, aux);
   if (e == hipSuccess) e = launch_nw_reset(D, gap, score, bnd, p->n_bnd, ctl, st);
@@ -767,11 +784,11 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
     // the long pairs: expand and score on the main stream, then their DP on
     // the lane stream while the main stream goes on with the rest
     if (scored) {
-      if (e == hipSuccess) e = expand_src(p, batch, dict, ws, 0, kl, 0, rl, st);
-      if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_b_long, 0);
+      if (e == hipSuccess) e = expand_src(p, batch, dict, ws, 0, kl, 0, rl, p->ev_b_long, st);
       if (e == hipSuccess) e = score_tiles(p, batch, sc, S, S_raw, ws, 0, gl, st);
     }
-    if (e == hipSuccess && scored) e = expand_src(p, batch, dict, ws, kl, p->n_src - kl, rl, D.n_rt - rl, xs);
+    if (e == hipSuccess && scored)
+      e = expand_src(p, batch, dict, ws, kl, p->n_src - kl, rl, D.n_rt - rl, p->ev_b_rest, xs);
     if (e == hipSuccess) e = hipEventRecord(p->ev_a_rest, xs);
     if (e == hipSuccess) e = hipEventRecord(p->ev_long, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(lane, p->ev_long, 0);
@@ -782,7 +799,7 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
     if (e == hipSuccess) e = hipEventRecord(p->ev_long_done, lane);
   }
   if (ol == 0) {
-    if (e == hipSuccess && scored) e = expand_src(p, batch, dict, ws, 0, p->n_src, 0, D.n_rt, xs);
+    if (e == hipSuccess && scored) e = expand_src(p, batch, dict, ws, 0, p->n_src, 0, D.n_rt, p->ev_b_rest, xs);
     if (e == hipSuccess) e = hipEventRecord(p->ev_a_rest, xs);
   }
   if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_a_rest, 0);

@@ -117,6 +117,7 @@ struct WsLayout {
   size_t b_rng;      // int32 [n_ct * nch][2] first / last global chunk of each compacted chunk
   size_t a_base;     // int64 [n_rt] first A-list entry of each row tile
   size_t b_base;     // int64 [n_ct] first B-list entry of each column tile
+  size_t p_voc;      // uint32 [B * ceil(V / 32)] target vocabulary of each pair (compacted contraction)
   size_t bwd;        // float [B * 4] per-pair partials + float [n_blocks * 4]
   size_t bnd;        // uint64 (value, epoch) boundary rows between strips
   size_t ctl;        // int32 [2]: DP queue head, error flag
