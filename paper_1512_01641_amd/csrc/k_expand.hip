@@ -454,7 +454,7 @@ __global__ __launch_bounds__(256) void k_build_a(PlanDev P, const int64_t *__res
   block_exclusive_scan(off, P.nch, tmp);
   int32_t *choff = a_choff + (int64_t)rt * (P.nch + 1);
   for (int c = threadIdx.x; c <= P.nch; c += 256) choff[c] = off[c];
-  const int total = off[P.nch];   // entries of the tile
+  const int total = __builtin_amdgcn_readfirstlane(off[P.nch]);   // entries of the tile (wave-uniform)
   __syncthreads();
   if (threadIdx.x == 0) a_base[rt] = tile_base;
   // placement: every position is taken first, then every entry is stored by
@@ -526,35 +526,52 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
   uint32_t *mybits = bits + wave * words;
   for (int c = threadIdx.x; c <= P.nch; c += 256) off[c] = 0;
   for (int w = lane; w < words; w += 64) mybits[w] = 0u;
-  if (compact)
-    for (int w = threadIdx.x; w < words; w += 256) ubits[w] = 0u;
-  // sentences of this wave: lane k fetches sentence wave + 4k's token range,
-  // then the first 64 tokens of every sentence are loaded together
+  // sentences of this wave: lane k fetches sentence wave + 4k's token range
+  // (sentences past the tile read sentence 0 and length 0), then the first
+  // 64 tokens of every sentence are loaded together by unconditional buffer
+  // loads (tokens past a sentence's length fall outside its buffer range)
   const int mycol = wave + 4 * lane;
   const bool vk = lane < ROWS_PER_WAVE && mycol < cols;
-  const int64_t q0 = vk ? tgt_off[t0 + mycol] : 0;
-  const int ql = vk ? (int)(tgt_off[t0 + mycol + 1] - q0) : 0;
+  const int64_t tq = t0 + (vk ? mycol : 0);
+  const int64_t q0 = tgt_off[tq];
+  const int ql = vk ? (int)(tgt_off[tq + 1] - q0) : 0;
+  auto sent_len = [&](int k) { return __builtin_amdgcn_readlane(ql, k); };
+  auto sent_off = [&](int k) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)q0, k);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)q0 >> 32), k);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+  };
   uint32_t tok[ROWS_PER_WAVE];
 #pragma unroll
   for (int k = 0; k < ROWS_PER_WAVE; ++k) {
-    const int64_t a = __shfl(q0, k, 64);
-    const int l = __shfl(ql, k, 64);
-    tok[k] = lane < l ? (uint32_t)tgt_tok[a + lane] : 0xFFFFFFFFu;
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(tgt_tok + sent_off(k)), (short)0,
+        __builtin_amdgcn_readfirstlane(min(max(sent_len(k), 0), 64) * 4), 0x00020000);
+    tok[k] = buf_u32(r, (uint32_t)lane * 4u);
   }
+#pragma unroll
+  for (int k = 0; k < ROWS_PER_WAVE; ++k)
+    if (lane >= sent_len(k)) tok[k] = 0xFFFFFFFFu;
   __syncthreads();
   if (compact) {
-    // the tile's vocabulary: union of its sentences' words, then the
-    // compacted position base of every chunk
+    // the tile's vocabulary: union of its sentences' words (each wave ORs
+    // its sentences into its own bitmap, then the four are combined), then
+    // the compacted position base of every chunk
 #pragma unroll
     for (int k = 0; k < ROWS_PER_WAVE; ++k) {
       const uint32_t u = tok[k];
-      if (u < (uint32_t)P.V) atomicOr(&ubits[u >> 5], 1u << (u & 31));
-      const int64_t a = __shfl(q0, k, 64);
-      const int l = __shfl(ql, k, 64);
+      if (u < (uint32_t)P.V) atomicOr(&mybits[u >> 5], 1u << (u & 31));
+      const int64_t a = sent_off(k);
+      const int l = sent_len(k);
       for (int x = 64 + lane; x < l; x += 64) {
         const uint32_t v = (uint32_t)tgt_tok[a + x];
-        if (v < (uint32_t)P.V) atomicOr(&ubits[v >> 5], 1u << (v & 31));
+        if (v < (uint32_t)P.V) atomicOr(&mybits[v >> 5], 1u << (v & 31));
       }
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < words; w += 256) {
+      ubits[w] = bits[w] | bits[words + w] | bits[2 * words + w] | bits[3 * words + w];
+      bits[w] = bits[words + w] = bits[2 * words + w] = bits[3 * words + w] = 0u;
     }
     __syncthreads();
     // the pair's vocabulary is the union of its tiles' (cleared beforehand)
@@ -609,8 +626,8 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
         atomicAdd(&off[kchunk(u)], 1);
       }
     }
-    const int64_t a = __shfl(q0, k, 64);
-    const int l = __shfl(ql, k, 64);
+    const int64_t a = sent_off(k);
+    const int l = sent_len(k);
     for (int x = 64 + lane; x < l; x += 64) {   // long sentences
       const uint32_t v = (uint32_t)tgt_tok[a + x];
       if (v < (uint32_t)P.V) {
@@ -638,8 +655,8 @@ __global__ __launch_bounds__(256) void k_build_b(PlanDev P, const int64_t *__res
       const int pos = atomicAdd(&off[kchunk(u)], 1);
       b_list[tile_base + pos] = kcode(u, r);
     }
-    const int64_t a = __shfl(q0, k, 64);
-    const int l = __shfl(ql, k, 64);
+    const int64_t a = sent_off(k);
+    const int l = sent_len(k);
     if (l > 64) {   // long sentences: redo the first-occurrence test
       const uint32_t u = tok[k];
       if (u < (uint32_t)P.V) atomicOr(&mybits[u >> 5], 1u << (u & 31));
