@@ -103,7 +103,11 @@ struct nwm_plan {
   // others
   int n_gt_long = 0, n_items_long = 0, n_pairs_long = 0, n_rt_long = 0, n_ct_long = 0;
   int64_t n_sent_long = 0;
-  hipStream_t lane_stream = nullptr;   // the long pairs' DP
+  // the first of the long pairs (chain >= TOP_CHAIN_PERCENT of the longest):
+  // their contraction tiles, DP items and pairs lead the long pairs' ranges
+  int n_gt_top = 0, n_items_top = 0, n_pairs_top = 0;
+  hipStream_t lane_stream = nullptr;   // the top pairs' DP
+  hipEvent_t ev_top = nullptr, ev_top_done = nullptr;
   hipStream_t exp_stream = nullptr;    // the other pairs' source-side expansion
   hipEvent_t ev_long = nullptr, ev_long_done = nullptr, ev_b_long = nullptr, ev_b_rest = nullptr;
   hipEvent_t ev_a_rest = nullptr;
@@ -260,15 +264,27 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   for (int b = 0; b < B; ++b)
     is_long[b] = p->n[b] > 0 && p->m[b] > 0 && p->max_chain > 0 &&
                  100 * chain(b) >= (int64_t)LONG_CHAIN_PERCENT * p->max_chain;
-  // tiles and source sentences in lane order: the long pairs first, then the
-  // others (each group in pair order)
+  std::vector<char> is_top(B, 0);
+  for (int b = 0; b < B; ++b)
+    is_top[b] = is_long[b] && 100 * chain(b) >= (int64_t)TOP_CHAIN_PERCENT * p->max_chain;
+  // tiles and source sentences in lane order: the long pairs first (longest
+  // chain first, so the top pairs lead), then the others in pair order
+  std::vector<int32_t> lane_pairs;
+  for (int b = 0; b < B; ++b)
+    if (is_long[b]) lane_pairs.push_back(b);
+  std::stable_sort(lane_pairs.begin(), lane_pairs.end(), [&](int a, int c) { return chain(a) > chain(c); });
+  const size_t n_long_pairs = lane_pairs.size();
+  for (int b = 0; b < B; ++b)
+    if (!is_long[b]) lane_pairs.push_back(b);
   std::vector<int64_t> sent_ids;
   sent_ids.reserve((size_t)sfirst[B]);
   p->n_rt_long = p->n_ct_long = p->n_gt_long = 0;
   p->n_sent_long = 0;
+  p->n_gt_top = 0;
   for (int pass = 0; pass < 2; ++pass) {
-    for (int b = 0; b < B; ++b) {
-      if ((is_long[b] != 0) != (pass == 0)) continue;
+    const size_t q0 = pass == 0 ? 0 : n_long_pairs, q1 = pass == 0 ? n_long_pairs : lane_pairs.size();
+    for (size_t q = q0; q < q1; ++q) {
+      const int b = lane_pairs[q];
       const int64_t nb = p->n[b], mb = p->m[b];
       for (int64_t i = sfirst[b]; i < sfirst[b + 1]; ++i) sent_ids.push_back(i);
       const int rt0 = (int)rt_pair.size(), ct0 = (int)ct_pair.size();
@@ -288,6 +304,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
           gt_rt.push_back(rt0 + ri);
           gt_ct.push_back(ct0 + ci);
         }
+      if (is_top[b]) p->n_gt_top = (int)gt_rt.size();
     }
     if (pass == 0) {
       p->n_rt_long = (int)rt_pair.size();
@@ -328,8 +345,11 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
     if (is_long[a]) return chain(a) > chain(c);
     return (int64_t)p->n[a] * p->m[a] > (int64_t)p->n[c] * p->m[c];
   });
-  p->n_pairs_long = 0;
-  for (int b = 0; b < B; ++b) p->n_pairs_long += is_long[b] ? 1 : 0;
+  p->n_pairs_long = p->n_pairs_top = 0;
+  for (int b = 0; b < B; ++b) {
+    p->n_pairs_long += is_long[b] ? 1 : 0;
+    p->n_pairs_top += is_top[b] ? 1 : 0;
+  }
   // DP work items: every strip of every non-empty pair, longest pair first;
   // boundary rows between consecutive strips
   std::vector<int32_t> it_pair, it_strip;
@@ -350,6 +370,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
       p->it_chain.push_back(chain(b));
     }
     if (is_long[b]) p->n_items_long = (int)it_pair.size();
+    if (is_top[b]) p->n_items_top = (int)it_pair.size();
   }
   hot_flags(p, it_strip);
   // ---- device metadata: one allocation -----------------------------------------
@@ -495,6 +516,8 @@ void nwm_plan_destroy(nwm_plan *plan) {
   if (plan->exp_stream) (void)hipStreamDestroy(plan->exp_stream);
   if (plan->ev_a_rest) (void)hipEventDestroy(plan->ev_a_rest);
   if (plan->ev_long_done) (void)hipEventDestroy(plan->ev_long_done);
+  if (plan->ev_top) (void)hipEventDestroy(plan->ev_top);
+  if (plan->ev_top_done) (void)hipEventDestroy(plan->ev_top_done);
   if (plan->dmeta) (void)hipFree(plan->dmeta);
   delete plan;
 }
@@ -611,6 +634,8 @@ static hipError_t ensure_streams(nwm_plan *p) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_long_done, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_b_long, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_b_rest, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_top, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_top_done, hipEventDisableTiming);
   return e;
 }
 
@@ -779,28 +804,43 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
     if (e == hipSuccess) e = expand_tgt(p, batch, ws, cl, D.n_ct - cl, false, aux);
   }
   if (e == hipSuccess) e = hipEventRecord(p->ev_b_rest, aux);
+  // the other pairs' source-side expansion, issued before any DP so that it
+  // does not queue behind one
+  if (e == hipSuccess && scored)
+    e = expand_src(p, batch, dict, ws, kl, p->n_src - kl, rl, D.n_rt - rl, p->ev_b_rest, xs);
+  if (e == hipSuccess) e = hipEventRecord(p->ev_a_rest, xs);
   if (e == hipSuccess) e = launch_nw_reset(D, gap, score, bnd, p->n_bnd, ctl, st);
+  const int gtop = p->n_gt_top, itop = p->n_items_top, otop = p->n_pairs_top;
   if (ol > 0) {
-    // the long pairs: expand and score on the main stream, then their DP on
-    // the lane stream while the main stream goes on with the rest
+    // the long pairs: expand and score on the main stream, the top pairs'
+    // tiles first; the top pairs' DP on the lane stream as soon as their
+    // tiles are scored, the other long pairs' DP after theirs on the side
+    // stream that built the column tiles (four streams in all, one hardware
+    // queue each), while the main stream goes on with the rest
     if (scored) {
       if (e == hipSuccess) e = expand_src(p, batch, dict, ws, 0, kl, 0, rl, p->ev_b_long, st);
-      if (e == hipSuccess) e = score_tiles(p, batch, sc, S, S_raw, ws, 0, gl, st);
+      if (e == hipSuccess) e = score_tiles(p, batch, sc, S, S_raw, ws, 0, gtop, st);
     }
-    if (e == hipSuccess && scored)
-      e = expand_src(p, batch, dict, ws, kl, p->n_src - kl, rl, D.n_rt - rl, p->ev_b_rest, xs);
-    if (e == hipSuccess) e = hipEventRecord(p->ev_a_rest, xs);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_top, st);
+    if (e == hipSuccess && scored) e = score_tiles(p, batch, sc, S, S_raw, ws, gtop, gl - gtop, st);
     if (e == hipSuccess) e = hipEventRecord(p->ev_long, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(lane, p->ev_long, 0);
-    if (e == hipSuccess)
-      e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl + 2, ctl + 1, 0, il, wpc, lane);
-    if (e == hipSuccess) e = launch_nw_walk(D, tbc, path, n_diag, 0, ol, lane);
-    if (e == hipSuccess) e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, 0, ol, lane);
-    if (e == hipSuccess) e = hipEventRecord(p->ev_long_done, lane);
-  }
-  if (ol == 0) {
-    if (e == hipSuccess && scored) e = expand_src(p, batch, dict, ws, 0, p->n_src, 0, D.n_rt, p->ev_b_rest, xs);
-    if (e == hipSuccess) e = hipEventRecord(p->ev_a_rest, xs);
+    if (otop > 0) {
+      if (e == hipSuccess) e = hipStreamWaitEvent(lane, p->ev_top, 0);
+      if (e == hipSuccess)
+        e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl + 2, ctl + 1, 0, itop, wpc, lane);
+      if (e == hipSuccess) e = launch_nw_walk(D, tbc, path, n_diag, 0, otop, lane);
+      if (e == hipSuccess) e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, 0, otop, lane);
+      if (e == hipSuccess) e = hipEventRecord(p->ev_top_done, lane);
+    }
+    if (ol > otop) {
+      if (e == hipSuccess) e = hipStreamWaitEvent(aux, p->ev_long, 0);
+      if (e == hipSuccess)
+        e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl + 3, ctl + 1, itop, il - itop, wpc, aux);
+      if (e == hipSuccess) e = launch_nw_walk(D, tbc, path, n_diag, otop, ol - otop, aux);
+      if (e == hipSuccess)
+        e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, otop, ol - otop, aux);
+      if (e == hipSuccess) e = hipEventRecord(p->ev_long_done, aux);
+    }
   }
   if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_a_rest, 0);
   if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_b_rest, 0);
@@ -809,7 +849,8 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
     e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl, ctl + 1, il, D.n_items - il, wpc, st);
   if (e == hipSuccess) e = launch_nw_walk(D, tbc, path, n_diag, ol, p->B - ol, st);
   if (e == hipSuccess) e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, ol, p->B - ol, st);
-  if (e == hipSuccess && ol > 0) e = hipStreamWaitEvent(st, p->ev_long_done, 0);
+  if (e == hipSuccess && ol > 0 && otop > 0) e = hipStreamWaitEvent(st, p->ev_top_done, 0);
+  if (e == hipSuccess && ol > otop) e = hipStreamWaitEvent(st, p->ev_long_done, 0);
   return dev_err(e);
 }
 

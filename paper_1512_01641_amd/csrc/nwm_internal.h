@@ -50,6 +50,10 @@ constexpr int32_t ITEM_HOT = 1 << 30;   // DP item flag: strip of a critical-cha
 // Pairs whose DP dependency chain is at least this percent of the longest are
 // the "long" pairs: prepared, scored and aligned ahead of the others.
 constexpr int LONG_CHAIN_PERCENT = 25;
+// Of those, the pairs whose chain is at least this percent of the longest are
+// the "top" pairs: scored first, their DP started as soon as their own tiles
+// are scored.
+constexpr int TOP_CHAIN_PERCENT = 60;
 
 // Direction codes of the traceback.
 constexpr int DIR_DIAG = 0, DIR_UP = 1, DIR_LEFT = 2;
