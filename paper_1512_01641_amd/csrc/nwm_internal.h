@@ -49,7 +49,7 @@ constexpr int MAX_M = 1 << 22;           // target sentences per pair (a 64-row 
 constexpr int32_t ITEM_HOT = 1 << 30;   // DP item flag: strip of a critical-chain pair
 // Pairs whose DP dependency chain is at least this percent of the longest are
 // the "long" pairs: prepared, scored and aligned ahead of the others.
-constexpr int LONG_CHAIN_PERCENT = 25;
+constexpr int LONG_CHAIN_PERCENT = 15;
 // Of those, the pairs whose chain is at least this percent of the longest are
 // the "top" pairs: scored first, their DP started as soon as their own tiles
 // are scored.
