@@ -410,6 +410,47 @@ def test_backward_matches_finite_differences():
         np.testing.assert_array_equal(blk, ind)
 
 
+@pytest.mark.parametrize("a_scale", [0.0, 1.0])
+def test_backward_dense_extra_term_matches_finite_differences(a_scale):
+    """Sec. 5.2 tuning gradient with an extra dense upstream E = dL/dS:
+    L(w) = sum_b a_b * PathSum_b(S(w)) + sum_ij E_ij * S_ij(w) on the fixed
+    traced path.  Centred differences of L in w0, w1 and b (FP64 scores, the
+    path held fixed) pin the chain dL/dz = (a P + E) S (1 - S) and its sums
+    against S_raw, rho and 1; grad_S must be E + a P cell for cell.  With
+    a = 0 the dense term is checked on its own."""
+    b = corpus.make_batch(4, pairs=5)
+    w = np.array([2.5, -0.75, -0.5])
+    sc = oracle.score(b, scorer=w)
+    res = oracle.align(b.n, b.m, sc["S32"], b.gap, b.threshold)
+    a = a_scale * np.linspace(0.5, 1.5, b.B)
+    E = np.random.default_rng(23).normal(size=sc["S64"].shape[0])
+    bw = oracle.backward(b.n, b.m, res, a, sc["S64"], sc["S_raw"], sc["rho"], grad_S_extra=E)
+
+    def loss(wv):
+        s = oracle.score(b, scorer=wv)["S64"]
+        tot = float(np.dot(E, s))
+        for q in range(b.B):
+            o = sc["s_off"][q]
+            for i, j in oracle.pair_path(res, q):
+                tot += a[q] * s[o + i * b.m[q] + j]
+        return tot
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = 1e-5
+        fd = (loss(w + e) - loss(w - e)) / 2e-5
+        assert fd == pytest.approx(bw["grad_wb"][c], rel=1e-6, abs=1e-8)
+    # dL/dS = E + a P, element for element (P = the traced path's DIAG cells)
+    expect = E.copy()
+    for q in range(b.B):
+        o = sc["s_off"][q]
+        for i, j in oracle.pair_path(res, q):
+            expect[o + i * b.m[q] + j] += a[q]
+    np.testing.assert_array_equal(bw["grad_S"], expect)
+    # the gap gradient does not see E
+    G = (b.n + b.m - 2 * res["n_diag"]).astype(np.float64)
+    assert bw["grad_gap"] == pytest.approx(float(np.dot(a, G)), rel=1e-12, abs=0)
+
+
 def test_backward_fd_in_S_on_unique_paths():
     rng = np.random.default_rng(22)
     n, m = 12, 15
