@@ -157,18 +157,35 @@ nwm_status nwm_score_pairs(nwm_plan *plan, const nwm_batch *batch, const nwm_dic
  *   n_kept  device [B];
  *   tb      device [tb_bytes] opaque traceback (direction bits + path), read
  *           by nwm_align_backward;
- *   ws      device [ws_bytes]. */
+ *   ws      device [ws_bytes].
+ * The strips of a tall pair run on different waves that hand rows to each
+ * other; a wave that waits longer than its poll limit (NWM_PARAM_DP_SPIN_LIMIT)
+ * gives up.  The call still returns NWM_OK (it does not wait for the
+ * kernels); the failed pairs get score NaN, n_diag 0 and n_kept 0, and
+ * nwm_align_check reports the failure. */
 nwm_status nwm_align_batch(nwm_plan *plan, const float *S, float gap, float threshold,
                            float *score, int32_t *n_diag, int32_t *kept, int32_t *n_kept,
                            void *tb, void *ws, void *stream);
 
+/* Status of the last nwm_align_batch or nwm_mine that ran on workspace `ws`
+ * with this plan: waits for `stream` (synchronous), then returns NWM_EDEVICE
+ * if a DP wave gave up waiting for the strip above it (the pairs concerned
+ * have a NaN score and no aligned or kept pairs), else NWM_OK.  `failed`
+ * (host, nullable) receives 1 or 0 likewise.  NWM_EINVAL for a NULL plan or
+ * (B > 0) a NULL ws. */
+nwm_status nwm_align_check(const nwm_plan *plan, const void *ws, int32_t *failed, void *stream);
+
 /* Backward of L = sum_b grad_score[b] * Score_b + sum_ij grad_S_extra[ij] * S[ij]
- * through the alignment and the logistic scorer.  The NW score is a maximum
- * of affine path sums, so dScore_b/dS = P_b (indicator of the aligned cells
- * of the traced path) and dScore_b/dgap = n_b + m_b - 2 k_b; the chain through
- * the sigmoid uses dS/dz = S (1 - S).
- *   tb, n_diag   from nwm_align_batch on the same plan;
- *   grad_score   device [B] dL/dScore_b (FP32);
+ * through the alignment and the logistic scorer, for gradient tuning of the
+ * scorer and the gap penalty (Sec. 5.2 tunes threshold and penalty against
+ * reference alignments).  The NW score (Sec. 5.1) is a maximum of affine path
+ * sums, so dScore_b/dS = P_b (indicator of the aligned cells of the traced
+ * path) and dScore_b/dgap = n_b + m_b - 2 k_b, exact where the optimal path is
+ * unique; the chain through the sigmoid (Sec. 4) uses dS/dz = S (1 - S).
+ *   tb, n_diag   from nwm_align_batch on the same plan (read only when
+ *                grad_score is given; path cells outside a pair are skipped);
+ *   grad_score   device [B] dL/dScore_b (FP32), or NULL: no score term (the
+ *                path is not read, grad_gap is 0);
  *   grad_S_extra device [S_elems] or NULL: extra dense dL/dS;
  *   grad_S       device [S_elems] or NULL: receives dL/dS (FP32);
  *   grad_gap     device double [1] or NULL: dL/dgap;
@@ -239,6 +256,12 @@ nwm_status nwm_union_kept(const nwm_plan *plan, const int32_t *kept_fwd, const i
  *                                 0 = over the whole vocabulary.  Default 1.
  *                                 The FP32 sums are taken in another order, so
  *                                 S may differ in the last bits.
+ *   NWM_PARAM_DP_SPIN_LIMIT       polls of the row above before a DP wave gives
+ *                                 up (0 = the default, 2^22; at most 2^30)
+ *   NWM_PARAM_DP_TEST_HOLD        testing only: 1 = the first strip of every
+ *                                 pair taller than one strip publishes nothing,
+ *                                 so the strips below it give up (exercises the
+ *                                 failure report of nwm_align_check); default 0
  * Out-of-range values give NWM_EINVAL.  Setting DP_HOT_PERCENT uploads the
  * plan's work list (synchronous).  A graph captured by nwm_mine is captured
  * again after any change. */
@@ -247,7 +270,10 @@ typedef enum {
   NWM_PARAM_MERGE_WAVES_PER_CU = 1,
   NWM_PARAM_SCORE_XCD_MAP = 2,
   NWM_PARAM_DP_HOT_PERCENT = 3,
-  NWM_PARAM_SCORE_COMPACT = 4
+  NWM_PARAM_SCORE_COMPACT = 4,
+  NWM_PARAM_DP_SPIN_LIMIT = 5,
+  NWM_PARAM_DP_TEST_HOLD = 6,
+  NWM_N_PARAMS = 7
 } nwm_param;
 nwm_status nwm_plan_set_param(nwm_plan *plan, nwm_param param, int32_t value);
 nwm_status nwm_plan_get_param(const nwm_plan *plan, nwm_param param, int32_t *value);

@@ -21,8 +21,8 @@ from . import _abi
 from ._abi import NWM_BF16, NWM_FP32, NwmError
 
 __all__ = ["Context", "DeviceBatch", "DeviceDict", "Plan", "Miner", "BiMiner", "score_pairs", "align_batch",
-           "align_backward", "mine", "union_kept", "NWAlign", "MineScore", "LogisticScore", "NWM_FP32", "NWM_BF16",
-           "NwmError"]
+           "align_check", "align_backward", "mine", "union_kept", "NWAlign", "MineScore", "LogisticScore", "NWM_FP32",
+           "NWM_BF16", "NwmError"]
 
 
 def _ptr(t):
@@ -203,9 +203,21 @@ def align_batch(plan: Plan, S, gap: float, threshold: float, score, n_diag, kept
                "nwm_align_batch")
 
 
+def align_check(plan: Plan, ws) -> bool:
+    """nwm_align_check: waits for the current stream and returns True if a DP
+    wave of the last alignment on `ws` gave up (those pairs have a NaN score
+    and no aligned pairs), False otherwise."""
+    failed = ctypes.c_int32(0)
+    st = plan.lib.nwm_align_check(plan.h, _ptr(ws), ctypes.byref(failed), _stream(plan.ctx.device))
+    if st not in (_abi.NWM_OK, _abi.NWM_EDEVICE) or (st == _abi.NWM_EDEVICE and not failed.value):
+        _abi.check(st, "nwm_align_check")
+    return bool(failed.value)
+
+
 def align_backward(plan: Plan, batch: DeviceBatch, tb, n_diag, grad_score, grad_S_extra=None, grad_S=None,
                    grad_gap=None, S=None, S_raw=None, scorer=(0.0, 0.0, 0.0), grad_wb=None, ws=None):
-    """nwm_align_backward on the current stream."""
+    """nwm_align_backward on the current stream.  grad_score may be None (no
+    score term: tb and n_diag are then not read)."""
     ws = plan.workspace() if ws is None else ws
     _abi.check(plan.lib.nwm_align_backward(plan.h, ctypes.byref(batch.c()), _ptr(tb), _ptr(n_diag),
                                            _ptr(grad_score), _ptr(grad_S_extra), _ptr(grad_S), _ptr(grad_gap),
@@ -240,9 +252,10 @@ class Miner:
         self.S = torch.empty(max(p.S_elems, 1), dtype=torch.float32, device=dev)
         self.S_raw = torch.empty(max(p.S_elems, 1), dtype=torch.float32, device=dev)
         B = batch.B
-        self.score = torch.empty(max(B, 1), dtype=torch.float32, device=dev)
-        self.n_diag = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
-        self.n_kept = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
+        # zeroed: a backward before any alignment reads an empty path
+        self.score = torch.zeros(max(B, 1), dtype=torch.float32, device=dev)
+        self.n_diag = torch.zeros(max(B, 1), dtype=torch.int32, device=dev)
+        self.n_kept = torch.zeros(max(B, 1), dtype=torch.int32, device=dev)
         self.kept = torch.empty((max(p.kept_cap, 1), 2), dtype=torch.int32, device=dev)
         self.tb = torch.empty(max(p.tb_bytes, 1), dtype=torch.uint8, device=dev)
         self.s_off = np.concatenate([[0], np.cumsum(batch.n.astype(np.int64) * batch.m)]).astype(np.int64)
@@ -268,6 +281,12 @@ class Miner:
             self._graph_on = True
         mine(self.plan, self.batch, self.dic, scorer, gap, threshold, self.S, self.S_raw if want_raw else None,
              self.score, self.n_diag, self.kept, self.n_kept, self.tb, self.ws)
+
+    def check(self):
+        """Raise NwmError(NWM_EDEVICE) if a DP wave of the last alignment gave
+        up waiting for the strip above it (waits for the current stream)."""
+        if align_check(self.plan, self.ws):
+            raise NwmError(_abi.NWM_EDEVICE, "nwm_align_check")
 
     def kept_pairs(self, b: int):
         """Kept (i, j) pairs of pair b (host copy)."""
@@ -308,73 +327,115 @@ class BiMiner:
         return self.kept[o:o + k].cpu().numpy()
 
 
+def _gap_grad(ctx, gg):
+    """dL/dgap in the type and on the device of the gap argument, or None
+    when the gap is a plain number or needs no gradient."""
+    if gg is None or not ctx.gap_tensor:
+        return None
+    return gg.to(dtype=ctx.gap_dtype, device=ctx.gap_device).reshape(ctx.gap_shape)
+
+
+def _save_gap(ctx, gap):
+    ctx.gap_tensor = torch.is_tensor(gap)
+    if ctx.gap_tensor:
+        ctx.gap_dtype, ctx.gap_device, ctx.gap_shape = gap.dtype, gap.device, gap.shape
+
+
 class LogisticScore(torch.autograd.Function):
-    """S = sigmoid(w0 S_raw + w1 rho + b) for every sentence pair; backward
-    gives dL/dw from dL/dS (through nwm_align_backward with zero score grad)."""
+    """S = sigmoid(w0 S_raw + w1 rho + b) for every sentence pair (Sec. 4),
+    returned as a flat [S_elems] tensor in the plan's layout.  Backward:
+    dL/dw from dL/dS through nwm_align_backward with no score term (the
+    alignment is not involved)."""
 
     @staticmethod
     def forward(ctx, w, miner: Miner):
-        miner.score_pairs(w)
+        miner.score_pairs(w, want_raw=True)
+        P = miner.plan.S_elems
+        S = miner.S[:P].clone()
+        ctx.save_for_backward(S, miner.S_raw[:P].clone())
         ctx.miner = miner
         ctx.w = w.detach().cpu()
-        ctx.wdev = w.device
-        return miner.S.clone()
+        ctx.w_dtype, ctx.w_device = w.dtype, w.device
+        return S
 
     @staticmethod
     def backward(ctx, gS):
+        if not ctx.needs_input_grad[0]:
+            return None, None
         mn = ctx.miner
-        dev = mn.ctx.device
-        zero = torch.zeros(max(mn.batch.B, 1), dtype=torch.float32, device=dev)
-        gwb = torch.zeros(3, dtype=torch.float64, device=dev)
-        align_backward(mn.plan, mn.batch, mn.tb, mn.n_diag, zero, grad_S_extra=gS.contiguous().float(),
-                       S=mn.S, S_raw=mn.S_raw, scorer=ctx.w, grad_wb=gwb, ws=mn.ws)
-        return gwb.to(dtype=torch.float32, device=ctx.wdev), None
+        S, S_raw = ctx.saved_tensors
+        gwb = torch.zeros(3, dtype=torch.float64, device=mn.ctx.device)
+        align_backward(mn.plan, mn.batch, None, None, None, grad_S_extra=gS.contiguous().float(), S=S, S_raw=S_raw,
+                       scorer=ctx.w, grad_wb=gwb, ws=mn.ws)
+        return gwb.to(dtype=ctx.w_dtype, device=ctx.w_device), None
 
 
 class NWAlign(torch.autograd.Function):
-    """Score_b = NW score of pair b for similarity S and gap; backward gives
-    dense dL/dS (path indicator) and dL/dgap (gap count)."""
+    """Score_b = NW score of pair b (Sec. 5.1) for similarity S (flat, the
+    plan's layout) and gap.  Backward: dL/dS = a_b times the traced path's
+    indicator (dense) and dL/dgap = sum_b a_b (n_b + m_b - 2 k_b).  The
+    traceback is saved, so later alignments on the same miner do not change
+    the gradient."""
 
     @staticmethod
     def forward(ctx, S, gap, miner: Miner, threshold: float = 0.5):
-        miner.align(float(gap), threshold, S=S.contiguous())
+        Sc = S.detach().contiguous()
+        if Sc.dtype != torch.float32 or Sc.numel() < miner.plan.S_elems:
+            raise ValueError("S must be float32 with at least S_elems elements")
+        miner.align(float(gap), threshold, S=Sc)
         ctx.miner = miner
+        ctx.S_numel, ctx.S_shape = S.numel(), S.shape
+        _save_gap(ctx, gap)
+        ctx.save_for_backward(miner.tb.clone(), miner.n_diag.clone())
         return miner.score[:miner.batch.B].clone()
 
     @staticmethod
     def backward(ctx, g):
         mn = ctx.miner
         dev = mn.ctx.device
-        gS = torch.empty(max(mn.plan.S_elems, 1), dtype=torch.float32, device=dev)
-        gg = torch.zeros(1, dtype=torch.float64, device=dev)
-        align_backward(mn.plan, mn.batch, mn.tb, mn.n_diag, g.contiguous().float(), grad_S=gS, grad_gap=gg,
-                       ws=mn.ws)
-        return gS, gg.to(torch.float32).reshape(()), None, None
+        tb, n_diag = ctx.saved_tensors
+        need_S = ctx.needs_input_grad[0]
+        need_gap = ctx.needs_input_grad[1] and ctx.gap_tensor
+        if not (need_S or need_gap):
+            return None, None, None, None
+        gS = torch.zeros(max(ctx.S_numel, 1), dtype=torch.float32, device=dev) if need_S else None
+        gg = torch.zeros(1, dtype=torch.float64, device=dev) if need_gap else None
+        align_backward(mn.plan, mn.batch, tb, n_diag, g.contiguous().float(), grad_S=gS, grad_gap=gg, ws=mn.ws)
+        gS = gS[:ctx.S_numel].reshape(ctx.S_shape) if need_S else None
+        return gS, _gap_grad(ctx, gg), None, None
 
 
 class MineScore(torch.autograd.Function):
     """Fused forward (score + align) with the path-sparse backward to the
-    scorer weights and the gap (FP64 batch reduction)."""
+    scorer weights and the gap (FP64 batch reduction), for the tuning of
+    Sec. 5.2.  grad_S_extra (flat, S layout) is an extra dense dL/dS added
+    in the backward."""
 
     @staticmethod
     def forward(ctx, w, gap, miner: Miner, threshold: float = 0.5, grad_S_extra=None):
         miner.mine(w, float(gap), threshold, want_raw=True)
+        P = miner.plan.S_elems
+        ctx.save_for_backward(miner.S[:P].clone(), miner.S_raw[:P].clone(), miner.tb.clone(), miner.n_diag.clone())
         ctx.miner = miner
         ctx.w = w.detach().cpu()
-        ctx.wdev = w.device
-        ctx.gdev = gap.device if torch.is_tensor(gap) else None
-        ctx.extra = grad_S_extra
+        ctx.w_dtype, ctx.w_device = w.dtype, w.device
+        _save_gap(ctx, gap)
+        ctx.extra = None if grad_S_extra is None else grad_S_extra.detach().contiguous().float()
         return miner.score[:miner.batch.B].clone()
 
     @staticmethod
     def backward(ctx, g):
         mn = ctx.miner
         dev = mn.ctx.device
-        gwb = torch.zeros(3, dtype=torch.float64, device=dev)
-        gg = torch.zeros(1, dtype=torch.float64, device=dev)
-        align_backward(mn.plan, mn.batch, mn.tb, mn.n_diag, g.contiguous().float(), grad_S_extra=ctx.extra,
-                       grad_gap=gg, S=mn.S, S_raw=mn.S_raw, scorer=ctx.w, grad_wb=gwb, ws=mn.ws)
-        ggap = gg.to(torch.float32).reshape(())
-        if ctx.gdev is not None:
-            ggap = ggap.to(ctx.gdev)
-        return gwb.to(dtype=torch.float32, device=ctx.wdev), ggap, None, None, None
+        S, S_raw, tb, n_diag = ctx.saved_tensors
+        need_w = ctx.needs_input_grad[0]
+        need_gap = ctx.needs_input_grad[1] and ctx.gap_tensor
+        if not (need_w or need_gap):
+            return None, None, None, None, None
+        gwb = torch.zeros(3, dtype=torch.float64, device=dev) if need_w else None
+        gg = torch.zeros(1, dtype=torch.float64, device=dev) if need_gap else None
+        align_backward(mn.plan, mn.batch, tb, n_diag, g.contiguous().float(),
+                       grad_S_extra=ctx.extra if need_w else None, grad_gap=gg, S=S, S_raw=S_raw, scorer=ctx.w,
+                       grad_wb=gwb, ws=mn.ws)
+        gw = gwb.to(dtype=ctx.w_dtype, device=ctx.w_device) if need_w else None
+        return gw, _gap_grad(ctx, gg), None, None, None

@@ -6,8 +6,8 @@
 //             item is one 64-row strip of one pair's DP lattice; items are
 //             ordered longest pair first, strips top to bottom.  Lane r owns
 //             row r of the strip and at step t computes column j = t - r + 1,
-//             so each step is one anti-diagonal of the strip -- the paper's
-//             "diagonal in parallel threads".  Per cell, in FP32 without
+//             so each step is one anti-diagonal of the strip, computed by
+//             all lanes at once (Sec. 5.1, Fig. 2).  Per cell, in FP32 without
 //             contraction:
 //                up = H[i-1][j] + g, left = H[i][j-1] + g, diag = H[i-1][j-1] + S
 //                first maximum of (up, left, diag) with '>' (UP > LEFT > DIAG)
@@ -18,7 +18,11 @@
 //             shifted window and is published every 16 steps as tagged 64-bit
 //             agent-coherent stores (no counters, no cache flushes), so the
 //             next strip runs concurrently on another wave about 100 steps
-//             behind (bounded re-read).
+//             behind (bounded re-read).  A wave that gives up waiting (its
+//             poll limit) sets the error flag, marks its own last row failed
+//             (tag TAG_FAIL, so the strips below give up at once instead of
+//             waiting out their own limits) and, in a pair's last strip,
+//             writes NaN as the score; the walk then leaves the pair empty.
 //             S is staged through an LDS ring whose slot index equals the step
 //             index (row r of column c lands in slot c + r), so every lane reads
 //             the same slot and one ds_read_b128 serves four steps; the ring
@@ -43,7 +47,8 @@ namespace nwm {
 constexpr int PAIR_PITCH = 68;        // ring floats per row pair: 2 x 32 steps + 4 padding
 constexpr int HALF = 32 * PAIR_PITCH;  // ring floats per group of 32 steps (64 rows)
 constexpr int GROUP = 32;             // steps per S staging group
-constexpr int SPIN_LIMIT = 1 << 22;   // polls before a wave gives up (error flag)
+constexpr int SPIN_LIMIT = 1 << 22;   // default polls before a wave gives up (error flag)
+constexpr uint32_t TAG_FAIL = 2u;     // tag of a boundary value whose producer gave up
 
 static __device__ __forceinline__ float dpp_shr1(float old, float src) {
   // lane l <- src of lane l-1; lane 0 keeps `old`
@@ -207,7 +212,9 @@ static __device__ __forceinline__ void run16(StripState &st, const float *ring, 
 
 struct FillArgs {
   int n_items, B;
-  int item0;   // first work item of this launch (its queue counts from 0)
+  int item0;        // first work item of this launch (its queue counts from 0)
+  int spin_limit;   // polls of a boundary window before the wave gives up
+  int hold;         // testing: the first strip of a pair publishes nothing
   const int32_t *it_pair, *it_strip, *n, *m;
   const int64_t *s_off, *tb_off, *bnd_off;
 };
@@ -300,23 +307,29 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
         __builtin_amdgcn_global_load_lds((const void *)(in_row + tw + 2 * lane),
                                          (__attribute__((address_space(3))) void *)buf, 16, 0, 16 /* sc1 */);
     };
+    // lanes 0..15 feed the next 16 steps; columns beyond m are never used
+    auto window_need = [&](int tw) -> bool { return lane < 16 && tw + 1 + lane <= m; };
     auto window_ready = [&](uint64_t v, int tw) -> bool {
-      // lanes 0..15 feed the next 16 steps; columns beyond m are never used
-      const bool need = lane < 16 && tw + 1 + lane <= m;
-      return __ballot(need && (uint32_t)(v >> 32) != epoch) == 0;
+      return __ballot(window_need(tw) && (uint32_t)(v >> 32) != epoch) == 0;
     };
-    // the producer has not got this far yet: reload (bounded) until it has
-    auto wait_window = [&](int tw) -> uint64_t {
-      uint64_t v = 0ull;
+    // the producer has not got this far yet: reload (bounded) until it has;
+    // a value tagged TAG_FAIL means the producer gave up
+    auto wait_window = [&](int tw, uint64_t v) -> uint64_t {
       int spins = 0;
-      do {
-        if (++spins > SPIN_LIMIT) {
+      for (;;) {
+        const uint32_t tag = (uint32_t)(v >> 32);
+        if (__ballot(window_need(tw) && tag == TAG_FAIL) != 0) {
+          failed = true;
+          break;
+        }
+        if (__ballot(window_need(tw) && tag != epoch) == 0) break;
+        if (++spins > A.spin_limit) {
           failed = true;
           break;
         }
         __builtin_amdgcn_s_sleep(1);
         v = load_window(tw);
-      } while (!window_ready(v, tw));
+      }
       return v;
     };
     // One chunk of 16 steps from its boundary window.  The publish of the
@@ -330,7 +343,7 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
       // lane l of the collector holds H of row 64 at step t0 + 15 - 63 + l,
       // i.e. column t0 - 110 + l; lanes 48.. publish
       const int j = t0 - 110 + lane;
-      const bool pub = !last && lane >= 48 && j >= 1 && j <= m;
+      const bool pub = !last && lane >= 48 && j >= 1 && j <= m && !(A.hold && s == 0);
       uint64_t *dst = pub ? out_row + j : my_sink + (lane & 15);
       __hip_atomic_store(dst, ((uint64_t)epoch << 32) | __float_as_uint(st.col), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
@@ -362,7 +375,7 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
       else if (ahead == 2) asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
       else asm volatile("s_waitcnt vmcnt(1)" ::: "memory");
       uint64_t v = buf[1 + lane];   // slot tw + 1 + lane (lanes 0..15 matter)
-      if (!window_ready(v, tw)) v = wait_window(tw);
+      if (!window_ready(v, tw)) v = wait_window(tw, v);
       return v;
     };
     // the ring half of the group at t0 has landed (chunk A of a group)
@@ -407,7 +420,11 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     if (last) {
       // lane r_last stopped updating after column m: it holds H[n][m]
       const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(st.H), r_last));
-      if (lane == 0 && !failed) score[b] = v;
+      if (lane == 0) score[b] = failed ? __builtin_nanf("") : v;
+    } else if (failed) {
+      // the strip below must not wait for a row that will never come
+      for (int j = 1 + lane; j <= m; j += 64)
+        __hip_atomic_store(out_row + j, (uint64_t)TAG_FAIL << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (failed && lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (hot) __builtin_amdgcn_s_setprio(0);
@@ -451,14 +468,16 @@ static __device__ __forceinline__ uint32_t code_at(uint32_t w0, uint32_t w1, uin
 // it waits for itself at the next block change.  Path cells reach memory in
 // coalesced stores.
 __global__ __launch_bounds__(64) void k_nw_walk(PlanDev P, const char *__restrict__ tb_bits,
-                                                int2 *__restrict__ path, int32_t *__restrict__ n_diag, int o0) {
+                                                const float *__restrict__ score, int2 *__restrict__ path,
+                                                int32_t *__restrict__ n_diag, int o0) {
   __shared__ int2 lbuf[WALK_LDS];
   const int b = P.dp_order[o0 + blockIdx.x];
   const int n = P.n[b], m = P.m[b];
   const int lane = threadIdx.x;
   const int cap = min(n, m);
   int2 *pa = path + P.p_off[b];   // entry q of the walk (descending) at cap - 1 - q
-  if (n <= 0 || m <= 0) {
+  // an empty side, or a fill that gave up (NaN score): no aligned pairs
+  if (n <= 0 || m <= 0 || __builtin_isnan(score[b])) {
     if (lane == 0) n_diag[b] = 0;
     return;
   }
@@ -612,6 +631,8 @@ static FillArgs fill_args(const PlanDev &P) {
   A.n_items = P.n_items;
   A.B = P.B;
   A.item0 = 0;
+  A.spin_limit = SPIN_LIMIT;
+  A.hold = 0;
   A.it_pair = P.it_pair;
   A.it_strip = P.it_strip;
   A.n = P.n;
@@ -637,7 +658,7 @@ hipError_t launch_nw_reset(const PlanDev &P, float g, float *score, uint64_t *bn
 // (cleared by the reset).  Strips of one pair must all be in one launch.
 hipError_t launch_nw_fill_items(const PlanDev &P, const float *S, float g, float *score, char *tb, uint64_t *bnd,
                                 int64_t n_bnd, int32_t *head, int32_t *err, int item0, int n, int waves_per_cu,
-                                hipStream_t st) {
+                                int spin_limit, int hold, hipStream_t st) {
   if (P.B <= 0 || n <= 0) return hipSuccess;
   if (g_fill_cus == 0) {
     hipError_t e = fill_set_attrs(0);
@@ -646,6 +667,8 @@ hipError_t launch_nw_fill_items(const PlanDev &P, const float *S, float g, float
   FillArgs A = fill_args(P);
   A.item0 = item0;
   A.n_items = n;
+  A.spin_limit = spin_limit > 0 ? spin_limit : SPIN_LIMIT;
+  A.hold = hold;
   // every wave of the grid is resident at once (the hand-off between strips
   // waits on other waves), so the grid never exceeds the occupancy
   const int per = (waves_per_cu > 0 && waves_per_cu < g_fill_per) ? waves_per_cu : g_fill_per;
@@ -662,17 +685,18 @@ hipError_t launch_nw_fill_items(const PlanDev &P, const float *S, float g, float
 }
 
 hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *score, char *tb, uint64_t *bnd,
-                          int64_t n_bnd, int32_t *ctl, int waves_per_cu, hipStream_t st) {
+                          int64_t n_bnd, int32_t *ctl, int waves_per_cu, int spin_limit, int hold, hipStream_t st) {
   hipError_t e = launch_nw_reset(P, g, score, bnd, n_bnd, ctl, st);
   if (e != hipSuccess) return e;
-  return launch_nw_fill_items(P, S, g, score, tb, bnd, n_bnd, ctl, ctl + 1, 0, P.n_items, waves_per_cu, st);
+  return launch_nw_fill_items(P, S, g, score, tb, bnd, n_bnd, ctl, ctl + 1, 0, P.n_items, waves_per_cu, spin_limit,
+                              hold, st);
 }
 
 // pairs dp_order[o0 .. o0 + n)
-hipError_t launch_nw_walk(const PlanDev &P, const char *tb, int2 *path, int32_t *n_diag, int o0, int n,
-                          hipStream_t st) {
+hipError_t launch_nw_walk(const PlanDev &P, const char *tb, const float *score, int2 *path, int32_t *n_diag, int o0,
+                          int n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_nw_walk, dim3(n), dim3(64), 0, st, P, tb, path, n_diag, o0);
+  hipLaunchKernelGGL(k_nw_walk, dim3(n), dim3(64), 0, st, P, tb, score, path, n_diag, o0);
   return hipGetLastError();
 }
 

@@ -11,7 +11,9 @@
 // k_bwd_dense   (optional) grad_S := grad_S_extra (or 0) for every cell, and
 //               the dense chain of grad_S_extra, per row tile in FP32.
 // k_bwd_path    one wave per pair: the path-sparse chain in FP32, grad_S += a_b
-//               on the path, per-pair partials (dw0, dw1, db, a_b * G).
+//               on the path, per-pair partials (dw0, dw1, db, a_b * G).  Not
+//               launched without a score gradient (no path term).  Path cells
+//               outside the pair's n x m block are skipped.
 // k_bwd_reduce  one block: FP64 sum of all partials in a fixed order.
 #include "nwm_internal.h"
 #include "libnwmine.h"
@@ -90,6 +92,7 @@ __global__ __launch_bounds__(64) void k_bwd_path(PlanDev P, const int64_t *__res
   float g0 = 0.f, g1 = 0.f, gb = 0.f;
   for (int q = lane; q < k; q += 64) {
     const int2 c = pa[q];
+    if ((unsigned)c.x >= (unsigned)n || (unsigned)c.y >= (unsigned)m) continue;
     const int64_t o = base + (int64_t)c.x * m + c.y;
     if (grad_S) grad_S[o] += a;
     if (want_wb) {
@@ -152,12 +155,16 @@ hipError_t launch_backward(const PlanDev &P, const int64_t *src_off, const int64
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_bwd_path, dim3(P.B), dim3(64), 0, st, P, src_off, tgt_off, path, n_diag, grad_score, S,
-                     S_raw, grad_S, part_path, want_wb);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  // without a score gradient there is no path term (tb and n_diag unused)
+  const int n_path = grad_score ? P.B : 0;
+  if (n_path > 0) {
+    hipLaunchKernelGGL(k_bwd_path, dim3(P.B), dim3(64), 0, st, P, src_off, tgt_off, path, n_diag, grad_score, S,
+                       S_raw, grad_S, part_path, want_wb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   const int nd = (E && want_wb) ? P.n_rt : 0;
-  hipLaunchKernelGGL(k_bwd_reduce, dim3(1), dim3(256), 0, st, P.B, part_path, nd, part_dense, grad_gap, grad_wb);
+  hipLaunchKernelGGL(k_bwd_reduce, dim3(1), dim3(256), 0, st, n_path, part_path, nd, part_dense, grad_gap, grad_wb);
   return hipGetLastError();
 }
 

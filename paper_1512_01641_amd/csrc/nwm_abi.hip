@@ -29,12 +29,12 @@ hipError_t launch_score(const PlanDev &, bool, const int64_t *, const int64_t *,
 size_t score_lds_bytes(int nch, bool bf16);
 hipError_t score_set_attrs(int nch_max);
 hipError_t launch_nw_fill(const PlanDev &, const float *, float, float *, char *, uint64_t *, int64_t, int32_t *,
-                          int, hipStream_t);
+                          int, int, int, hipStream_t);
 hipError_t fill_set_attrs(int);
 hipError_t launch_nw_reset(const PlanDev &, float, float *, uint64_t *, int64_t, int32_t *, hipStream_t);
 hipError_t launch_nw_fill_items(const PlanDev &, const float *, float, float *, char *, uint64_t *, int64_t,
-                                int32_t *, int32_t *, int, int, int, hipStream_t);
-hipError_t launch_nw_walk(const PlanDev &, const char *, int2 *, int32_t *, int, int, hipStream_t);
+                                int32_t *, int32_t *, int, int, int, int, int, hipStream_t);
+hipError_t launch_nw_walk(const PlanDev &, const char *, const float *, int2 *, int32_t *, int, int, hipStream_t);
 hipError_t launch_keep(const PlanDev &, const float *, float, const int2 *, const int32_t *, int2 *, int32_t *, int,
                        int, hipStream_t);
 hipError_t merge_set_attrs(int max_entries);
@@ -90,7 +90,7 @@ struct nwm_plan {
   int64_t n_bnd = 0;   // uint64 entries of the published-row region
   int max_entries = 1; // dictionary entries of the longest source sentence (tokens x max_deg)
   // launch parameters (nwm_param) and what re-deriving the DP priority flags needs
-  int32_t param[5] = {0, 0, 1, 50, 1};
+  int32_t param[NWM_N_PARAMS] = {0, 0, 1, 50, 1, 0, 0};
   uint64_t param_version = 0;
   std::vector<int32_t> it_strip;   // strip index per DP item (no flags)
   std::vector<int64_t> it_chain;   // dependency chain of the item's pair
@@ -667,17 +667,33 @@ nwm_status nwm_align_batch(nwm_plan *p, const float *S, float gap, float thresho
   {
     Mark mk(p, K_FILL, st);
     e = launch_nw_fill(p->dev, S, gap, score, tbc, (uint64_t *)(w + p->ws.bnd), p->n_bnd,
-                       (int32_t *)(w + p->ws.ctl), p->param[NWM_PARAM_FILL_WAVES_PER_CU], st);
+                       (int32_t *)(w + p->ws.ctl), p->param[NWM_PARAM_FILL_WAVES_PER_CU],
+                       p->param[NWM_PARAM_DP_SPIN_LIMIT], p->param[NWM_PARAM_DP_TEST_HOLD], st);
     mk.done();
   }
   if (e != hipSuccess) return NWM_EDEVICE;
   {
     Mark mk(p, K_WALK, st);
-    e = launch_nw_walk(p->dev, tbc, path, n_diag, 0, p->B, st);
+    e = launch_nw_walk(p->dev, tbc, score, path, n_diag, 0, p->B, st);
     if (e == hipSuccess) e = launch_keep(p->dev, S, threshold, path, n_diag, (int2 *)kept, n_kept, 0, p->B, st);
     mk.done();
   }
   return dev_err(e);
+}
+
+nwm_status nwm_align_check(const nwm_plan *p, const void *ws, int32_t *failed, void *stream) {
+  if (failed) *failed = 0;
+  if (!p) return NWM_EINVAL;
+  if (p->B == 0) return NWM_OK;
+  if (!ws) return NWM_EINVAL;
+  int32_t flag = 0;
+  const char *w = static_cast<const char *>(ws);
+  hipStream_t st = (hipStream_t)stream;
+  if (hipMemcpyAsync(&flag, w + p->ws.ctl + 4, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return NWM_EDEVICE;
+  if (failed) *failed = flag != 0;
+  return flag != 0 ? NWM_EDEVICE : NWM_OK;
 }
 
 nwm_status nwm_align_backward(nwm_plan *p, const nwm_batch *batch, const void *tb, const int32_t *n_diag,
@@ -689,8 +705,10 @@ nwm_status nwm_align_backward(nwm_plan *p, const nwm_batch *batch, const void *t
   nwm_status s = check_batch(p, batch);
   if (s != NWM_OK) return s;
   if (p->B == 0) return NWM_OK;
-  if (!n_diag || !grad_score || !ws) return NWM_EINVAL;
-  if (p->sizes.kept_cap > 0 && !tb) return NWM_EINVAL;
+  if (!ws) return NWM_EINVAL;
+  // the path term needs the traceback of nwm_align_batch; without a score
+  // gradient only the dense term runs and tb / n_diag are not read
+  if (grad_score && (!n_diag || (p->sizes.kept_cap > 0 && !tb))) return NWM_EINVAL;
   if (grad_wb && p->sizes.S_elems > 0 && (!S || !S_raw)) return NWM_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const char *tbc = static_cast<const char *>(tb);
@@ -719,6 +737,12 @@ nwm_status nwm_plan_set_param(nwm_plan *p, nwm_param param, int32_t value) {
     case NWM_PARAM_DP_HOT_PERCENT:
       if (value < 0 || value > 100) return NWM_EINVAL;
       break;
+    case NWM_PARAM_DP_SPIN_LIMIT:
+      if (value < 0 || value > (1 << 30)) return NWM_EINVAL;
+      break;
+    case NWM_PARAM_DP_TEST_HOLD:
+      if (value != 0 && value != 1) return NWM_EINVAL;
+      break;
     default:
       return NWM_EINVAL;
   }
@@ -737,7 +761,7 @@ nwm_status nwm_plan_set_param(nwm_plan *p, nwm_param param, int32_t value) {
 }
 
 nwm_status nwm_plan_get_param(const nwm_plan *p, nwm_param param, int32_t *value) {
-  if (!p || !value || (int)param < 0 || (int)param > 4) return NWM_EINVAL;
+  if (!p || !value || (int)param < 0 || (int)param >= NWM_N_PARAMS) return NWM_EINVAL;
   *value = p->param[param];
   return NWM_OK;
 }
@@ -785,6 +809,7 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
   uint64_t *bnd = (uint64_t *)(w + p->ws.bnd);
   int32_t *ctl = (int32_t *)(w + p->ws.ctl);
   const int wpc = p->param[NWM_PARAM_FILL_WAVES_PER_CU];
+  const int spin = p->param[NWM_PARAM_DP_SPIN_LIMIT], hold = p->param[NWM_PARAM_DP_TEST_HOLD];
   const PlanDev &D = p->dev;
   const bool scored = p->sizes.S_elems > 0;
   const int gl = p->n_gt_long, il = p->n_items_long, ol = p->n_pairs_long;
@@ -827,16 +852,18 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
     if (otop > 0) {
       if (e == hipSuccess) e = hipStreamWaitEvent(lane, p->ev_top, 0);
       if (e == hipSuccess)
-        e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl + 2, ctl + 1, 0, itop, wpc, lane);
-      if (e == hipSuccess) e = launch_nw_walk(D, tbc, path, n_diag, 0, otop, lane);
+        e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl + 2, ctl + 1, 0, itop, wpc, spin, hold,
+                                 lane);
+      if (e == hipSuccess) e = launch_nw_walk(D, tbc, score, path, n_diag, 0, otop, lane);
       if (e == hipSuccess) e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, 0, otop, lane);
       if (e == hipSuccess) e = hipEventRecord(p->ev_top_done, lane);
     }
     if (ol > otop) {
       if (e == hipSuccess) e = hipStreamWaitEvent(aux, p->ev_long, 0);
       if (e == hipSuccess)
-        e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl + 3, ctl + 1, itop, il - itop, wpc, aux);
-      if (e == hipSuccess) e = launch_nw_walk(D, tbc, path, n_diag, otop, ol - otop, aux);
+        e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl + 3, ctl + 1, itop, il - itop, wpc, spin,
+                                 hold, aux);
+      if (e == hipSuccess) e = launch_nw_walk(D, tbc, score, path, n_diag, otop, ol - otop, aux);
       if (e == hipSuccess)
         e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, otop, ol - otop, aux);
       if (e == hipSuccess) e = hipEventRecord(p->ev_long_done, aux);
@@ -846,8 +873,9 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
   if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_b_rest, 0);
   if (e == hipSuccess && scored) e = score_tiles(p, batch, sc, S, S_raw, ws, gl, D.n_gt - gl, st);
   if (e == hipSuccess)
-    e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl, ctl + 1, il, D.n_items - il, wpc, st);
-  if (e == hipSuccess) e = launch_nw_walk(D, tbc, path, n_diag, ol, p->B - ol, st);
+    e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl, ctl + 1, il, D.n_items - il, wpc, spin, hold,
+                             st);
+  if (e == hipSuccess) e = launch_nw_walk(D, tbc, score, path, n_diag, ol, p->B - ol, st);
   if (e == hipSuccess) e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, ol, p->B - ol, st);
   if (e == hipSuccess && ol > 0 && otop > 0) e = hipStreamWaitEvent(st, p->ev_top_done, 0);
   if (e == hipSuccess && ol > otop) e = hipStreamWaitEvent(st, p->ev_long_done, 0);

@@ -61,3 +61,33 @@ def test_create_without_gpu_reports_device_error():
 def test_product_path_refuses_to_run_without_library(tmp_path):
     with pytest.raises(RuntimeError, match="not built"):
         _abi.load(str(tmp_path / "missing.so"))
+
+
+def test_null_arguments_rejected_new_calls():
+    lib = _abi.load()
+    failed = ctypes.c_int32(7)
+    assert lib.nwm_align_check(None, None, ctypes.byref(failed), None) == _abi.NWM_EINVAL
+    assert failed.value == 0
+    assert lib.nwm_plan_set_param(None, 5, 1) == _abi.NWM_EINVAL
+
+
+def test_build_guard_rejects_scratch_in_hand_counted_kernels():
+    """The build fails when a kernel whose memory waits are counted by hand
+    spills to scratch (parsed from the compiler's resource-usage remarks)."""
+    from paper_1512_01641_amd import build as B
+
+    def remarks(scratch):
+        lines = []
+        for k in ("_ZN3nwm9k_nw_fillILb1EEEv", "_ZN3nwm9k_nw_walkENS_7PlanDevE"):
+            lines.append("k_align.hip:1:1: remark: Function Name: %s [-Rpass-analysis=kernel-resource-usage]" % k)
+            lines.append("k_align.hip:1:1: remark:     VGPRs: 64 [-Rpass-analysis=kernel-resource-usage]")
+            lines.append("k_align.hip:1:1: remark:     ScratchSize [bytes/lane]: %d "
+                         "[-Rpass-analysis=kernel-resource-usage]" % (scratch if "fill" in k else 0))
+        return "\n".join(lines)
+    assert B.resource_usage(remarks(0))["_ZN3nwm9k_nw_fillILb1EEEv"]["VGPRs"] == 64
+    B.check_scratch("k_align.hip", remarks(0))
+    with pytest.raises(RuntimeError, match="scratch"):
+        B.check_scratch("k_align.hip", remarks(16))
+    with pytest.raises(RuntimeError, match="no resource-usage"):
+        B.check_scratch("k_align.hip", "")
+    B.check_scratch("k_score.hip", "")   # not guarded

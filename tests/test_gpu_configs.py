@@ -107,6 +107,23 @@ def test_config2_f1_parity_oriented():
         assert abs(f - f64) <= 0.5, (prec, f, f64)
 
 
+def _f1_parity(run, batch, pairs, scorer):
+    """Planted-alignment F1 of the GPU's kept pairs on `pairs` against the
+    FP64 oracle's (oracle S64 -> FP32 DP -> keep) on the same pairs."""
+    sub = batch.subset(pairs)
+    ora = oracle.score(sub, scorer=scorer)
+    al = oracle.align(sub.n, sub.m, ora["S32"], batch.gap, batch.threshold)
+    gold = [sub.gold[sub.gold_off[q]:sub.gold_off[q + 1]] for q in range(sub.B)]
+    f64 = oracle.f1([oracle.pair_kept(al, q) for q in range(sub.B)], gold)
+    f = oracle.f1([run.kept(b) for b in pairs], gold)
+    worst = 0.0
+    for q, b in enumerate(pairs):
+        S = run.S(b)
+        if S.size:
+            worst = max(worst, float(np.abs(S.astype(np.float64) - ora["S64"][ora["s_off"][q]:ora["s_off"][q + 1]]).max()))
+    return f, f64, worst
+
+
 def test_config3_full_bf16():
     _log("cfg3: generating 256 pairs of 5000x5000")
     b = corpus.make_batch(3)
@@ -116,6 +133,17 @@ def test_config3_full_bf16():
     _log("cfg3: oracle on pairs %s" % pairs)
     worst = _check_pairs(run, b, pairs, BF16)
     _log("cfg3: max |S - S64| on sampled pairs %.3g" % worst)
+    del run
+    # planted-alignment F1 with the oriented scorer, BF16 vs the FP64 oracle
+    w = H.load_oriented(3)
+    _log("cfg3: GPU BF16, oriented scorer")
+    run = H.GpuRun(b, prec=BF16, scorer=w)
+    pairs = [7, 200]
+    f, f64, worst = _f1_parity(run, b, pairs, w)
+    _log("cfg3: planted F1 BF16 %.3f vs FP64 %.3f on pairs %s; max |S - S64| %.3g" % (f, f64, pairs, worst))
+    assert f64 > 50.0
+    assert abs(f - f64) <= 0.5
+    assert worst <= 2e-2
 
 
 def test_config4_full_forward_backward():
@@ -160,3 +188,51 @@ def test_config5_full_bf16():
                       (b.n[e] + b.m[e]).astype(np.float32) * np.float32(b.gap)).astype(np.float32)
     np.testing.assert_array_equal(run.score[e].view(np.uint32), expect.view(np.uint32))
     assert np.all(run.n_kept[e] == 0)
+    del run
+    # planted-alignment F1 with the oriented scorer, BF16 vs the FP64 oracle
+    w = H.load_oriented(5)
+    _log("cfg5: GPU BF16, oriented scorer")
+    run = H.GpuRun(b, prec=BF16, scorer=w)
+    pairs = H.sample_pairs(b, 256, seed=55)
+    f, f64, worst = _f1_parity(run, b, pairs, w)
+    _log("cfg5: planted F1 BF16 %.3f vs FP64 %.3f on %d sampled pairs; max |S - S64| %.3g"
+         % (f, f64, len(pairs), worst))
+    assert f64 > 50.0
+    assert abs(f - f64) <= 0.5
+    assert worst <= 2e-2
+    del run
+    # the backward on a seeded 5 % tuning subsample (forward in BF16)
+    _config5_backward_subsample(b, w)
+
+
+def _config5_backward_subsample(b, w):
+    import torch
+    import paper_1512_01641_amd as nw
+    rng = np.random.default_rng(1512)
+    idx = np.sort(rng.choice(b.B, size=b.B // 20, replace=False))
+    sub = b.subset(idx)
+    _log("cfg5: backward on a 5%% subsample (%d pairs, %d cells)" % (sub.B, sub.cells()))
+    run = H.GpuRun(sub, prec=BF16, scorer=w)
+    mn = run.mn
+    dev = mn.ctx.device
+    a = (0.5 + (np.arange(sub.B) % 8) / 8.0).astype(np.float32)
+    gS = torch.empty(max(mn.plan.S_elems, 1), dtype=torch.float32, device=dev)
+    gg = torch.zeros(1, dtype=torch.float64, device=dev)
+    gwb = torch.zeros(3, dtype=torch.float64, device=dev)
+    nw.align_backward(mn.plan, mn.batch, mn.tb, mn.n_diag, torch.as_tensor(a).to(dev), grad_S=gS, grad_gap=gg,
+                      S=mn.S, S_raw=mn.S_raw, scorer=w, grad_wb=gwb, ws=mn.ws)
+    torch.cuda.synchronize()
+    Sg = run.S_all()
+    al = oracle.align(sub.n, sub.m, Sg, sub.gap, sub.threshold)   # the DP on the GPU's S
+    np.testing.assert_array_equal(run.score.view(np.uint32), al["score"].view(np.uint32))
+    sc = oracle.score(sub, scorer=w)
+    Sr = mn.S_raw[:mn.plan.S_elems].cpu().numpy().astype(np.float64)
+    bw = oracle.backward(sub.n, sub.m, al, a.astype(np.float64), Sg.astype(np.float64), Sr, sc["rho"])
+    np.testing.assert_array_equal(gS[:mn.plan.S_elems].cpu().numpy(), bw["grad_S"].astype(np.float32))
+    assert gg.item() == pytest.approx(bw["grad_gap"], rel=1e-12)
+    np.testing.assert_allclose(gwb.cpu().numpy(), bw["grad_wb"], rtol=1e-4, atol=1e-6)
+    # against the oracle's FP64 scores: the BF16 similarity's own error
+    bw64 = oracle.backward(sub.n, sub.m, al, a.astype(np.float64), sc["S64"], sc["S_raw"], sc["rho"],
+                           want_grad_S=False)
+    np.testing.assert_allclose(gwb.cpu().numpy(), bw64["grad_wb"], rtol=1e-2)
+    _log("cfg5: backward grad_wb %s, oracle FP64 %s" % (gwb.cpu().numpy(), bw64["grad_wb"]))

@@ -137,13 +137,29 @@ def test_scores_oriented_scorer_fp32_bf16():
     _check_scores(b, 1, tol_abs=2e-2, scorer=w)
 
 
-def test_scores_ragged_batch_fp32():
-    # several tiles and ragged tails on both sides, empty pairs mixed in
-    b = corpus.make_batch(2, pairs=40)
-    b2 = b.subset(list(range(40)))
-    b2.n[3] = 0
-    gpu_ok = b.subset(list(range(40)))
-    _check_scores(gpu_ok, 0, tol_rel=1e-5)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_scores_ragged_batch_with_empty_pairs(prec):
+    # several tiles and ragged tails on both sides, with pairs that have an
+    # empty source side, an empty target side, or both, mixed in
+    n, m = corpus.make_sizes(2, 40)
+    n, m = n.copy(), m.copy()
+    n[3], m[7], n[11], m[11], n[39] = 0, 0, 0, 0, 0
+    m[20] = 1
+    n[21] = 1
+    b = corpus.make_batch(2, pairs=40, sizes=(n, m))
+    assert b.cells() > 0 and np.count_nonzero(b.n.astype(np.int64) * b.m == 0) == 4
+    if prec == 0:
+        gpu, ora = _check_scores(b, 0, tol_rel=1e-5)
+    else:
+        gpu, ora = _check_scores(b, 1, tol_abs=2e-2)
+    # the DP on the GPU's S, bit-exact; empty sides score fl32((n + m) g)
+    al = oracle.align(b.n, b.m, gpu["S"], b.gap, b.threshold)
+    np.testing.assert_array_equal(gpu["score"].view(np.uint32), al["score"].view(np.uint32))
+    np.testing.assert_array_equal(gpu["n_diag"], al["n_diag"])
+    np.testing.assert_array_equal(gpu["n_kept"], al["n_kept"])
+    for q in (3, 7, 11, 39):
+        assert gpu["n_kept"][q] == 0 and gpu["n_diag"][q] == 0
+        assert gpu["score"][q] == np.float32(b.n[q] + b.m[q]) * np.float32(b.gap)
 
 
 def _wide_vocabulary_batch():
