@@ -4,11 +4,15 @@ One step = one pass of the whole hot path over the batch: similarity of every
 sentence pair (dictionary expansion, contraction + logistic scorer), NW fill,
 traceback and threshold filter.  Inputs are resident in HBM before timing.
 
-Workload (default): 4096 seeded synthetic document pairs, sentence counts
-lognormal (median 60, clipped 20..2000, +-30 % target skew), V = 4096,
-contraction operands BF16 with FP32 accumulation, DP in FP32.  Also measured
-on the same pairs: the batched path with FP32 operands and the plain path
-(the same library called once per pair, FP32, no batching).
+Workload of the JSON line's `value` (default): 4096 seeded synthetic document
+pairs, sentence counts lognormal (median 60, clipped 20..2000, +-30 % target
+skew), V = 4096, contraction operands BF16 with FP32 accumulation, DP in FP32.
+Also measured on the same pairs: the batched path with FP32 operands and the
+plain path (the same library called once per pair, FP32, no batching).  Two
+more workloads are measured beside it (under `workloads`): 256 pairs of
+5000 x 5000 sentences (V = 16384) and 100k pairs with lognormal counts
+(median 60, up to 4000, 8 % empty-or-tiny sides, V = 16384, Zipf 1.05), both
+BF16, the latter with the plain per-pair FP32 path on a seeded subsample.
 
 Prints ONE JSON line.  Only one GPU is used; --gpus N > 1 exits with a
 message.
@@ -28,15 +32,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
 WORKLOADS = {
     2: "%d document pairs, sentence counts lognormal median 60 clipped 20-2000 (+-30%% skew), V=%d hashed vocab, "
-       "Zipf(1.1) tokens, BF16 contraction operands, FP32 DP, gap -0.2, threshold 0.5",
-    3: "%d document pairs of 5000x5000 sentences, V=%d hashed vocab, Zipf(1.1) tokens, BF16 contraction "
+       "Zipf(1.1) tokens, %s contraction operands, FP32 DP, gap -0.2, threshold 0.5",
+    3: "%d document pairs of 5000x5000 sentences, V=%d hashed vocab, Zipf(1.1) tokens, %s contraction "
        "operands, FP32 DP, gap -0.2, threshold 0.5",
     5: "%d document pairs, sentence counts lognormal median 60 clipped 1-4000, 8%% empty-or-tiny sides, V=%d "
-       "hashed vocab, Zipf(1.05) tokens, BF16 contraction operands, FP32 DP, gap -0.2, threshold 0.5",
+       "hashed vocab, Zipf(1.05) tokens, %s contraction operands, FP32 DP, gap -0.2, threshold 0.5",
 }
-MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
+EXTRA = {3: "256x5000x5000_V16384", 5: "100k_lognormal_V16384"}
+TUNED = os.path.join(ROOT, "paper_1512_01641_amd", "tuned_params.json")
 
 
 def _log(msg):
@@ -71,6 +77,8 @@ def profiled_traffic(kernel):
     return rec["bytes_per_launch"]
 
 
+# ---- algorithmic work per launch -------------------------------------------------
+
 def compacted_chunks(batch):
     """Sum over contraction tiles (64 source x 64 target sentences of a pair)
     of the compacted K chunks the tile multiplies: ceil(K / 32), K = distinct
@@ -90,26 +98,225 @@ def compacted_chunks(batch):
     return total
 
 
-def cpu_baseline(batch, seconds_hint=30.0):
-    """The CPU oracle (FP64 scores, FP32 DP) on the host cores, timed on a
-    bounded sample of the same workload."""
-    import oracle
-    cores = min(os.cpu_count() or 1, 16)
-    # sample: leading pairs whose cells fit the hint at a conservative
-    # 100 M cells/s aggregate oracle rate
-    budget = seconds_hint * 1.0e8
-    cells = np.cumsum(batch.n.astype(np.int64) * batch.m)
-    k = int(np.searchsorted(cells, budget)) + 1
-    k = max(1, min(k, batch.B))
-    sub = batch.subset(range(k)) if k < batch.B else batch
-    t0 = time.perf_counter()
-    sc = oracle.score(sub, nthreads=cores)
-    oracle.align(sub.n, sub.m, sc["S32"], sub.gap, sub.threshold, nthreads=cores)
-    dt = time.perf_counter() - t0
-    return {"value": round(sub.B / dt, 3), "unit": "doc-pairs/s", "cores": cores, "kind": "oracle",
-            "sample": "first %d of %d pairs (%d cells), score FP64 + NW FP32 + keep, %.1f s" % (
-                sub.B, batch.B, sub.cells(), dt)}
+def work_model(batch):
+    """Algorithmic work of one launch of each kernel class over the batch,
+    with its roofline bound and the definition used."""
+    B, V = batch.B, batch.V
+    n = batch.n.astype(np.int64)
+    m = batch.m.astype(np.int64)
+    cells = int(np.dot(n, m))
+    n_src, n_tgt = int(n.sum()), int(m.sum())
+    T_src, T_tgt = int(batch.src_tok.size), int(batch.tgt_tok.size)
+    deg = np.diff(batch.d_row_off.astype(np.int64))
+    E = int(deg[batch.src_tok].sum()) if T_src else 0
+    nch = (V + 31) // 32
+    ok = (n > 0) & (m > 0)
+    n_rt = int(((n + 63) // 64)[ok].sum())
+    n_ct = int(((m + 63) // 64)[ok].sum())
+    n_kc = compacted_chunks(batch)
+    path = int(np.minimum(n, m).sum())
+    return {
+        "merge": ("hbm", 4 * T_src + 8 * T_src + 8 * E + 16 * n_src + 8 * E + 4 * n_src,
+                  "read: 4 B token + 8 B dictionary row offsets per source token, 8 B per dictionary entry, 16 B "
+                  "per sentence; write: 8 B per merged entry (at most one per dictionary entry) + 4 B count per "
+                  "sentence"),
+        "build_a": ("hbm", 8 * E + 4 * n_src + 8 * E + 4 * n_rt * (nch + 1),
+                    "read: 8 B per merged entry + 4 B count per sentence; write: 8 B per list entry (at most one "
+                    "per merged entry) + 4 B chunk offsets per row tile and 32-word chunk"),
+        "build_b": ("hbm", 4 * T_tgt + 8 * n_tgt + 4 * T_tgt + n_ct * (4 * (nch + 1) + 16 * nch) + 4 * B * nch,
+                    "read: 4 B token + 8 B offset per target token / sentence; write: 4 B list entry per token, "
+                    "per column tile its chunk offsets, word masks and chunk ranges (20 B per 32-word chunk), per "
+                    "pair a V-bit vocabulary"),
+        "score": ("mfma", 2.0 * 64 * 64 * 32 * n_kc,
+                  "2*64*64*32 flop per compacted K chunk of a 64x64 tile, %d chunks; the whole-vocabulary "
+                  "definition would be 2*V*cells = %.4g flop" % (n_kc, 2.0 * V * cells)),
+        "nw_fill": ("hbm", 4.25 * cells, "4.25 B/cell (4 B S read + 2-bit traceback)"),
+        "walk": ("hbm", 16.0 * int((n + m)[ok].sum()) + 8 * path,
+                 "16 B of direction codes per traceback step (n+m steps per pair) + 8 B per aligned pair"),
+        "keep": ("hbm", 20.0 * path, "8 B aligned pair + 4 B S read + 8 B kept pair per aligned pair"),
+    }, cells, n_kc
 
+
+def rooflines(model, kernel_ms, prec_name):
+    """Roofline object per timed kernel class (achieved = algorithmic work
+    per launch / average launch duration)."""
+    out = {}
+    for k, (bound, work, definition) in model.items():
+        ms = kernel_ms.get(k)
+        if not ms or ms <= 0:
+            continue
+        if bound == "mfma":
+            ach = work / (ms / 1000.0) / 1e12
+            peak, unit = MFMA_PEAK_TFLOPS[prec_name], "TFLOP/s"
+        else:
+            ach = work / (ms / 1000.0) / 1e9
+            peak, unit = HBM_PEAK_GBS, "GB/s"
+        out[k] = {"bound": bound, "achieved": round(ach, 2), "peak": peak, "unit": unit,
+                  "frac": round(ach / peak, 4), "kernel_ms": round(ms, 4), "algorithmic": definition}
+    return out
+
+
+KERNEL_NAMES = {"merge": "k_merge_src", "build_a": "k_build_a", "build_b": "k_build_b",
+                "score": "k_score_c<%s>", "nw_fill": "k_nw_fill", "walk": "k_nw_walk", "keep": "k_keep"}
+
+
+# ---- GPU measurements --------------------------------------------------------------
+
+def batched(nw, torch, ctx, batch, prec_name, prec, args, db=None, dd=None):
+    """Graph-replayed and eager (per-kernel events) times of the batched path."""
+    db = nw.DeviceBatch.from_host(batch) if db is None else db
+    dd = nw.DeviceDict.from_host(batch) if dd is None else dd
+    mn = nw.Miner(ctx, db, dd, prec)
+    w, gap, thr = batch.scorer, batch.gap, batch.threshold
+    params = "defaults"
+    if not args.no_autotune:
+        from paper_1512_01641_amd import autotune
+        r = autotune.autotune(mn, w, gap, thr, reps=5, cache_path=TUNED)
+        params = dict(r["params"], source="cache" if r["cached"] else "tuned in this run")
+        _log("launch parameters %s: %s" % (prec_name, params))
+    step = lambda: mn.mine(w, gap, thr)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # eager launches, every kernel bracketed by HIP events on its stream
+    mn.plan.set_timing(True)
+    eager_ms = _time_steps(step, args.steps, 0, torch)
+    km = mn.plan.kernel_ms(reset=True)
+    mn.plan.set_timing(False)
+    kernel = {k: v[0] / max(v[1], 1) for k, v in km.items() if v[1]}
+    launches = {k: v[1] / args.steps for k, v in km.items() if v[1]}
+    ms = eager_ms
+    if not args.no_graph:
+        gstep = lambda: mn.mine(w, gap, thr, graph=True)
+        ms = _time_steps(gstep, args.steps, max(args.warmup, 1), torch)
+    _log("%s: eager %.4f ms/step, %s %.4f ms/step" % (prec_name, eager_ms, "eager" if args.no_graph else "graph",
+                                                      ms))
+    return dict(ms=ms, eager_ms=eager_ms, kernel=kernel, launches=launches, params=params, miner=mn)
+
+
+def plain(nw, torch, ctx, batch, idx, dd):
+    """The same library called once per document pair (B = 1 plans, FP32,
+    eager), over pairs `idx`; returns ms for the whole pass."""
+    miners = []
+    for k, b in enumerate(idx):
+        sub = batch.subset([b])
+        miners.append(nw.Miner(ctx, nw.DeviceBatch.from_host(sub), dd, nw.NWM_FP32))
+        if (k + 1) % 1024 == 0:
+            _log("plain setup %d/%d" % (k + 1, len(idx)))
+    w, gap, thr = batch.scorer, batch.gap, batch.threshold
+
+    def one_pass():
+        for mnb in miners:
+            mnb.mine(w, gap, thr)
+    ms = _time_steps(one_pass, 1, 1, torch)
+    del miners
+    return ms
+
+
+def summarize(batch, res, prec_name):
+    model, cells, n_kc = work_model(batch)
+    rl = rooflines(model, res["kernel"], prec_name)
+    for k, r in rl.items():
+        name = KERNEL_NAMES[k] % prec_name if "%" in KERNEL_NAMES[k] else KERNEL_NAMES[k]
+        r["kernel"] = name
+        r["traffic"] = profiled_traffic(name)
+    dom = max(rl, key=lambda k: rl[k]["kernel_ms"])
+    fill = res["kernel"].get("nw_fill")
+    return dict(pairs_per_s=round(batch.B / (res["ms"] / 1000.0), 2), ms_per_step=round(res["ms"], 4),
+                ms_per_step_eager=round(res["eager_ms"], 4),
+                gcups=round(cells / (fill / 1000.0) / 1e9, 3) if fill else None,
+                kernel_ms_per_step={k: round(v, 4) for k, v in res["kernel"].items()},
+                launches_per_step=res["launches"], launch_params=res["params"],
+                rooflines=rl, dominant=dom)
+
+
+# ---- CPU baseline (the oracle) -----------------------------------------------------
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_pass(oracle, sub, nthreads):
+    t0 = time.perf_counter()
+    sc = oracle.score(sub, nthreads=nthreads)
+    t1 = time.perf_counter()
+    oracle.align(sub.n, sub.m, sc["S32"], sub.gap, sub.threshold, nthreads=nthreads)
+    t2 = time.perf_counter()
+    return sc, t1 - t0, t2 - t1
+
+
+def cpu_baseline(nw, torch, ctx, batch, head_miner, head_prec, dd):
+    """The CPU oracle (FP64 scores, FP32 DP + keep) timed on the host cores,
+    on all of them and on one thread, with the S and DP phases separately;
+    then the parity figures of the GPU path against it on the same workload."""
+    import oracle
+    from synth import corpus
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = max(1, min(avail, oracle.max_threads(), int(os.environ.get("OMP_NUM_THREADS", avail))))
+    # all cores: leading pairs worth about 10 s at a conservative 1e8 cells/s (the
+    # whole benchmark workload takes about a second)
+    cum = np.cumsum(batch.n.astype(np.int64) * batch.m)
+    k = max(1, min(batch.B, int(np.searchsorted(cum, 10.0 * 1e8)) + 1))
+    sub = batch.subset(range(k)) if k < batch.B else batch
+    sc, ts, td = _oracle_pass(oracle, sub, cores)
+    dt = ts + td
+    # one thread: leading pairs sized to about 8 s at the rate just measured
+    rate1 = sub.cells() / dt / cores
+    k1 = max(1, min(batch.B, int(np.searchsorted(cum, 8.0 * rate1)) + 1))
+    sub1 = batch.subset(range(k1))
+    _, ts1, td1 = _oracle_pass(oracle, sub1, 1)
+    out = {"value": round(sub.B / dt, 3), "unit": "doc-pairs/s", "cores": cores, "kind": "oracle",
+           "sample": "first %d of %d pairs (%d cells): score FP64 + NW FP32 + keep, %.2f s on %d threads" % (
+               sub.B, batch.B, sub.cells(), dt, cores),
+           "cpu_model": cpu_model(),
+           "phase_s": {"score": round(ts, 3), "nw_and_keep": round(td, 3)},
+           "single_thread": {"value": round(sub1.B / (ts1 + td1), 3), "unit": "doc-pairs/s", "cores": 1,
+                             "sample": "first %d pairs (%d cells)" % (sub1.B, sub1.cells()),
+                             "phase_s": {"score": round(ts1, 3), "nw_and_keep": round(td1, 3)}}}
+    # parity of the GPU's batched run (head precision) on the same pairs
+    s_off = oracle.s_offsets(batch.n, batch.m)
+    S_gpu = head_miner.S[:int(s_off[sub.B])].cpu().numpy()
+    dS = np.abs(S_gpu.astype(np.float64) - sc["S64"])
+    al = oracle.align(sub.n, sub.m, S_gpu, batch.gap, batch.threshold, nthreads=cores)
+    score = head_miner.score[:sub.B].cpu().numpy()
+    n_kept = head_miner.n_kept[:sub.B].cpu().numpy()
+    kept = head_miner.kept.cpu().numpy()
+    exact = (score.view(np.uint32) == al["score"].view(np.uint32)) & (n_kept == al["n_kept"]) & (
+        head_miner.n_diag[:sub.B].cpu().numpy() == al["n_diag"])
+    p_off = al["path_off"]
+    for b in np.nonzero(exact)[0]:
+        o, kk = int(p_off[b]), int(n_kept[b])
+        exact[b] = np.array_equal(kept[o:o + kk], al["kept"][o:o + kk])
+    # planted-alignment F1 with the oriented scorer (FP64 oracle vs the GPU)
+    with open(os.path.join(ROOT, "tests", "golden", "oriented_scorer.json")) as f:
+        wo = np.asarray(json.load(f)[str(batch.cfg)]["w"], np.float32)
+    fs = batch.subset(range(min(batch.B, 512)))
+    so = oracle.score(fs, scorer=wo, nthreads=cores)
+    ao = oracle.align(fs.n, fs.m, so["S32"], fs.gap, fs.threshold, nthreads=cores)
+    gold = [fs.gold[fs.gold_off[q]:fs.gold_off[q + 1]] for q in range(fs.B)]
+    f64 = oracle.f1([oracle.pair_kept(ao, q) for q in range(fs.B)], gold)
+    fm = nw.Miner(ctx, nw.DeviceBatch.from_host(fs), dd, head_prec)
+    fm.mine(wo, fs.gap, fs.threshold)
+    torch.cuda.synchronize()
+    fg = oracle.f1([fm.kept_pairs(q) for q in range(fs.B)], gold)
+    out["parity"] = {
+        "pairs": sub.B,
+        "max_abs_dS_vs_fp64": float(dS.max()) if dS.size else 0.0,
+        "dp_bitexact_rate": round(float(exact.mean()) if exact.size else 1.0, 6),
+        "dp_definition": "oracle NW + keep on the GPU's S vs the GPU's score bits, path length and kept pairs",
+        "f1_planted_fp64": round(f64, 3), "f1_planted_gpu": round(fg, 3), "f1_delta_points": round(fg - f64, 3),
+        "f1_definition": "oriented scorer, first %d pairs, kept pairs vs the planted alignment" % fs.B}
+    return out
+
+
+# ---- main -------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser()
@@ -120,6 +327,10 @@ def main():
     ap.add_argument("--workload", type=int, choices=(2, 3, 5), default=2,
                     help="2: 4096 pairs, lognormal median 60, V=4096 (the benchmark line); 3: 256 pairs of "
                          "5000x5000, V=16384; 5: 100k pairs, lognormal median 60, V=16384")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 256x5000x5000 and 100k-pair workloads")
+    ap.add_argument("--extra-steps", type=int, default=3)
+    ap.add_argument("--plain-sample", type=int, default=1000,
+                    help="pairs of the 100k-pair workload timed on the plain per-pair path (seeded sample)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-bidir", action="store_true", help="skip the bi-directional mining measurement")
     ap.add_argument("--no-search", action="store_true", help="skip the random-search tuning measurement")
@@ -142,11 +353,10 @@ def main():
     from synth import corpus
 
     cfg = args.workload
-    _log("generating workload")
+    _log("generating workload %d" % cfg)
     batch = corpus.make_batch(cfg, pairs=args.pairs)
-    B = batch.B
+    B, V = batch.B, batch.V
     cells = batch.cells()
-    V = batch.V
     ctx = nw.Context(0)
     db = nw.DeviceBatch.from_host(batch)
     dd = nw.DeviceDict.from_host(batch)
@@ -166,46 +376,22 @@ def main():
         del src, dst
 
     precs = [p for p in (("bf16", nw.NWM_BF16), ("f32", nw.NWM_FP32)) if args.prec in ("both", p[0])]
-    results = {}
-    eager = {}
-    kernel = {}
-    tuned = {}
+    head, head_prec = precs[0]
+    runs = {}
     for prec_name, prec in precs:
         _log("batched %s" % prec_name)
-        mn = nw.Miner(ctx, db, dd, prec)
-        if not args.no_autotune:
-            from paper_1512_01641_amd import autotune
-            tuned[prec_name] = autotune.autotune(mn, w, gap, thr, reps=5)["params"]
-            _log("autotuned %s: %s" % (prec_name, tuned[prec_name]))
-        step = lambda mn=mn: mn.mine(w, gap, thr)
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        # timed region 1: eager launches, every kernel bracketed by HIP events
-        # on the stream it runs on
-        mn.plan.set_timing(True)
-        ms = _time_steps(step, args.steps, 0, torch)
-        km = mn.plan.kernel_ms(reset=True)
-        mn.plan.set_timing(False)
-        eager[prec_name] = ms
-        kernel[prec_name] = {k: (v[0] / max(v[1], 1)) for k, v in km.items() if v[1]}
-        kernel[prec_name + "_launches_per_step"] = {k: v[1] / args.steps for k, v in km.items() if v[1]}
-        results[prec_name] = ms
-        if not args.no_graph:
-            # timed region 2: the whole path as one captured HIP graph per step
-            gstep = lambda mn=mn: mn.mine(w, gap, thr, graph=True)
-            results[prec_name] = _time_steps(gstep, args.steps, max(args.warmup, 1), torch)
-        _log("%s: eager %.4f ms/step, %s %.4f ms/step" % (prec_name, ms, "eager" if args.no_graph else "graph",
-                                                          results[prec_name]))
-        del mn
+        runs[prec_name] = batched(nw, torch, ctx, batch, prec_name, prec, args, db, dd)
+        if prec_name != head:
+            runs[prec_name].pop("miner")
+    head_sum = summarize(batch, runs[head], head)
 
     bidir = None
     if not args.no_bidir:
         # bi-directional mining (Sec. 5.4, Table 3 "BI"): forward + reverse
         # direction (target side as the source, reverse dictionary) + union
-        _log("bi-directional %s" % precs[0][0])
+        _log("bi-directional %s" % head)
         rbatch = corpus.reverse_batch(batch)
-        bm = nw.BiMiner(ctx, db, dd, nw.DeviceDict.from_host(rbatch), precs[0][1])
+        bm = nw.BiMiner(ctx, db, dd, nw.DeviceDict.from_host(rbatch), head_prec)
         gb = not args.no_graph
         bstep = lambda: bm.mine(w, rbatch.scorer, gap, thr, graph=gb)
         bi_ms = _time_steps(bstep, args.steps, max(args.warmup, 1), torch)
@@ -215,11 +401,10 @@ def main():
             bm.union()
         ev1.record()
         torch.cuda.synchronize()
-        n_bi = int(bm.n_kept[:B].sum().item())
-        n_mono = int(bm.fwd.n_kept[:B].sum().item())
         bidir = {"pairs_per_s": round(B / (bi_ms / 1000.0), 2), "ms_per_step": round(bi_ms, 4),
                  "union_ms": round(ev0.elapsed_time(ev1) / args.steps, 4),
-                 "kept_pairs_forward": n_mono, "kept_pairs_bidirectional": n_bi,
+                 "kept_pairs_forward": int(bm.fwd.n_kept[:B].sum().item()),
+                 "kept_pairs_bidirectional": int(bm.n_kept[:B].sum().item()),
                  "launch": "two graph replays + union kernel" if gb else "eager"}
         del bm
 
@@ -230,7 +415,7 @@ def main():
         # planted alignments stand in)
         from paper_1512_01641_amd import tune
         tb_ = batch.subset(range(min(100, B)))
-        smn = nw.Miner(ctx, nw.DeviceBatch.from_host(tb_), dd, precs[0][1])
+        smn = nw.Miner(ctx, nw.DeviceBatch.from_host(tb_), dd, head_prec)
         tune.random_search(smn, w, tb_.gold_off, tb_.gold, trials=2, seed=1)   # warm-up
         torch.cuda.synchronize()
         trials = 64
@@ -243,92 +428,84 @@ def main():
                   "note": "per trial: NW fill + traceback + keep on the GPU, similarity on the host"}
         del smn
 
-    plain = None
+    plain_ms = None
     if not args.no_plain:
-        _log("plain per-pair FP32")
-        # the same library called once per document pair, FP32, no batching
-        so = np.concatenate([[0], np.cumsum(batch.n, dtype=np.int64)])
-        to = np.concatenate([[0], np.cumsum(batch.m, dtype=np.int64)])
-        miners = []
-        for b in range(B):
-            sub = batch.subset([b])
-            miners.append(nw.Miner(ctx, nw.DeviceBatch.from_host(sub), dd, nw.NWM_FP32))
-            if (b + 1) % 512 == 0:
-                _log("plain setup %d/%d" % (b + 1, B))
-        del so, to
+        _log("plain per-pair FP32 (%d pairs)" % B)
+        plain_ms = plain(nw, torch, ctx, batch, range(B), dd)
 
-        def plain_pass():
-            for mnb in miners:
-                mnb.mine(w, gap, thr)
-        plain = _time_steps(plain_pass, 1, 1, torch)
-        del miners
+    cpu = None
+    if not args.no_cpu:
+        _log("cpu baseline")
+        cpu = cpu_baseline(nw, torch, ctx, batch, runs[head]["miner"], head_prec, dd)
+    runs[head].pop("miner")
+    del db
 
-    head = precs[0][0]
-    bf_ms = results[head]
-    value = B / (bf_ms / 1000.0)
-    kb = kernel[head]
-    score_ms = kb.get("score", float("nan"))
-    fill_ms = kb.get("nw_fill", float("nan"))
-    # the contraction multiplies each 64 x 64 tile over the compacted chunks
-    # of its target-side vocabulary: 2 * 64 * 64 * 32 flop per chunk executed
-    # on the matrix cores; the dense definition (2 V flop per cell) is
-    # reported beside it
-    dense_flops = 2.0 * V * cells
-    n_kc = compacted_chunks(batch)
-    flops = 2.0 * 64 * 64 * 32 * n_kc
-    achieved = flops / (score_ms / 1000.0) / 1e12
-    gcups = cells / (fill_ms / 1000.0) / 1e9
-    dp_bytes = cells * 4.25
+    extra = {}
+    if not args.no_extra:
+        for xc in (3, 5):
+            if xc == cfg:
+                continue
+            _log("workload %d: generating" % xc)
+            xb = corpus.make_batch(xc)
+            xd = nw.DeviceDict.from_host(xb)
+            xa = argparse.Namespace(**vars(args))
+            xa.steps, xa.warmup = args.extra_steps, 1
+            r = batched(nw, torch, ctx, xb, "bf16", nw.NWM_BF16, xa, dd=xd)
+            r.pop("miner")
+            s = summarize(xb, r, "bf16")
+            s.update(pairs=xb.B, cells=xb.cells(), V=xb.V, workload=WORKLOADS[xc] % (xb.B, xb.V, "BF16"))
+            if xc == 5 and not args.no_plain:
+                rng = np.random.default_rng(1512)
+                idx = np.sort(rng.choice(xb.B, size=min(args.plain_sample, xb.B), replace=False))
+                _log("workload 5: plain per-pair FP32 on %d sampled pairs" % len(idx))
+                pms = plain(nw, torch, ctx, xb, idx, xd)
+                pps = len(idx) / (pms / 1000.0)
+                s["pairs_per_s_plain_fp32"] = round(pps, 2)
+                s["plain_sample"] = "%d pairs drawn by numpy default_rng(1512) without replacement" % len(idx)
+                s["ratio_batched_bf16_vs_plain_fp32"] = round(s["pairs_per_s"] / pps, 2)
+            extra[EXTRA[xc]] = s
+            del xb, xd
+            torch.cuda.empty_cache()
+
+    hs = head_sum
+    dom = hs["dominant"]
     out = {
         "metric": "NW GCUPS + aligned doc-pairs/s, batched BF16 vs plain FP32, same GPU",
-        "value": round(value, 2),
+        "value": hs["pairs_per_s"],
         "unit": "doc-pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(bf_ms, 4),
+        "ms_per_step": hs["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": head,
         "data": "synthetic (seeded comparable-corpus generator with planted alignments)",
-        "config": {"workload": WORKLOADS[cfg] % (B, V),
-                   "pairs": B, "cells": cells, "V": V},
-        "gcups": round(gcups, 3),
+        "config": {"workload": WORKLOADS[cfg] % (B, V, head.upper()), "pairs": B, "cells": cells, "V": V},
+        "gcups": hs["gcups"],
         "launch": "eager" if args.no_graph else "hipGraph replay of the whole path per step",
-        "launch_params": tuned if tuned else "defaults",
-        "ms_per_step_eager": {p: round(v, 4) for p, v in eager.items()},
-        "pairs_per_s_batched_fp32": round(B / (results["f32"] / 1000.0), 2) if "f32" in results else None,
-        "pairs_per_s_plain_fp32": round(B / (plain / 1000.0), 2) if plain else None,
-        "ratio_batched_bf16_vs_plain_fp32": round(plain / bf_ms, 2) if plain else None,
-        "kernel_ms_per_step": {p: {k: round(v, 4) for k, v in kernel[p].items()} for p, _ in precs},
-        "contraction_roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": MFMA_PEAK_TFLOPS[head],
-                     "unit": "TFLOP/s", "frac": round(achieved / MFMA_PEAK_TFLOPS[head], 4),
-                     "traffic": profiled_traffic("k_score_c<%s>" % head),
-                     "kernel": "k_score_c<%s> (compacted contraction + logistic epilogue)" % head,
-                     "algorithmic": "2*64*64*32 flop per compacted K chunk of a 64x64 tile, %d chunks = %.4g "
-                                    "flop per launch" % (n_kc, flops),
-                     "dense_equivalent": {"flop": dense_flops, "TFLOP/s": round(dense_flops / (score_ms / 1000.0)
-                                                                                / 1e12, 2),
-                                          "note": "2*V*sum(n*m): the whole-vocabulary definition; the compacted "
-                                                  "contraction skips words absent from a tile's target sentences"}},
-        "dp_roofline": {"bound": "hbm", "achieved": round(dp_bytes / (fill_ms / 1000.0) / 1e9, 1),
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(dp_bytes / (fill_ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
-                        "kernel": "k_nw_fill", "algorithmic": "4.25 B/cell (S read + 2-bit traceback)",
-                        "traffic": profiled_traffic("k_nw_fill")},
+        "launch_params": {p: r["params"] for p, r in runs.items()},
+        "ms_per_step_eager": {p: round(r["eager_ms"], 4) for p, r in runs.items()},
+        "pairs_per_s_batched_fp32": round(B / (runs["f32"]["ms"] / 1000.0), 2) if "f32" in runs else None,
+        "pairs_per_s_plain_fp32": round(B / (plain_ms / 1000.0), 2) if plain_ms else None,
+        "ratio_batched_bf16_vs_plain_fp32": round(plain_ms / hs["ms_per_step"], 2) if plain_ms else None,
+        "kernel_ms_per_step": {p: {k: round(v, 4) for k, v in r["kernel"].items()} for p, r in runs.items()},
+        "rooflines": hs["rooflines"],
+        "contraction_roofline": hs["rooflines"].get("score"),
+        "dp_roofline": hs["rooflines"].get("nw_fill"),
     }
-    # `roofline` is the one of the kernel that took longest per step (the
-    # contraction or the NW fill; both are reported)
-    dom = "contraction_roofline" if score_ms >= fill_ms else "dp_roofline"
-    out["roofline"] = dict(out[dom], dominant_kernel_ms=round(max(score_ms, fill_ms), 4))
+    # `roofline`: the kernel that took longest per step in the eager timed
+    # region (every kernel class is a candidate; all are in `rooflines`)
+    out["roofline"] = dict(hs["rooflines"][dom], dominant_class=dom)
+    if extra:
+        out["workloads"] = extra
     if bidir is not None:
         out["bidirectional"] = bidir
     if search is not None:
         out["random_search"] = search
-    if not args.no_cpu:
-        _log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(batch)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -108,8 +108,14 @@ typedef struct {
 /* Create a context bound to HIP device `hip_device`.  Fails with NWM_EDEVICE
  * if the device is absent or not gfx950. */
 nwm_status nwm_create(nwm_ctx **ctx, int hip_device);
+/* Destroy a context.  Plans made from it may be destroyed before or after. */
 void nwm_destroy(nwm_ctx *ctx);
 const char *nwm_strerror(nwm_status s);
+/* Name of the HIP error behind the last NWM_EDEVICE an entry point returned
+ * on the calling thread ("none" if there was none).  Entry points clear an
+ * error left by an earlier, unrelated HIP call before they launch, so the
+ * error named here is the library's own.  The string is static. */
+const char *nwm_last_device_error(void);
 
 /* --- plan ----------------------------------------------------------------- */
 
@@ -280,17 +286,29 @@ nwm_status nwm_plan_get_param(const nwm_plan *plan, nwm_param param, int32_t *va
 
 /* --- measurement ------------------------------------------------------------ */
 
+/* Kernel classes of the per-kernel timing. */
+typedef enum {
+  NWM_K_MERGE = 0,     /* merged dictionary rows of the source sentences */
+  NWM_K_BUILD_A = 1,   /* source-side (row-tile) operand lists */
+  NWM_K_BUILD_B = 2,   /* target-side (column-tile) operand lists and vocabularies */
+  NWM_K_SCORE = 3,     /* contraction + logistic scorer */
+  NWM_K_FILL = 4,      /* NW fill (with the reset of its hand-off rows) */
+  NWM_K_WALK = 5,      /* traceback */
+  NWM_K_KEEP = 6,      /* threshold filter */
+  NWM_K_BACKWARD = 7,  /* nwm_align_backward */
+  NWM_N_KCLASSES = 8
+} nwm_kclass;
+
 /* Record HIP events around every kernel the plan launches (0 = off).  While
- * on, nwm_plan_kernel_ms returns the summed device time per kernel class of
- * all launches since the last reset, measured on the launching stream:
- *   [0] expand (merged dictionary rows + source-side tile lists; the
- *       target-side lists run concurrently on a second stream, untimed)
- *   [1] contraction + logistic
- *   [2] NW fill                                [3] traceback + keep
- *   [4] backward.
- * `counts` receives launches per class.  Reading waits for the events. */
+ * on, nwm_mine runs its kernels one at a time on the caller's stream (the
+ * target-side lists on a second stream, as in nwm_score_pairs), and
+ * nwm_plan_kernel_ms returns the summed device time per kernel class
+ * (nwm_kclass) of all launches since the last reset, each measured on the
+ * stream that launched it.  `counts` (nullable) receives launches per class.
+ * Reading waits for the events. */
 nwm_status nwm_plan_set_timing(nwm_plan *plan, int on);
-nwm_status nwm_plan_kernel_ms(nwm_plan *plan, double ms[5], int32_t counts[5], int reset);
+nwm_status nwm_plan_kernel_ms(nwm_plan *plan, double ms[NWM_N_KCLASSES], int32_t counts[NWM_N_KCLASSES],
+                              int reset);
 
 #ifdef __cplusplus
 }

@@ -21,8 +21,8 @@ from . import _abi
 from ._abi import NWM_BF16, NWM_FP32, NwmError
 
 __all__ = ["Context", "DeviceBatch", "DeviceDict", "Plan", "Miner", "BiMiner", "score_pairs", "align_batch",
-           "align_check", "align_backward", "mine", "union_kept", "NWAlign", "MineScore", "LogisticScore", "NWM_FP32",
-           "NWM_BF16", "NwmError"]
+           "align_check", "align_backward", "mine", "union_kept", "NWAlign", "MineScore",
+           "LogisticScore", "NWM_FP32", "NWM_BF16", "NwmError"]
 
 
 def _ptr(t):
@@ -163,11 +163,13 @@ class Plan:
     def set_timing(self, on: bool):
         _abi.check(self.lib.nwm_plan_set_timing(self.h, int(bool(on))), "nwm_plan_set_timing")
 
-    KERNEL_CLASSES = ("expand", "score", "nw_fill", "traceback", "backward")
+    KERNEL_CLASSES = ("merge", "build_a", "build_b", "score", "nw_fill", "walk", "keep", "backward")
 
     def kernel_ms(self, reset: bool = True):
-        ms = (ctypes.c_double * 5)()
-        cnt = (ctypes.c_int32 * 5)()
+        """{kernel class: (summed ms, launches)} since the last reset."""
+        k = len(self.KERNEL_CLASSES)
+        ms = (ctypes.c_double * k)()
+        cnt = (ctypes.c_int32 * k)()
         _abi.check(self.lib.nwm_plan_kernel_ms(self.h, ms, cnt, int(bool(reset))), "nwm_plan_kernel_ms")
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.KERNEL_CLASSES)}
 

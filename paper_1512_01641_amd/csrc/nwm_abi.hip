@@ -54,7 +54,18 @@ struct nwm_ctx {
 
 namespace {
 
-enum { K_EXPAND = 0, K_SCORE = 1, K_FILL = 2, K_WALK = 3, K_BWD = 4, K_CLASSES = 5 };
+// kernel classes of the per-kernel timing (nwm_kclass)
+enum {
+  K_MERGE = NWM_K_MERGE,
+  K_BUILD_A = NWM_K_BUILD_A,
+  K_BUILD_B = NWM_K_BUILD_B,
+  K_SCORE = NWM_K_SCORE,
+  K_FILL = NWM_K_FILL,
+  K_WALK = NWM_K_WALK,
+  K_KEEP = NWM_K_KEEP,
+  K_BWD = NWM_K_BACKWARD,
+  K_CLASSES = NWM_N_KCLASSES
+};
 
 struct Timer {
   bool on = false;
@@ -82,8 +93,10 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 }  // namespace
 
+
 struct nwm_plan {
   nwm_ctx *ctx = nullptr;
+  int device = 0;   // the context's device (kept here: a plan may outlive its context's handle)
   int B = 0, V = 0, max_deg = 0;
   nwm_prec prec = NWM_FP32;
   int64_t n_src = 0, n_tgt = 0, src_tokens = 0, tgt_tokens = 0;
@@ -130,7 +143,20 @@ struct nwm_plan {
 
 namespace {
 
-nwm_status dev_err(hipError_t e) { return e == hipSuccess ? NWM_OK : NWM_EDEVICE; }
+// The HIP error behind the last NWM_EDEVICE of this thread (nwm_last_device_error).
+thread_local hipError_t g_last_hip_error = hipSuccess;
+
+nwm_status dev_err(hipError_t e) {
+  if (e == hipSuccess) return NWM_OK;
+  g_last_hip_error = e;
+  return NWM_EDEVICE;
+}
+
+// Launch checks read hipGetLastError, which also returns an error left by an
+// earlier, unrelated HIP call of this thread (another library's, or a failed
+// destroy): entry points clear it first, so a failure they report is their
+// own.
+void clear_stale_error() { (void)hipGetLastError(); }
 
 // DP item words: strip index, plus ITEM_HOT for pairs whose dependency chain
 // is at least NWM_PARAM_DP_HOT_PERCENT of the longest
@@ -172,6 +198,10 @@ bool finite(float x) { return std::isfinite(x); }
 }  // namespace
 
 extern "C" {
+
+const char *nwm_last_device_error(void) {
+  return g_last_hip_error == hipSuccess ? "none" : hipGetErrorName(g_last_hip_error);
+}
 
 const char *nwm_strerror(nwm_status s) {
   switch (s) {
@@ -219,6 +249,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   nwm_plan *p = new (std::nothrow) nwm_plan();
   if (!p) return NWM_ENOMEM;
   p->ctx = ctx;
+  p->device = ctx->device;
   p->B = B;
   p->V = batch->V;
   p->max_deg = max_deg;
@@ -503,7 +534,7 @@ nwm_status nwm_plan_sizes(const nwm_plan *plan, nwm_sizes *sizes) {
 
 void nwm_plan_destroy(nwm_plan *plan) {
   if (!plan) return;
-  (void)hipSetDevice(plan->ctx->device);
+  (void)hipSetDevice(plan->device);
   if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
   if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
   if (plan->aux_stream) (void)hipStreamDestroy(plan->aux_stream);
@@ -566,16 +597,18 @@ static hipError_t expand_src(nwm_plan *p, const nwm_batch *batch, const nwm_dict
   // operand tiles
   const int pitch = bf16 ? PITCH_BF16 : PITCH_F32;
   const int esize = bf16 ? 2 : 4;
-  Mark mk(p, K_EXPAND, st);
+  Mark mk(p, K_MERGE, st);
   hipError_t e = launch_merge_src(ns, p->dev.sent_ids, k0, batch->src_off, batch->src_tok, dict->row_off, dict->col,
                                   dict->val, p->V, p->max_deg, p->max_entries, merged, cnt,
                                   p->param[NWM_PARAM_MERGE_WAVES_PER_CU], st);
+  mk.done();
   if (e == hipSuccess && tgt_done) e = hipStreamWaitEvent(st, tgt_done, 0);
+  Mark ma(p, K_BUILD_A, st);
   if (e == hipSuccess)
     e = launch_build_a(p->dev, batch->src_off, merged, cnt, (uint2 *)(w + p->ws.a_list),
                        (int32_t *)(w + p->ws.a_choff), pitch, esize, p->param[NWM_PARAM_SCORE_COMPACT],
                        (int64_t *)(w + p->ws.a_base), pair_vocab(p, ws), r0, nr, st);
-  mk.done();
+  ma.done();
   return e;
 }
 
@@ -586,13 +619,16 @@ static hipError_t expand_tgt(nwm_plan *p, const nwm_batch *batch, void *ws, int 
   char *w = static_cast<char *>(ws);
   const bool bf16 = p->prec == NWM_BF16;
   uint32_t *voc = pair_vocab(p, ws);
+  Mark mk(p, K_BUILD_B, st);
   hipError_t e = hipSuccess;
   if (first && voc) e = launch_clear_u32(voc, (int64_t)p->B * p->dev.nch, st);
-  if (e != hipSuccess) return e;
-  return launch_build_b(p->dev, batch->tgt_off, batch->tgt_tok, (uint32_t *)(w + p->ws.b_list),
-                        (int32_t *)(w + p->ws.b_choff), bf16 ? PITCH_BF16 : PITCH_F32, bf16 ? 2 : 4,
-                        p->param[NWM_PARAM_SCORE_COMPACT], (uint2 *)(w + p->ws.b_mt), (int32_t *)(w + p->ws.b_kcn),
-                        (int2 *)(w + p->ws.b_rng), (int64_t *)(w + p->ws.b_base), voc, c0, nc, st);
+  if (e == hipSuccess)
+    e = launch_build_b(p->dev, batch->tgt_off, batch->tgt_tok, (uint32_t *)(w + p->ws.b_list),
+                       (int32_t *)(w + p->ws.b_choff), bf16 ? PITCH_BF16 : PITCH_F32, bf16 ? 2 : 4,
+                       p->param[NWM_PARAM_SCORE_COMPACT], (uint2 *)(w + p->ws.b_mt), (int32_t *)(w + p->ws.b_kcn),
+                       (int2 *)(w + p->ws.b_rng), (int64_t *)(w + p->ws.b_base), voc, c0, nc, st);
+  mk.done();
+  return e;
 }
 
 // The whole expansion.  The target-side lists do not depend on the source
@@ -641,6 +677,7 @@ static hipError_t ensure_streams(nwm_plan *p) {
 
 nwm_status nwm_score_pairs(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, nwm_scorer sc, float *S,
                            float *S_raw, void *ws, void *stream) {
+  clear_stale_error();
   nwm_status s = check_score_args(p, batch, dict, sc, S, ws);
   if (s != NWM_OK || p->sizes.S_elems == 0) return s;
   hipStream_t st = (hipStream_t)stream;
@@ -652,6 +689,7 @@ nwm_status nwm_score_pairs(nwm_plan *p, const nwm_batch *batch, const nwm_dict *
 
 nwm_status nwm_align_batch(nwm_plan *p, const float *S, float gap, float threshold, float *score,
                            int32_t *n_diag, int32_t *kept, int32_t *n_kept, void *tb, void *ws, void *stream) {
+  clear_stale_error();
   if (!p) return NWM_EINVAL;
   if (!finite(gap) || !finite(threshold)) return NWM_EINVAL;
   if (p->B == 0) return NWM_OK;
@@ -671,11 +709,15 @@ nwm_status nwm_align_batch(nwm_plan *p, const float *S, float gap, float thresho
                        p->param[NWM_PARAM_DP_SPIN_LIMIT], p->param[NWM_PARAM_DP_TEST_HOLD], st);
     mk.done();
   }
-  if (e != hipSuccess) return NWM_EDEVICE;
+  if (e != hipSuccess) return dev_err(e);
   {
     Mark mk(p, K_WALK, st);
     e = launch_nw_walk(p->dev, tbc, score, path, n_diag, 0, p->B, st);
-    if (e == hipSuccess) e = launch_keep(p->dev, S, threshold, path, n_diag, (int2 *)kept, n_kept, 0, p->B, st);
+    mk.done();
+  }
+  if (e == hipSuccess) {
+    Mark mk(p, K_KEEP, st);
+    e = launch_keep(p->dev, S, threshold, path, n_diag, (int2 *)kept, n_kept, 0, p->B, st);
     mk.done();
   }
   return dev_err(e);
@@ -702,6 +744,7 @@ nwm_status nwm_align_backward(nwm_plan *p, const nwm_batch *batch, const void *t
                               void *stream) {
   (void)sc;
   if (!p) return NWM_EINVAL;
+  clear_stale_error();
   nwm_status s = check_batch(p, batch);
   if (s != NWM_OK) return s;
   if (p->B == 0) return NWM_OK;
@@ -752,7 +795,7 @@ nwm_status nwm_plan_set_param(nwm_plan *p, nwm_param param, int32_t value) {
   if (param == NWM_PARAM_DP_HOT_PERCENT && !p->it_strip.empty()) {
     std::vector<int32_t> words;
     hot_flags(p, words);
-    if (hipSetDevice(p->ctx->device) != hipSuccess ||
+    if (hipSetDevice(p->device) != hipSuccess ||
         hipMemcpy(const_cast<int32_t *>(p->dev.it_strip), words.data(), 4 * words.size(), hipMemcpyHostToDevice) !=
             hipSuccess)
       return NWM_EDEVICE;
@@ -772,6 +815,7 @@ nwm_status nwm_union_kept(const nwm_plan *p, const int32_t *kept_fwd, const int3
   if (!p) return NWM_EINVAL;
   if (p->B == 0) return NWM_OK;
   if (!n_kept_fwd || !n_kept_rev || !n_out) return NWM_EINVAL;
+  clear_stale_error();
   if (p->sizes.kept_cap > 0 && (!kept_fwd || !kept_rev || !kept_out)) return NWM_EINVAL;
   return dev_err(launch_union_kept(p->B, p->dev.p_off, (const int2 *)kept_fwd, n_kept_fwd, (const int2 *)kept_rev,
                                    n_kept_rev, (int2 *)kept_out, n_out, (hipStream_t)stream));
@@ -886,6 +930,7 @@ nwm_status nwm_mine(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, n
                     float threshold, float *S, float *S_raw, float *score, int32_t *n_diag, int32_t *kept,
                     int32_t *n_kept, void *tb, void *ws, void *stream) {
   if (!p) return NWM_EINVAL;
+  clear_stale_error();
   if (!p->graph_on) {
     if (p->timer.on) {
       // per-kernel timing: one kernel at a time on the caller's stream
@@ -916,26 +961,27 @@ nwm_status nwm_mine(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, n
       (void)hipGraphExecDestroy(p->graph_exec);
       p->graph_exec = nullptr;
     }
-    if (!p->cap_stream && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
-      return NWM_EDEVICE;
-    if (ensure_streams(p) != hipSuccess) return NWM_EDEVICE;
-    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return NWM_EDEVICE;
+    hipError_t e = hipSuccess;
+    if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = ensure_streams(p);
+    if (e == hipSuccess) e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return dev_err(e);
     p->capturing = true;
     nwm_status s = mine_path(p, batch, dict, sc, gap, threshold, S, S_raw, score, n_diag, kept, n_kept, tb, ws,
                              p->cap_stream);
     p->capturing = false;
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    e = hipStreamEndCapture(p->cap_stream, &g);
     if (s != NWM_OK) {
       if (g) (void)hipGraphDestroy(g);
       return s;
     }
-    if (e != hipSuccess || !g) return NWM_EDEVICE;
+    if (e != hipSuccess || !g) return dev_err(e != hipSuccess ? e : hipErrorUnknown);
     e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
       p->graph_exec = nullptr;
-      return NWM_EDEVICE;
+      return dev_err(e);
     }
     p->graph_key = key;
   }
@@ -949,7 +995,7 @@ nwm_status nwm_plan_set_timing(nwm_plan *p, int on) {
   return NWM_OK;
 }
 
-nwm_status nwm_plan_kernel_ms(nwm_plan *p, double ms[5], int32_t counts[5], int reset) {
+nwm_status nwm_plan_kernel_ms(nwm_plan *p, double ms[NWM_N_KCLASSES], int32_t counts[NWM_N_KCLASSES], int reset) {
   if (!p || !ms) return NWM_EINVAL;
   for (int k = 0; k < K_CLASSES; ++k) {
     ms[k] = 0.0;

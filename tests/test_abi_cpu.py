@@ -34,6 +34,8 @@ def test_strerror():
     assert lib.nwm_strerror(0) == b"ok"
     assert lib.nwm_strerror(1) == b"invalid argument"
     assert lib.nwm_strerror(99) == b"unknown status"
+    # no entry point has failed on a device in this thread
+    assert lib.nwm_last_device_error() == b"none"
 
 
 def test_null_arguments_rejected():
