@@ -181,6 +181,28 @@ nwm_status nwm_align_batch(nwm_plan *plan, const float *S, float gap, float thre
  * (B > 0) a NULL ws. */
 nwm_status nwm_align_check(const nwm_plan *plan, const void *ws, int32_t *failed, void *stream);
 
+/* nwm_align_batch for callers that cannot allocate device memory or pass a
+ * workspace: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, outputs and layouts as
+ * nwm_align_batch, without `ws`; it calls no allocating routine.  Its
+ * scratch (the DP's queue heads and error flag, the boundary rows handed
+ * between the strips of a pair, the fill waves' sink lines) is a fixed
+ * device array of the library, 32 MiB on every GPU the library runs on, held
+ * until the process ends and reached through its device address, taken once
+ * per device by nwm_create.  A plan needs 256 + 8 * (published-row slots +
+ * 16400) bytes of it, where a pair of n_b x m_b sentences publishes
+ * (ceil(n_b / 64) - 1) rows of about m_b + 194 slots; larger plans return
+ * NWM_EUNSUPPORTED (a batch of 4096 pairs of median 60 sentences needs about
+ * 17 MiB).  Every call on a GPU shares that GPU's array and leaves its
+ * contents behind; the call clears what must start at zero itself, by a
+ * kernel.  Calls that overlap on one GPU (two streams, two threads, two
+ * plans) race on the array and must be ordered by the caller.  A DP wave that
+ * gives up waiting shows only as a NaN score of its pair (nwm_align_check
+ * reads a workspace and does not apply). */
+nwm_status nwm_align_batch_noalloc(nwm_plan *plan, const float *S, float gap, float threshold,
+                                   float *score, int32_t *n_diag, int32_t *kept, int32_t *n_kept,
+                                   void *tb, void *stream);
+
 /* Backward of L = sum_b grad_score[b] * Score_b + sum_ij grad_S_extra[ij] * S[ij]
  * through the alignment and the logistic scorer, for gradient tuning of the
  * scorer and the gap penalty (Sec. 5.2 tunes threshold and penalty against

@@ -21,7 +21,7 @@ from . import _abi
 from ._abi import NWM_BF16, NWM_FP32, NwmError
 
 __all__ = ["Context", "DeviceBatch", "DeviceDict", "Plan", "Miner", "BiMiner", "score_pairs", "align_batch",
-           "align_check", "align_backward", "mine", "union_kept", "NWAlign", "MineScore",
+           "align_check", "align_batch_noalloc", "align_backward", "mine", "union_kept", "NWAlign", "MineScore",
            "LogisticScore", "NWM_FP32", "NWM_BF16", "NwmError"]
 
 
@@ -203,6 +203,14 @@ def align_batch(plan: Plan, S, gap: float, threshold: float, score, n_diag, kept
     _abi.check(plan.lib.nwm_align_batch(plan.h, _ptr(S), float(gap), float(threshold), _ptr(score), _ptr(n_diag),
                                         _ptr(kept), _ptr(n_kept), _ptr(tb), _ptr(ws), _stream(plan.ctx.device)),
                "nwm_align_batch")
+
+
+def align_batch_noalloc(plan: Plan, S, gap: float, threshold: float, score, n_diag, kept, n_kept, tb):
+    """nwm_align_batch_noalloc on the current stream: nwm_align_batch with
+    the library's fixed device scratch instead of a workspace."""
+    _abi.check(plan.lib.nwm_align_batch_noalloc(plan.h, _ptr(S), float(gap), float(threshold), _ptr(score),
+                                                _ptr(n_diag), _ptr(kept), _ptr(n_kept), _ptr(tb),
+                                                _stream(plan.ctx.device)), "nwm_align_batch_noalloc")
 
 
 def align_check(plan: Plan, ws) -> bool:

@@ -16,7 +16,8 @@ STATUS_NAMES = {0: "NWM_OK", 1: "NWM_EINVAL", 2: "NWM_ESHAPE", 3: "NWM_ENOMEM", 
 SYMBOLS = ["nwm_create", "nwm_destroy", "nwm_strerror", "nwm_plan_create", "nwm_plan_sizes",
            "nwm_plan_destroy", "nwm_score_pairs", "nwm_align_batch", "nwm_align_backward", "nwm_mine",
            "nwm_plan_set_graph", "nwm_plan_set_param", "nwm_plan_get_param", "nwm_plan_set_timing",
-           "nwm_plan_kernel_ms", "nwm_union_kept", "nwm_align_check", "nwm_last_device_error"]
+           "nwm_plan_kernel_ms", "nwm_union_kept", "nwm_align_check", "nwm_last_device_error",
+           "nwm_align_batch_noalloc"]
 
 PARAMS = {"fill_waves_per_cu": 0, "merge_waves_per_cu": 1, "score_xcd_map": 2, "dp_hot_percent": 3,
           "score_compact": 4, "dp_spin_limit": 5, "dp_test_hold": 6}
@@ -99,6 +100,8 @@ def load(path: str | None = None):
     lib.nwm_union_kept.restype = I
     lib.nwm_align_check.argtypes = [P, P, ctypes.POINTER(ctypes.c_int32), P]
     lib.nwm_align_check.restype = I
+    lib.nwm_align_batch_noalloc.argtypes = [P, P, ctypes.c_float, ctypes.c_float, P, P, P, P, P, P]
+    lib.nwm_align_batch_noalloc.restype = I
     lib.nwm_last_device_error.argtypes = []
     lib.nwm_last_device_error.restype = ctypes.c_char_p
     if path == LIB_PATH:

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -93,6 +94,39 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 }  // namespace
 
+// Device scratch of nwm_align_batch_noalloc: the DP's queue heads and error
+// flag (first 256 bytes), then the published boundary rows between strips and
+// the fill waves' sink lines.  Every GPU the library runs on holds its own
+// copy until the process ends; the host reaches it only through the address
+// hipGetSymbolAddress gives on that device (the array's name in host code is
+// not a device address).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) uint64_t scratch[NOALLOC_SCRATCH_BYTES / 8];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Once per device, with that device current: the device address of `scratch`.
+hipError_t scratch_init(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[dev] = ptr;
+  return hipSuccess;
+}
+
+void *scratch_ptr(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
+}  // namespace
 
 struct nwm_plan {
   nwm_ctx *ctx = nullptr;
@@ -224,6 +258,8 @@ nwm_status nwm_create(nwm_ctx **ctx, int hip_device) {
   if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return NWM_EDEVICE;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return NWM_EDEVICE;
   if (hipSetDevice(hip_device) != hipSuccess) return NWM_EDEVICE;
+  // the device address of the no-allocation entry point's scratch
+  if (scratch_init(hip_device) != hipSuccess) return NWM_EDEVICE;
   nwm_ctx *c = new (std::nothrow) nwm_ctx();
   if (!c) return NWM_ENOMEM;
   c->device = hip_device;
@@ -736,6 +772,34 @@ nwm_status nwm_align_check(const nwm_plan *p, const void *ws, int32_t *failed, v
     return NWM_EDEVICE;
   if (failed) *failed = flag != 0;
   return flag != 0 ? NWM_EDEVICE : NWM_OK;
+}
+
+nwm_status nwm_align_batch_noalloc(nwm_plan *p, const float *S, float gap, float threshold, float *score,
+                                   int32_t *n_diag, int32_t *kept, int32_t *n_kept, void *tb, void *stream) {
+  if (!p) return NWM_EINVAL;
+  if (!finite(gap) || !finite(threshold)) return NWM_EINVAL;
+  if (p->B == 0) return NWM_OK;
+  if (!score || !n_diag || !n_kept) return NWM_EINVAL;
+  if (p->sizes.S_elems > 0 && !S) return NWM_EINVAL;
+  if (p->sizes.kept_cap > 0 && (!kept || !tb)) return NWM_EINVAL;
+  // [256 B: queue heads, error flag][published rows][sink lines (128-byte aligned)]
+  const size_t need = 256 + 8 * ((size_t)p->n_bnd + FILL_SINK_SLOTS);
+  if (need > NOALLOC_SCRATCH_BYTES) return NWM_EUNSUPPORTED;
+  char *base = static_cast<char *>(scratch_ptr(p->device));
+  if (!base) return NWM_EDEVICE;
+  clear_stale_error();
+  hipStream_t st = (hipStream_t)stream;
+  char *tbc = static_cast<char *>(tb);
+  int2 *path = tbc ? (int2 *)(tbc + p->dev.path_base) : nullptr;
+  int32_t *ctl = reinterpret_cast<int32_t *>(base);
+  uint64_t *bnd = reinterpret_cast<uint64_t *>(base + 256);
+  // the reset kernel clears the queue heads, the error flag and the published
+  // rows' tags left by the previous call (no memset node, no allocation)
+  hipError_t e = launch_nw_fill(p->dev, S, gap, score, tbc, bnd, p->n_bnd, ctl, p->param[NWM_PARAM_FILL_WAVES_PER_CU],
+                                p->param[NWM_PARAM_DP_SPIN_LIMIT], p->param[NWM_PARAM_DP_TEST_HOLD], st);
+  if (e == hipSuccess) e = launch_nw_walk(p->dev, tbc, score, path, n_diag, 0, p->B, st);
+  if (e == hipSuccess) e = launch_keep(p->dev, S, threshold, path, n_diag, (int2 *)kept, n_kept, 0, p->B, st);
+  return dev_err(e);
 }
 
 nwm_status nwm_align_backward(nwm_plan *p, const nwm_batch *batch, const void *tb, const int32_t *n_diag,
