@@ -71,66 +71,59 @@ static __device__ __forceinline__ T *uniform_ptr(T *p) {
 }
 
 // The parallelogram of S used by steps [GROUP*q, GROUP*q + GROUP): row r,
-// columns GROUP*q - r + [0, GROUP); cells outside the strip read 0.  It goes
-// straight from memory into ring half (q & 1) by LDS-direct buffer loads, one
-// per row pair (lanes 0..31 row 2k, lanes 32..63 row 2k + 1, one step each),
-// so row r of the half starts at float (r >> 1) * PAIR_PITCH + (r & 1) * 32
-// and step t of the group is float t of the row.  No register holds S.
+// columns GROUP*q - r + [0, GROUP).  It goes straight from memory into ring
+// half (q & 1) by 32 LDS-direct buffer loads, one per row pair (lanes 0..31
+// row 2k, lanes 32..63 row 2k + 1, one step each), so row r of the half
+// starts at float (r >> 1) * PAIR_PITCH + (r & 1) * 32 and step t of the
+// group is float t of the row.  No register holds S.
+//
+// Lane l of load k reads strip element (2k + h) m + GROUP q + c - 2k - h
+// (h = l >> 5, c = l & 31), i.e. lane_off + k (2m - 2) + GROUP q: one linear
+// address for every group.  A cell outside the strip's m columns (the first
+// steps of a row, the steps after its last column) reads another cell of the
+// strip, or 0 past the strip's end through the buffer range check: a finite
+// value that only the masked steps see, and those leave H unchanged there.
+// Rows at or beyond `rows` (the last strip of a pair) lie past the end.
 struct StripSrc {
   __amdgpu_buffer_rsrc_t rs;
   int m, rows;
   int lane_off;   // bytes: row (lane >> 5), column (lane & 31) - (lane >> 5)
 };
 
-static __device__ __forceinline__ bool group_interior(const StripSrc &src, int q) {
-  // every cell of the group lies inside the strip
-  return src.rows == 64 && q >= 2 && GROUP * q + GROUP <= src.m;
-}
-
 typedef __attribute__((address_space(3))) void lds_void;
-constexpr uint32_t S_OOB = 0xFFFFFFF0u;   // a buffer offset past every strip: the load returns 0
 
-// One LDS-direct buffer load: lane l's dword at (voff + soff) of the strip
-// lands at LDS byte address lds + 4 l.  Written as one asm statement so that
-// the compiler neither reorders it with other memory accesses nor adds waits
-// for it: every read of the ring waits for it with an explicit vmcnt (below).
-// M0, which gives the LDS address, is restored afterwards.
-static __device__ __forceinline__ void s_to_lds(const StripSrc &src, const float *lds, uint32_t voff, int soff) {
-  const uint32_t la = (uint32_t)(uintptr_t)(lds_void *)lds;
-  uint32_t save;
+#define NWM_S_LOAD_NEXT                 \
+  "s_add_u32 m0, m0, 272\n\t"            \
+  "v_add_u32 %1, %6, %1\n\t"             \
+  "buffer_load_dword %1, %4, %5 offen lds\n\t"
+#define NWM_S_LOAD_NEXT4 NWM_S_LOAD_NEXT NWM_S_LOAD_NEXT NWM_S_LOAD_NEXT NWM_S_LOAD_NEXT
+
+// The 32 loads of group q, in one asm statement so that the compiler neither
+// reorders them with other memory accesses nor adds waits for them: every
+// read of the ring waits for them with an explicit vmcnt (below).  M0 (the
+// LDS address of a load) is saved, stepped by one row pair (PAIR_PITCH
+// floats) per load and restored; the address VGPR steps by 2m - 2 elements.
+static_assert(PAIR_PITCH * 4 == 272, "ring row-pair pitch");
+static __device__ __forceinline__ void load_group(float *ring, const StripSrc &src, int q) {
+  const uint32_t la = (uint32_t)(uintptr_t)(lds_void *)(ring + (q & 1) * HALF);
+  const int soff = GROUP * q * 4;
+  const uint32_t step = (uint32_t)(2 * src.m - 2) * 4u;
+  uint32_t save, vo;
   asm volatile(
       "s_mov_b32 %0, m0\n\t"
-      "s_mov_b32 m0, %1\n\t"
-      "s_nop 0\n\t"
-      "buffer_load_dword %2, %3, %4 offen lds\n\t"
+      "s_mov_b32 m0, %2\n\t"
+      "v_mov_b32 %1, %3\n\t"
+      "buffer_load_dword %1, %4, %5 offen lds\n\t"
+      NWM_S_LOAD_NEXT NWM_S_LOAD_NEXT NWM_S_LOAD_NEXT
+      NWM_S_LOAD_NEXT4 NWM_S_LOAD_NEXT4 NWM_S_LOAD_NEXT4 NWM_S_LOAD_NEXT4
+      NWM_S_LOAD_NEXT4 NWM_S_LOAD_NEXT4 NWM_S_LOAD_NEXT4
       "s_mov_b32 m0, %0"
-      : "=&s"(save)
-      : "s"(la), "v"(voff), "s"(src.rs), "s"(soff)
-      : "memory");
+      : "=&s"(save), "=&v"(vo)
+      : "s"(la), "v"(src.lane_off), "s"(src.rs), "s"(soff), "s"(step)
+      : "memory", "scc");
 }
-
-static __device__ __forceinline__ void load_group(float *ring, const StripSrc &src, int q, int lane) {
-  float *dst = ring + (q & 1) * HALF;
-  if (group_interior(src, q)) {
-    int soff = GROUP * q * 4;
-    const int step = (2 * src.m - 2) * 4;
-#pragma unroll
-    for (int k = 0; k < GROUP; ++k) {
-      s_to_lds(src, dst + k * PAIR_PITCH, (uint32_t)src.lane_off, soff);
-      soff += step;
-    }
-  } else {
-    const int h = lane >> 5, cl = lane & (GROUP - 1);
-#pragma unroll
-    for (int k = 0; k < GROUP; ++k) {
-      const int row = 2 * k + h;
-      const int c = GROUP * q + cl - row;
-      const bool ok = row < src.rows && (unsigned)c < (unsigned)src.m;
-      s_to_lds(src, dst + k * PAIR_PITCH, ok ? (uint32_t)(row * src.m + c) * 4u : S_OOB, 0);
-      if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);   // bound the live offsets
-    }
-  }
-}
+#undef NWM_S_LOAD_NEXT4
+#undef NWM_S_LOAD_NEXT
 
 struct StripState {
   float H, diag, pw, col;
@@ -287,8 +280,8 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     st.pw = 0.0f;
 
     // S ring prologue: groups 0 and 1 in flight
-    load_group(ring, src, 0, lane);
-    load_group(ring, src, 1, lane);
+    load_group(ring, src, 0);
+    load_group(ring, src, 1);
 
     // Boundary window prev[tw + 1 + lane]: the first row, or the previous
     // strip's last row published by another wave.  Every published value is
@@ -405,7 +398,7 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
       // every ring read of this group has returned (lgkmcnt(0)) before its
       // half is refilled with the group after next
       __builtin_amdgcn_s_waitcnt(0xc07f);
-      load_group(ring, src, t0 / GROUP + 2, lane);
+      load_group(ring, src, t0 / GROUP + 2);
       first = false;
     }
     if (t0 < T_pad && !failed) {   // a last single chunk
