@@ -439,6 +439,37 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
     if (is_long[b]) p->n_items_long = (int)it_pair.size();
     if (is_top[b]) p->n_items_top = (int)it_pair.size();
   }
+  // Queue order inside each launch (top pairs, other long pairs, the rest):
+  // by the latest step at which a strip can start without lengthening the
+  // longest chain, max_chain - chain(pair) + STRIP_LAG * strip.  A strip can
+  // start about STRIP_LAG steps after the one above it; popping a pair's
+  // strips one after another instead would leave most of them waiting for
+  // their predecessors while holding a wave (on 256 pairs of 5000 x 5000
+  // sentences about half of all wave time).  Strips of one pair keep their
+  // order (a strip's predecessor is always popped first), and among equal
+  // keys the pair order above (longest chain first) is kept.
+  {
+    const size_t N = it_pair.size();
+    std::vector<int64_t> key(N);
+    for (size_t k = 0; k < N; ++k)
+      key[k] = (p->max_chain - p->it_chain[k]) + (int64_t)STRIP_LAG * p->it_strip[k];
+    const size_t cut[4] = {0, (size_t)p->n_items_top, (size_t)p->n_items_long, N};
+    std::vector<size_t> idx(N);
+    std::iota(idx.begin(), idx.end(), (size_t)0);
+    for (int r = 0; r < 3; ++r)
+      std::stable_sort(idx.begin() + cut[r], idx.begin() + cut[r + 1],
+                       [&](size_t a, size_t c) { return key[a] < key[c]; });
+    std::vector<int32_t> ip(N), is(N);
+    std::vector<int64_t> ic(N);
+    for (size_t k = 0; k < N; ++k) {
+      ip[k] = it_pair[idx[k]];
+      is[k] = p->it_strip[idx[k]];
+      ic[k] = p->it_chain[idx[k]];
+    }
+    it_pair.swap(ip);
+    p->it_strip.swap(is);
+    p->it_chain.swap(ic);
+  }
   hot_flags(p, it_strip);
   // ---- device metadata: one allocation -----------------------------------------
   struct Piece {

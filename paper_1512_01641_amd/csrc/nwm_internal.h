@@ -47,6 +47,10 @@ constexpr int FILL_SINK_WAVES = 1024;
 constexpr int64_t FILL_SINK_SLOTS = (int64_t)FILL_SINK_WAVES * 16 + 16;   // uint64 entries, incl. alignment slack
 constexpr int MAX_M = 1 << 22;           // target sentences per pair (a 64-row strip of S stays below 1 GiB)
 constexpr int32_t ITEM_HOT = 1 << 30;   // DP item flag: strip of a critical-chain pair
+// Steps a strip trails the strip above it (the 63-step skew of a 64-row
+// strip, a 16-step publish chunk, the two-chunk window prefetch and the
+// hand-off's memory round trip): the queue order spaces a pair's strips by it.
+constexpr int STRIP_LAG = 128;
 // Pairs whose DP dependency chain is at least this percent of the longest are
 // the "long" pairs: prepared, scored and aligned ahead of the others.
 constexpr int LONG_CHAIN_PERCENT = 15;
@@ -100,7 +104,7 @@ struct PlanDev {
   int n_gt;
   const int32_t *gt_rt, *gt_ct;
   const GtMeta *gt_meta;
-  // DP order (longest first) and DP work items (pair, strip), longest pair first
+  // DP order (longest first) and DP work items (pair, strip) in queue order
   const int32_t *dp_order;
   const int64_t *sent_ids;   // [sum n] source sentences, long pairs' first
   int n_items;
