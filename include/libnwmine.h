@@ -290,6 +290,17 @@ nwm_status nwm_union_kept(const nwm_plan *plan, const int32_t *kept_fwd, const i
  *                                 pair taller than one strip publishes nothing,
  *                                 so the strips below it give up (exercises the
  *                                 failure report of nwm_align_check); default 0
+ *   NWM_PARAM_SCORE_KGROUP        K width of one round of the compacted
+ *                                 contraction: 1 = one 32-word chunk per round,
+ *                                 2 = two chunks (64 words) scattered before one
+ *                                 barrier; the same sums in the same order, so
+ *                                 the results are identical.  Default 1.
+ *   NWM_PARAM_FILL_STAGING        how the NW fill stages S: 0 = a two-group LDS
+ *                                 ring filled by LDS-direct loads (64 rows x 32
+ *                                 steps per group), 1 = 16 cells per lane in
+ *                                 registers, two 16-step chunks ahead (no LDS:
+ *                                 more waves per compute unit).  The same cells
+ *                                 in the same order: identical results.
  * Out-of-range values give NWM_EINVAL.  Setting DP_HOT_PERCENT uploads the
  * plan's work list (synchronous).  A graph captured by nwm_mine is captured
  * again after any change. */
@@ -301,7 +312,9 @@ typedef enum {
   NWM_PARAM_SCORE_COMPACT = 4,
   NWM_PARAM_DP_SPIN_LIMIT = 5,
   NWM_PARAM_DP_TEST_HOLD = 6,
-  NWM_N_PARAMS = 7
+  NWM_PARAM_SCORE_KGROUP = 7,
+  NWM_PARAM_FILL_STAGING = 8,
+  NWM_N_PARAMS = 9
 } nwm_param;
 nwm_status nwm_plan_set_param(nwm_plan *plan, nwm_param param, int32_t value);
 nwm_status nwm_plan_get_param(const nwm_plan *plan, nwm_param param, int32_t *value);

@@ -143,13 +143,8 @@ struct StripState {
 // that is not -0 never produce either (H starts at +0 or i*gap != 0, and a
 // sum is -0 only when both terms are).  A gap of -0 takes the compare chain.
 template <bool MASKED, bool MAX3>
-static __device__ __forceinline__ void run16(StripState &st, const float *ring, int t0, int m, float g,
-                                             int lane) {
-  float4 sv[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    sv[q] = *reinterpret_cast<const float4 *>(ring + ((t0 >> 5) & 1) * HALF + (lane >> 1) * PAIR_PITCH +
-                                               (lane & 1) * 32 + (t0 & 31) + 4 * q);
+static __device__ __forceinline__ void run16v(StripState &st, const float4 (&sv)[4], int t0, int m, float g,
+                                              int lane) {
   float H = st.H, diag = st.diag, pw = st.pw, col = st.col;
   uint32_t bits = 0;
   int d = t0 - lane;   // column - 1 of this lane at the current step
@@ -201,6 +196,18 @@ static __device__ __forceinline__ void run16(StripState &st, const float *ring, 
   st.pw = pw;
   st.col = col;
   st.bits = bits;
+}
+
+// The 16 S values of lane `lane` for the steps [t0, t0 + 16) from the LDS ring.
+template <bool MASKED, bool MAX3>
+static __device__ __forceinline__ void run16(StripState &st, const float *ring, int t0, int m, float g,
+                                             int lane) {
+  float4 sv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    sv[q] = *reinterpret_cast<const float4 *>(ring + ((t0 >> 5) & 1) * HALF + (lane >> 1) * PAIR_PITCH +
+                                               (lane & 1) * 32 + (t0 & 31) + 4 * q);
+  run16v<MASKED, MAX3>(st, sv, t0, m, g, lane);
 }
 
 struct FillArgs {
@@ -424,6 +431,148 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
   }
 }
 
+// ---- the fill with S staged in registers -----------------------------------------
+// The same strip sweep, the same cells, hand-off and publication as k_nw_fill,
+// with every memory access an ordinary compiler-tracked load or store: no LDS
+// ring and no hand-counted waits.  Lane r loads the 16 cells of its row that
+// a 16-step chunk uses (four 16-byte buffer loads of consecutive columns: the
+// cell of step t is (r, t - r), byte 4 (r (m - 1) + t) of the strip) two
+// chunks ahead into one of three register sets; lanes 0..15 load that chunk's
+// boundary window the same way (agent-coherent 8-byte loads).  A cell outside
+// the strip's columns reads another cell of the strip, or 0 past its end (the
+// buffer range check): only masked steps see it.  Without the 17 KiB ring a
+// wave needs registers only, so more waves fit on a compute unit.
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+
+static __device__ __forceinline__ void load_s16(float4 (&d)[4], __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const u32x4v v = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16u * q, 0, 0);
+    d[q] = make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
+  }
+}
+
+template <bool MAX3>
+__global__ __launch_bounds__(64) void k_nw_fill_r(FillArgs A, const float *__restrict__ S, float g,
+                                                  float *__restrict__ score, char *__restrict__ tb,
+                                                  uint64_t *__restrict__ bnd, uint64_t *__restrict__ sink,
+                                                  int32_t *__restrict__ head, int32_t *__restrict__ err) {
+  constexpr uint32_t epoch = 1u;   // tag of a published value (the reset clears to 0)
+  const int lane = threadIdx.x;
+  uint64_t *my_sink = sink + (int64_t)(blockIdx.x & (FILL_SINK_WAVES - 1)) * 16;   // this wave's line
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = atomicAdd(head, 1);
+    item = uniform(item);
+    if (item >= A.n_items) break;
+    item += A.item0;
+    const int b = uniform(A.it_pair[item]);
+    const int s_tag = uniform(A.it_strip[item]);
+    const int s = s_tag & ~ITEM_HOT;
+    const bool hot = (s_tag & ITEM_HOT) != 0;
+    if (hot) __builtin_amdgcn_s_setprio(2);
+    const int n = uniform(A.n[b]), m = uniform(A.m[b]);
+    const int nstrips = (n + 63) >> 6;
+    const bool last = s == nstrips - 1;
+    const int i0 = 64 * s;
+    const int rows = min(64, n - i0);
+    const float *Sb = S + A.s_off[b];
+    const int64_t mstride = bnd_stride(m);
+    const uint64_t *in_row = bnd + A.bnd_off[b] + (int64_t)(s - 1) * mstride;   // used when s > 0
+    uint64_t *out_row = bnd + A.bnd_off[b] + (int64_t)s * mstride;               // used when !last
+    const int nG = (m + 63 + 63) >> 6;
+    uint32_t *tbw = reinterpret_cast<uint32_t *>(reinterpret_cast<uint4 *>(tb + A.tb_off[b]) + (int64_t)s * nG * 64);
+    const int T_end = m + rows - 1;
+    const int T_pad = (T_end + 15) & ~15;
+    const int r_last = n - 1 - i0;   // lane of row n in the last strip
+    bool failed = false;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)uniform_ptr(Sb + (int64_t)i0 * m), (short)0, uniform(rows * m * 4), 0x00020000);
+    const uint32_t lo = (uint32_t)lane * (uint32_t)(m - 1) * 4u;
+
+    StripState st;
+    const int i = i0 + 1 + lane;
+    st.H = (float)i * g;                                    // H[i][0]
+    st.diag = (i0 == 0) ? 0.0f : (float)i0 * g;             // lane 0: H[i0][0]
+    st.col = 0.0f;
+    st.bits = 0u;
+    st.pw = 0.0f;
+
+    // the row above: lanes 0..15 hold slots tw + 1 .. tw + 16 (see k_nw_fill)
+    auto wload = [&](int tw) -> uint64_t {
+      return (s > 0 && lane < 16)
+                 ? __hip_atomic_load(in_row + tw + 1 + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                 : 0ull;
+    };
+    auto window_need = [&](int tw) -> bool { return lane < 16 && tw + 1 + lane <= m; };
+    auto wait_window = [&](int tw, uint64_t v) -> uint64_t {
+      int spins = 0;
+      for (;;) {
+        const uint32_t tag = (uint32_t)(v >> 32);
+        if (__ballot(window_need(tw) && tag == TAG_FAIL) != 0) {
+          failed = true;
+          break;
+        }
+        if (__ballot(window_need(tw) && tag != epoch) == 0) break;
+        if (++spins > A.spin_limit) {
+          failed = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        v = wload(tw);
+      }
+      return v;
+    };
+
+    float4 SA[4], SB[4], SC[4];
+    load_s16(SA, rs, lo);
+    uint64_t WA = wload(0);
+    load_s16(SB, rs, lo + 64u);
+    uint64_t WB = wload(16), WC = 0ull;
+    int t0 = 0;
+    // one 16-step chunk from register set CUR while chunk t0 + 32 loads into NXT
+#define NWM_FILL_RCHUNK(CUR, WCUR, NXT, WNXT)                                                       \
+  {                                                                                                \
+    if (t0 >= T_pad) break;                                                                        \
+    load_s16(NXT, rs, lo + 4u * (uint32_t)(t0 + 32));                                              \
+    WNXT = wload(t0 + 32);                                                                         \
+    uint64_t win = WCUR;                                                                           \
+    if (s > 0 && __ballot(window_need(t0) && (uint32_t)(win >> 32) != epoch) != 0) {               \
+      win = wait_window(t0, win);                                                                  \
+      if (failed) break;                                                                           \
+    }                                                                                              \
+    st.pw = s > 0 ? __uint_as_float((uint32_t)win) : (float)(t0 + 1 + lane) * g;                  \
+    if (t0 < 64 || t0 + 16 > m) run16v<true, MAX3>(st, CUR, t0, m, g, lane);                      \
+    else run16v<false, MAX3>(st, CUR, t0, m, g, lane);                                             \
+    {                                                                                              \
+      const int j = t0 - 110 + lane;                                                               \
+      const bool pub = !last && lane >= 48 && j >= 1 && j <= m && !(A.hold && s == 0);             \
+      uint64_t *dst = pub ? out_row + j : my_sink + (lane & 15);                                   \
+      __hip_atomic_store(dst, ((uint64_t)epoch << 32) | __float_as_uint(st.col), __ATOMIC_RELAXED,  \
+                         __HIP_MEMORY_SCOPE_AGENT);                                                \
+    }                                                                                              \
+    tbw[((t0 >> 6) * 64 + lane) * 4 + ((t0 >> 4) & 3)] = st.bits;                                  \
+    t0 += 16;                                                                                      \
+  }
+    for (;;) {
+      NWM_FILL_RCHUNK(SA, WA, SC, WC)
+      NWM_FILL_RCHUNK(SB, WB, SA, WA)
+      NWM_FILL_RCHUNK(SC, WC, SB, WB)
+    }
+#undef NWM_FILL_RCHUNK
+    if (last) {
+      // lane r_last stopped updating after column m: it holds H[n][m]
+      const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(st.H), r_last));
+      if (lane == 0) score[b] = failed ? __builtin_nanf("") : v;
+    } else if (failed) {
+      for (int j = 1 + lane; j <= m; j += 64)
+        __hip_atomic_store(out_row + j, (uint64_t)TAG_FAIL << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (failed && lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (hot) __builtin_amdgcn_s_setprio(0);
+  }
+}
+
 constexpr int WALK_LDS = 4096;   // path cells buffered in LDS per pair before a flush
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -602,18 +751,24 @@ __global__ __launch_bounds__(64) void k_keep(PlanDev P, const float *__restrict_
   if (lane == 0) n_kept[b] = nk;
 }
 
-static int g_fill_cus = 0, g_fill_per = 0;   // compute units, resident fill waves per unit
+// compute units; resident fill waves per unit for the LDS-ring and the
+// register staging
+static int g_fill_cus = 0, g_fill_per = 0, g_fill_per_r = 0;
 
 hipError_t fill_set_attrs(int) {
   if (g_fill_cus == 0) {
-    int dev = 0, cus = 0, per = 0, per3 = 0;
+    int dev = 0, cus = 0, per = 0, per3 = 0, pr = 0, pr3 = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_nw_fill<false>, 64, 0);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per3, k_nw_fill<true>, 64, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pr, k_nw_fill_r<false>, 64, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pr3, k_nw_fill_r<true>, 64, 0);
     if (e != hipSuccess) return e;
     per = per < per3 ? per : per3;   // either variant's grid is resident at once
+    pr = pr < pr3 ? pr : pr3;
     g_fill_per = per > 0 ? per : 1;
+    g_fill_per_r = pr > 0 ? pr : 1;
     g_fill_cus = cus > 0 ? cus : 1;
   }
   return hipSuccess;
@@ -651,7 +806,7 @@ hipError_t launch_nw_reset(const PlanDev &P, float g, float *score, uint64_t *bn
 // (cleared by the reset).  Strips of one pair must all be in one launch.
 hipError_t launch_nw_fill_items(const PlanDev &P, const float *S, float g, float *score, char *tb, uint64_t *bnd,
                                 int64_t n_bnd, int32_t *head, int32_t *err, int item0, int n, int waves_per_cu,
-                                int spin_limit, int hold, hipStream_t st) {
+                                int spin_limit, int hold, int staging, hipStream_t st) {
   if (P.B <= 0 || n <= 0) return hipSuccess;
   if (g_fill_cus == 0) {
     hipError_t e = fill_set_attrs(0);
@@ -664,25 +819,35 @@ hipError_t launch_nw_fill_items(const PlanDev &P, const float *S, float g, float
   A.hold = hold;
   // every wave of the grid is resident at once (the hand-off between strips
   // waits on other waves), so the grid never exceeds the occupancy
-  const int per = (waves_per_cu > 0 && waves_per_cu < g_fill_per) ? waves_per_cu : g_fill_per;
+  const int fit = staging ? g_fill_per_r : g_fill_per;
+  const int per = (waves_per_cu > 0 && waves_per_cu < fit) ? waves_per_cu : fit;
   const int full = g_fill_cus * per;
   const int grid = n < full ? n : full;
   // the sink: FILL_SINK_WAVES 128-byte lines after the published rows
   uint64_t *sink = reinterpret_cast<uint64_t *>((reinterpret_cast<uintptr_t>(bnd + n_bnd) + 127) & ~(uintptr_t)127);
-  // a gap of -0 keeps the compare chain (see run16)
-  if (g == 0.0f && std::signbit(g))
-    hipLaunchKernelGGL(k_nw_fill<false>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, sink, head, err);
-  else
-    hipLaunchKernelGGL(k_nw_fill<true>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, sink, head, err);
+  // a gap of -0 keeps the compare chain (see run16v)
+  const bool max3 = !(g == 0.0f && std::signbit(g));
+  if (staging) {
+    if (max3)
+      hipLaunchKernelGGL(k_nw_fill_r<true>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, sink, head, err);
+    else
+      hipLaunchKernelGGL(k_nw_fill_r<false>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, sink, head, err);
+  } else {
+    if (max3)
+      hipLaunchKernelGGL(k_nw_fill<true>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, sink, head, err);
+    else
+      hipLaunchKernelGGL(k_nw_fill<false>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, sink, head, err);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *score, char *tb, uint64_t *bnd,
-                          int64_t n_bnd, int32_t *ctl, int waves_per_cu, int spin_limit, int hold, hipStream_t st) {
+                          int64_t n_bnd, int32_t *ctl, int waves_per_cu, int spin_limit, int hold, int staging,
+                          hipStream_t st) {
   hipError_t e = launch_nw_reset(P, g, score, bnd, n_bnd, ctl, st);
   if (e != hipSuccess) return e;
   return launch_nw_fill_items(P, S, g, score, tb, bnd, n_bnd, ctl, ctl + 1, 0, P.n_items, waves_per_cu, spin_limit,
-                              hold, st);
+                              hold, staging, st);
 }
 
 // pairs dp_order[o0 .. o0 + n)

@@ -508,10 +508,12 @@ struct CWin {
   int a0, a1, b0, b1;
 };
 
-template <bool BF16>
+// LDS of the compacted contraction: KG tile pairs [A, B] (KG compacted
+// chunks scattered per round).
+template <bool BF16, int KG>
 struct ScoreLdsC {
-  static constexpr int OPS = 2 * ScoreLds<BF16>::TILE;   // [A, B]
-  static constexpr int BYTES = OPS;
+  static constexpr int OPS = 2 * ScoreLds<BF16>::TILE;   // one [A, B] pair
+  static constexpr int BYTES = KG * OPS;
 };
 
 static __device__ __forceinline__ void cwin_load(CWin &W, int base, int Kc, const int2 *rng,
@@ -586,7 +588,13 @@ static __device__ __forceinline__ void cscatter(const CChunk &C, char *At, char 
   for (int e = CREG_B * 64 + lane; e < C.nb; e += 64) lds_put<T>(Bt, pb[C.b0 + e], T(1.0f));
 }
 
-template <bool BF16>
+// KG: compacted chunks per round (the K width of a round is 32 KG words).
+// With KG = 2 both chunks of a round are scattered into their own tile pair
+// before one wave barrier, then the MFMAs of the first and of the second run:
+// every accumulator sums the chunks in the same order as with KG = 1, so the
+// results are identical; the round's fixed costs (barrier, waits, loop) are
+// shared by two chunks at the price of a fourth register set.
+template <bool BF16, int KG>
 __global__ __launch_bounds__(64) void k_score_c(PlanDev P, const int64_t *__restrict__ src_off,
                                                 const int64_t *__restrict__ tgt_off,
                                                 const uint2 *__restrict__ a_list, const int32_t *__restrict__ a_choff,
@@ -598,8 +606,8 @@ __global__ __launch_bounds__(64) void k_score_c(PlanDev P, const int64_t *__rest
                                                 float *__restrict__ S, float *__restrict__ S_raw, int xcd_map,
                                                 int g0, int G) {
   constexpr int TB = ScoreLds<BF16>::TILE;
-  __shared__ __align__(16) char smem[ScoreLdsC<BF16>::BYTES];   // [A tile, B tile]
-  extern __shared__ __align__(16) uint2 dyn[];                  // chunk table [nch]
+  __shared__ __align__(16) char smem[ScoreLdsC<BF16, KG>::BYTES];   // KG x [A tile, B tile]
+  extern __shared__ __align__(16) uint2 dyn[];                      // chunk table [nch]
   char *At = smem, *Bt = smem + TB;
 
   // tiles [g0, g0 + G) of the plan
@@ -630,7 +638,7 @@ __global__ __launch_bounds__(64) void k_score_c(PlanDev P, const int64_t *__rest
   cwin_load(W, 0, Kc, rng, chA, chB, lane);
   cload(X, pa, pb, W, 0, lane);
   cload(Y, pa, pb, W, 1, lane);
-  for (int e = lane; e < ScoreLdsC<BF16>::OPS / 16; e += 64)
+  for (int e = lane; e < ScoreLdsC<BF16, KG>::BYTES / 16; e += 64)
     reinterpret_cast<uint4 *>(smem)[e] = make_uint4(0u, 0u, 0u, 0u);
   for (int c = lane; c < nch; c += 64) mtl[c] = mtg[c];
   wave_sync();
@@ -644,8 +652,8 @@ __global__ __launch_bounds__(64) void k_score_c(PlanDev P, const int64_t *__rest
   // padding element (row 0, column KC) no fragment reads: where lanes with
   // nothing to write go, all to one address
   const uint32_t junk = (uint32_t)(KC * (int)sizeof(typename Op<BF16>::T));
-  constexpr int NCLR = ScoreLdsC<BF16>::OPS / 16 / 64;
-  static_assert(ScoreLdsC<BF16>::OPS % (16 * 64) == 0, "tile clear");
+  constexpr int NCLR = ScoreLdsC<BF16, KG>::OPS / 16 / 64;   // per tile pair
+  static_assert(ScoreLdsC<BF16, KG>::OPS % (16 * 64) == 0, "tile clear");
   Frags<BF16> F;
 
   // chunk kc from register set Cur while the chunk after next (of the same
@@ -663,21 +671,64 @@ __global__ __launch_bounds__(64) void k_score_c(PlanDev P, const int64_t *__rest
   }
   // windows of 64 compacted chunks (one almost always covers the tile); the
   // loads past the window's last chunk read an empty range
-  for (int wb = 0; wb < Kc; wb += 64) {
-    if (wb > 0) {
-      cwin_load(W, wb, Kc, rng, chA, chB, lane);
-      cload(X, pa, pb, W, wb, lane);
-      cload(Y, pa, pb, W, wb + 1, lane);
+  if constexpr (KG == 1) {
+    for (int wb = 0; wb < Kc; wb += 64) {
+      if (wb > 0) {
+        cwin_load(W, wb, Kc, rng, chA, chB, lane);
+        cload(X, pa, pb, W, wb, lane);
+        cload(Y, pa, pb, W, wb + 1, lane);
+      }
+      const int we = min(Kc, wb + 64) - wb;   // chunks in this window
+      int k = 0;
+      for (; k + 3 <= we; k += 3) {
+        NWM_SCORE_CCHUNK(wb + k, X, Z)
+        NWM_SCORE_CCHUNK(wb + k + 1, Y, X)
+        NWM_SCORE_CCHUNK(wb + k + 2, Z, Y)
+      }
+      if (k < we) NWM_SCORE_CCHUNK(wb + k, X, Z)
+      if (k + 1 < we) NWM_SCORE_CCHUNK(wb + k + 1, Y, X)
     }
-    const int we = min(Kc, wb + 64) - wb;   // chunks in this window
-    int k = 0;
-    for (; k + 3 <= we; k += 3) {
-      NWM_SCORE_CCHUNK(wb + k, X, Z)
-      NWM_SCORE_CCHUNK(wb + k + 1, Y, X)
-      NWM_SCORE_CCHUNK(wb + k + 2, Z, Y)
+  } else {
+    // rounds of chunks (kc, kc + 1) from sets (C0, C1) while (kc + 2, kc + 3)
+    // load into (N0, N1); the second tile pair follows the first in LDS.  A
+    // round whose second chunk is past the window's end skips its MFMAs (its
+    // tiles stay zero).
+    char *At1 = smem + 2 * TB, *Bt1 = smem + 3 * TB;
+    CChunk X1 = Y, Y0, Y1;
+#define NWM_SCORE_CROUND(kc, C0, C1, N0, N1, has2)                                     \
+  {                                                                                    \
+    cload(N0, pa, pb, W, (kc) + 2, lane);                                              \
+    cload(N1, pa, pb, W, (kc) + 3, lane);                                              \
+    cscatter<BF16>(C0, At, Bt, mtl, pa, pb, (kc), lane, junk);                         \
+    cscatter<BF16>(C1, At1, Bt1, mtl, pa, pb, (kc) + 1, lane, junk);                   \
+    wave_sync();                                                                       \
+    read_frags<BF16>(F, At, Bt, lane);                                                 \
+    _Pragma("unroll") for (int e_ = 0; e_ < NCLR; ++e_)                                \
+      reinterpret_cast<uint4 *>(smem)[e_ * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);    \
+    mfma_frags<BF16>(F, acc);                                                          \
+    if (has2) {                                                                        \
+      read_frags<BF16>(F, At1, Bt1, lane);                                             \
+      _Pragma("unroll") for (int e_ = 0; e_ < NCLR; ++e_)                              \
+        reinterpret_cast<uint4 *>(smem + 2 * TB)[e_ * 64 + lane] = make_uint4(0u, 0u, 0u, 0u); \
+      mfma_frags<BF16>(F, acc);                                                        \
+    }                                                                                  \
+  }
+    for (int wb = 0; wb < Kc; wb += 64) {
+      if (wb > 0) {
+        cwin_load(W, wb, Kc, rng, chA, chB, lane);
+        cload(X, pa, pb, W, wb, lane);
+        cload(X1, pa, pb, W, wb + 1, lane);
+      }
+      const int we = min(Kc, wb + 64) - wb;   // chunks in this window
+      int k = 0;
+      for (; k + 4 <= we; k += 4) {
+        NWM_SCORE_CROUND(wb + k, X, X1, Y0, Y1, true)
+        NWM_SCORE_CROUND(wb + k + 2, Y0, Y1, X, X1, true)
+      }
+      if (k < we) NWM_SCORE_CROUND(wb + k, X, X1, Y0, Y1, k + 1 < we)
+      if (k + 2 < we) NWM_SCORE_CROUND(wb + k + 2, Y0, Y1, X, X1, k + 3 < we)
     }
-    if (k < we) NWM_SCORE_CCHUNK(wb + k, X, Z)
-    if (k + 1 < we) NWM_SCORE_CCHUNK(wb + k + 1, Y, X)
+#undef NWM_SCORE_CROUND
   }
 #undef NWM_SCORE_CCHUNK
   score_epilogue_regs(acc, src_off, tgt_off, sc, S + g.s_off, S_raw ? S_raw + g.s_off : nullptr, g.row0, g.rows,
@@ -691,18 +742,23 @@ size_t score_lds_bytes(int, bool bf16) {
 hipError_t launch_score(const PlanDev &P, bool bf16, const int64_t *src_off, const int64_t *tgt_off,
                         const uint2 *a_list, const int32_t *a_choff, const uint32_t *b_list,
                         const int32_t *b_choff, nwm_scorer sc, float *S, float *S_raw, int xcd_map, int compact,
-                        const uint2 *mt, const int32_t *kcn, const int2 *krng, const int64_t *a_base,
+                        int kgroup, const uint2 *mt, const int32_t *kcn, const int2 *krng, const int64_t *a_base,
                         const int64_t *b_base, int g0, int G, hipStream_t st) {
   if (G <= 0) return hipSuccess;
   const int grid = xcd_map ? 8 * ((G + 7) / 8) : G;
   if (compact) {
     const size_t dyn = sizeof(uint2) * (size_t)P.nch;
-    if (bf16)
-      hipLaunchKernelGGL(k_score_c<true>, dim3(grid), dim3(64), dyn, st, P, src_off, tgt_off, a_list, a_choff,
-                         b_list, b_choff, mt, kcn, krng, a_base, b_base, sc, S, S_raw, xcd_map, g0, G);
-    else
-      hipLaunchKernelGGL(k_score_c<false>, dim3(grid), dim3(64), dyn, st, P, src_off, tgt_off, a_list, a_choff,
-                         b_list, b_choff, mt, kcn, krng, a_base, b_base, sc, S, S_raw, xcd_map, g0, G);
+#define NWM_LAUNCH_C(B_, K_)                                                                              \
+  hipLaunchKernelGGL((k_score_c<B_, K_>), dim3(grid), dim3(64), dyn, st, P, src_off, tgt_off, a_list, a_choff, \
+                     b_list, b_choff, mt, kcn, krng, a_base, b_base, sc, S, S_raw, xcd_map, g0, G)
+    if (bf16) {
+      if (kgroup == 2) NWM_LAUNCH_C(true, 2);
+      else NWM_LAUNCH_C(true, 1);
+    } else {
+      if (kgroup == 2) NWM_LAUNCH_C(false, 2);
+      else NWM_LAUNCH_C(false, 1);
+    }
+#undef NWM_LAUNCH_C
     return hipGetLastError();
   }
   if (bf16)

@@ -25,16 +25,16 @@ hipError_t launch_build_b(const PlanDev &, const int64_t *, const int32_t *, uin
 hipError_t launch_clear_u32(uint32_t *, int64_t, hipStream_t);
 hipError_t build_set_attrs(int nch, int V);
 hipError_t launch_score(const PlanDev &, bool, const int64_t *, const int64_t *, const uint2 *, const int32_t *,
-                        const uint32_t *, const int32_t *, nwm_scorer, float *, float *, int, int, const uint2 *,
+                        const uint32_t *, const int32_t *, nwm_scorer, float *, float *, int, int, int, const uint2 *,
                         const int32_t *, const int2 *, const int64_t *, const int64_t *, int, int, hipStream_t);
 size_t score_lds_bytes(int nch, bool bf16);
 hipError_t score_set_attrs(int nch_max);
 hipError_t launch_nw_fill(const PlanDev &, const float *, float, float *, char *, uint64_t *, int64_t, int32_t *,
-                          int, int, int, hipStream_t);
+                          int, int, int, int, hipStream_t);
 hipError_t fill_set_attrs(int);
 hipError_t launch_nw_reset(const PlanDev &, float, float *, uint64_t *, int64_t, int32_t *, hipStream_t);
 hipError_t launch_nw_fill_items(const PlanDev &, const float *, float, float *, char *, uint64_t *, int64_t,
-                                int32_t *, int32_t *, int, int, int, int, int, hipStream_t);
+                                int32_t *, int32_t *, int, int, int, int, int, int, hipStream_t);
 hipError_t launch_nw_walk(const PlanDev &, const char *, const float *, int2 *, int32_t *, int, int, hipStream_t);
 hipError_t launch_keep(const PlanDev &, const float *, float, const int2 *, const int32_t *, int2 *, int32_t *, int,
                        int, hipStream_t);
@@ -137,7 +137,7 @@ struct nwm_plan {
   int64_t n_bnd = 0;   // uint64 entries of the published-row region
   int max_entries = 1; // dictionary entries of the longest source sentence (tokens x max_deg)
   // launch parameters (nwm_param) and what re-deriving the DP priority flags needs
-  int32_t param[NWM_N_PARAMS] = {0, 0, 1, 50, 1, 0, 0};
+  int32_t param[NWM_N_PARAMS] = {0, 0, 1, 50, 1, 0, 0, 1, 0};
   uint64_t param_version = 0;
   std::vector<int32_t> it_strip;   // strip index per DP item (no flags)
   std::vector<int64_t> it_chain;   // dependency chain of the item's pair
@@ -718,7 +718,8 @@ static hipError_t score_tiles(nwm_plan *p, const nwm_batch *batch, nwm_scorer sc
   hipError_t e = launch_score(p->dev, p->prec == NWM_BF16, batch->src_off, batch->tgt_off, (uint2 *)(w + p->ws.a_list),
                               (int32_t *)(w + p->ws.a_choff), (uint32_t *)(w + p->ws.b_list),
                               (int32_t *)(w + p->ws.b_choff), sc, S, S_raw, p->param[NWM_PARAM_SCORE_XCD_MAP],
-                              p->param[NWM_PARAM_SCORE_COMPACT], (uint2 *)(w + p->ws.b_mt),
+                              p->param[NWM_PARAM_SCORE_COMPACT], p->param[NWM_PARAM_SCORE_KGROUP],
+                              (uint2 *)(w + p->ws.b_mt),
                               (int32_t *)(w + p->ws.b_kcn), (int2 *)(w + p->ws.b_rng), (int64_t *)(w + p->ws.a_base),
                               (int64_t *)(w + p->ws.b_base), g0, G, st);
   mk.done();
@@ -773,7 +774,8 @@ nwm_status nwm_align_batch(nwm_plan *p, const float *S, float gap, float thresho
     Mark mk(p, K_FILL, st);
     e = launch_nw_fill(p->dev, S, gap, score, tbc, (uint64_t *)(w + p->ws.bnd), p->n_bnd,
                        (int32_t *)(w + p->ws.ctl), p->param[NWM_PARAM_FILL_WAVES_PER_CU],
-                       p->param[NWM_PARAM_DP_SPIN_LIMIT], p->param[NWM_PARAM_DP_TEST_HOLD], st);
+                       p->param[NWM_PARAM_DP_SPIN_LIMIT], p->param[NWM_PARAM_DP_TEST_HOLD],
+                       p->param[NWM_PARAM_FILL_STAGING], st);
     mk.done();
   }
   if (e != hipSuccess) return dev_err(e);
@@ -827,7 +829,8 @@ nwm_status nwm_align_batch_noalloc(nwm_plan *p, const float *S, float gap, float
   // the reset kernel clears the queue heads, the error flag and the published
   // rows' tags left by the previous call (no memset node, no allocation)
   hipError_t e = launch_nw_fill(p->dev, S, gap, score, tbc, bnd, p->n_bnd, ctl, p->param[NWM_PARAM_FILL_WAVES_PER_CU],
-                                p->param[NWM_PARAM_DP_SPIN_LIMIT], p->param[NWM_PARAM_DP_TEST_HOLD], st);
+                                p->param[NWM_PARAM_DP_SPIN_LIMIT], p->param[NWM_PARAM_DP_TEST_HOLD],
+                                p->param[NWM_PARAM_FILL_STAGING], st);
   if (e == hipSuccess) e = launch_nw_walk(p->dev, tbc, score, path, n_diag, 0, p->B, st);
   if (e == hipSuccess) e = launch_keep(p->dev, S, threshold, path, n_diag, (int2 *)kept, n_kept, 0, p->B, st);
   return dev_err(e);
@@ -879,6 +882,12 @@ nwm_status nwm_plan_set_param(nwm_plan *p, nwm_param param, int32_t value) {
       if (value < 0 || value > (1 << 30)) return NWM_EINVAL;
       break;
     case NWM_PARAM_DP_TEST_HOLD:
+      if (value != 0 && value != 1) return NWM_EINVAL;
+      break;
+    case NWM_PARAM_SCORE_KGROUP:
+      if (value != 1 && value != 2) return NWM_EINVAL;
+      break;
+    case NWM_PARAM_FILL_STAGING:
       if (value != 0 && value != 1) return NWM_EINVAL;
       break;
     default:
@@ -949,6 +958,7 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
   int32_t *ctl = (int32_t *)(w + p->ws.ctl);
   const int wpc = p->param[NWM_PARAM_FILL_WAVES_PER_CU];
   const int spin = p->param[NWM_PARAM_DP_SPIN_LIMIT], hold = p->param[NWM_PARAM_DP_TEST_HOLD];
+  const int stg = p->param[NWM_PARAM_FILL_STAGING];
   const PlanDev &D = p->dev;
   const bool scored = p->sizes.S_elems > 0;
   const int gl = p->n_gt_long, il = p->n_items_long, ol = p->n_pairs_long;
@@ -992,7 +1002,7 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
       if (e == hipSuccess) e = hipStreamWaitEvent(lane, p->ev_top, 0);
       if (e == hipSuccess)
         e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl + 2, ctl + 1, 0, itop, wpc, spin, hold,
-                                 lane);
+                                 stg, lane);
       if (e == hipSuccess) e = launch_nw_walk(D, tbc, score, path, n_diag, 0, otop, lane);
       if (e == hipSuccess) e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, 0, otop, lane);
       if (e == hipSuccess) e = hipEventRecord(p->ev_top_done, lane);
@@ -1001,7 +1011,7 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
       if (e == hipSuccess) e = hipStreamWaitEvent(aux, p->ev_long, 0);
       if (e == hipSuccess)
         e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl + 3, ctl + 1, itop, il - itop, wpc, spin,
-                                 hold, aux);
+                                 hold, stg, aux);
       if (e == hipSuccess) e = launch_nw_walk(D, tbc, score, path, n_diag, otop, ol - otop, aux);
       if (e == hipSuccess)
         e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, otop, ol - otop, aux);
@@ -1013,7 +1023,7 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
   if (e == hipSuccess && scored) e = score_tiles(p, batch, sc, S, S_raw, ws, gl, D.n_gt - gl, st);
   if (e == hipSuccess)
     e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl, ctl + 1, il, D.n_items - il, wpc, spin, hold,
-                             st);
+                             stg, st);
   if (e == hipSuccess) e = launch_nw_walk(D, tbc, score, path, n_diag, ol, p->B - ol, st);
   if (e == hipSuccess) e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, ol, p->B - ol, st);
   if (e == hipSuccess && ol > 0 && otop > 0) e = hipStreamWaitEvent(st, p->ev_top_done, 0);

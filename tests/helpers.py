@@ -40,8 +40,9 @@ def run_gpu(batch, prec=0, scorer=None, gap=None, threshold=None, device="cuda:0
     return out
 
 
-def gpu_align_only(n, m, S32, gap, threshold, device="cuda:0"):
-    """GPU NW + keep on a given packed S (host FP32)."""
+def gpu_align_only(n, m, S32, gap, threshold, device="cuda:0", params=None):
+    """GPU NW + keep on a given packed S (host FP32).  `params`: launch
+    parameters set on the plan first ({name: value})."""
     import torch
     import paper_1512_01641_amd as nw
     n = np.asarray(n, np.int32)
@@ -52,6 +53,8 @@ def gpu_align_only(n, m, S32, gap, threshold, device="cuda:0"):
     to = np.zeros(int(m.sum()) + 1, np.int64)
     db = nw.DeviceBatch(n, m, so, np.zeros(0, np.int32), to, np.zeros(0, np.int32), 64, device, max_sent_tokens=0)
     plan = nw.Plan(ctx, db, 1, 0)
+    for k, v in (params or {}).items():
+        plan.set_param(k, v)
     dev = torch.device(device)
     S = torch.as_tensor(np.ascontiguousarray(S32, np.float32)).to(dev)
     B = len(n)

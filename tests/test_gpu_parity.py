@@ -96,6 +96,26 @@ def test_dp_empty_sides():
     H.assert_align_equal(gpu, ora, ns, ms)
 
 
+@pytest.mark.parametrize("g", [-0.2, -0.0])
+def test_dp_register_staging_bitexact(g):
+    # the fill with S staged in registers: brute-force sizes, ragged strips
+    # with exact ties, empty sides and tall pairs (hand-offs), bit-exact
+    rng = np.random.default_rng(7)
+    sizes = [(0, 4), (5, 0), (1, 1), (3, 6), (6, 3), (1, 300), (300, 1), (63, 64), (64, 63), (65, 65), (127, 33),
+             (129, 31), (200, 220), (2, 500), (500, 2), (700, 650), (1300, 90)]
+    ns = [a for a, _ in sizes]
+    ms = [b for _, b in sizes]
+    for kind in ("coarse", "fine"):
+        if kind == "coarse":
+            blocks = [(rng.integers(0, 3, n * m) / 2.0).astype(np.float32) for n, m in sizes]
+        else:
+            blocks = [rng.random(n * m).astype(np.float32) for n, m in sizes]
+        S = np.concatenate(blocks)
+        gpu = H.gpu_align_only(ns, ms, S, g, 0.5, params={"fill_staging": 1})
+        ora = oracle.align(ns, ms, S, g, 0.5)
+        H.assert_align_equal(gpu, ora, ns, ms)
+
+
 def test_dp_large_pair_bitexact():
     rng = np.random.default_rng(4)
     ns, ms = [1500, 700], [1300, 2100]
@@ -229,6 +249,21 @@ def test_scores_compacted_and_dense_contraction(compact):
     gpu, ora = _check_scores(w, 0, tol_rel=1e-5, params=p)
     np.testing.assert_allclose(gpu["S_raw"], ora["S_raw"], rtol=1e-5, atol=1e-7)
     _check_scores(w, 1, tol_abs=2e-2, params=p)
+
+
+def test_contraction_k_width_two_chunks_per_round():
+    # the compacted contraction with two 32-word chunks per round: the same
+    # bits as one chunk per round (same summation order) and the oracle bars,
+    # on the ragged batch (odd chunk counts) and the wide-vocabulary batch
+    # (more than 64 compacted chunks: window slide, register overflow)
+    for b in (corpus.make_batch(2, pairs=40), _wide_vocabulary_batch()):
+        for prec in (0, 1):
+            one = H.run_gpu(b, prec=prec, params={"score_kgroup": 1})
+            two, ora = _check_scores(b, prec, tol_rel=1e-5 if prec == 0 else None,
+                                     tol_abs=2e-2 if prec == 1 else None, params={"score_kgroup": 2})
+            np.testing.assert_array_equal(two["S"].view(np.uint32), one["S"].view(np.uint32))
+            np.testing.assert_array_equal(two["S_raw"].view(np.uint32), one["S_raw"].view(np.uint32))
+            H.assert_align_equal(two, oracle.align(b.n, b.m, two["S"], b.gap, b.threshold), b.n, b.m)
 
 
 def test_end_to_end_dp_bitexact_on_gpu_scores():
