@@ -169,7 +169,11 @@ def batched(nw, torch, ctx, batch, prec_name, prec, args, db=None, dd=None):
     mn = nw.Miner(ctx, db, dd, prec)
     w, gap, thr = batch.scorer, batch.gap, batch.threshold
     params = "defaults"
-    if not args.no_autotune:
+    for kv in args.param:
+        k, v = kv.split("=")
+        mn.plan.set_param(k, int(v))
+        params = dict(p.split("=") for p in args.param)
+    if not args.no_autotune and not args.param:
         from paper_1512_01641_amd import autotune
         r = autotune.autotune(mn, w, gap, thr, reps=5, cache_path=TUNED)
         params = dict(r["params"], source="cache" if r["cached"] else "tuned in this run")
@@ -338,6 +342,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
     ap.add_argument("--prec", choices=("both", "bf16", "f32"), default="both")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch parameters")
+    ap.add_argument("--param", action="append", default=[], metavar="NAME=VALUE",
+                    help="set a launch parameter on every plan (implies --no-autotune)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="run a plain device copy of MIB MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()

@@ -77,13 +77,19 @@ def autotune(miner, scorer, gap: float, threshold: float, space=None, reps: int 
     plan = miner.plan
     sig = signature(miner)
     cache = _load(cache_path)
+    todo = dict(space)
     if sig in cache:
         for k, v in cache[sig]["params"].items():
-            plan.set_param(k, v)
-        return {"params": dict(cache[sig]["params"]), "ms": cache[sig]["ms"], "cached": True}
+            if k in space:
+                plan.set_param(k, v)
+        # a cached choice covers the parameters it names; any parameter added
+        # to the search space since is tuned from there
+        todo = {k: v for k, v in space.items() if k not in cache[sig]["params"]}
+        if not todo:
+            return {"params": {k: cache[sig]["params"][k] for k in space}, "ms": cache[sig]["ms"], "cached": True}
     best = {k: plan.get_param(k) for k in space}
     best_ms = time_mine(miner, scorer, gap, threshold, reps, graph=graph)
-    for k, values in space.items():
+    for k, values in todo.items():
         for v in values:
             if v == best[k]:
                 continue
