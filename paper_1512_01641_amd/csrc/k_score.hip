@@ -292,16 +292,19 @@ static __device__ __forceinline__ void score_epilogue(const f32x4 (&acc)[4][4], 
   const int col = lane;
   const bool vcol = col < cols;
   const float lt = vcol ? (float)(tgt_off[t_first + col + 1] - tgt_off[t_first + col]) : 0.0f;
+  const float rlt = __builtin_amdgcn_rcpf(lt);
   float *Sp = S + P.s_off[pair];
   float *Rp = S_raw ? S_raw + P.s_off[pair] : nullptr;
   const float LOG2E = 1.4426950408889634f;
   for (int row = 0; row < rows; ++row) {
     const float dot = red[row * RP + col];
     const float ls = (float)(src_off[s_first + row + 1] - src_off[s_first + row]);
-    // S_raw = dot / l_i (0 for an empty sentence); rho = min / max of lengths
-    const float sraw = ls > 0.0f ? dot * __builtin_amdgcn_rcpf(ls) : 0.0f;
+    const float rls = __builtin_amdgcn_rcpf(ls);
+    // S_raw = dot / l_i (0 for an empty sentence); rho = min / max of lengths,
+    // 1 / max(l_i, l'_j) = min(1 / l_i, 1 / l'_j)
+    const float sraw = ls > 0.0f ? dot * rls : 0.0f;
     const float mx = fmaxf(ls, lt);
-    const float rho = mx > 0.0f ? fminf(ls, lt) * __builtin_amdgcn_rcpf(mx) : 1.0f;
+    const float rho = mx > 0.0f ? fminf(ls, lt) * fminf(rls, rlt) : 1.0f;
     const float z = __builtin_fmaf(sc.w0, sraw, __builtin_fmaf(sc.w1, rho, sc.b));
     // sigmoid in the overflow-free form: e = exp(-|z|), S = 1/(1+e) or e/(1+e)
     const float e = __builtin_amdgcn_exp2f(-fabsf(z) * LOG2E);
@@ -331,21 +334,37 @@ static __device__ __forceinline__ void score_epilogue_regs(const f32x4 (&acc)[4]
   float *Rp = Rb ? Rb + (int64_t)row0 * m + col0 : nullptr;
   const float LOG2E = 1.4426950408889634f;
   const int r16 = lane & 15, rq = lane >> 4;
+  // the lengths of this lane's 16 rows and 4 columns and their reciprocals,
+  // once: 1 / max(l_i, l'_j) = min(1 / l_i, 1 / l'_j) (the reciprocal is
+  // decreasing; 1 / 0 = inf leaves the other), so no reciprocal per cell but
+  // the sigmoid's
+  float ls[4][4], rls[4][4], lt[4], rlt[4];
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      ls[bi][r] = __shfl(my_ls, 16 * bi + 4 * rq + r, 64);
+      rls[bi][r] = __builtin_amdgcn_rcpf(ls[bi][r]);
+    }
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj) {
+    lt[bj] = __shfl(my_lt, 16 * bj + r16, 64);
+    rlt[bj] = __builtin_amdgcn_rcpf(lt[bj]);
+  }
 #pragma unroll
   for (int bj = 0; bj < 4; ++bj) {
     const int col = 16 * bj + r16;
-    const float lt = __shfl(my_lt, col, 64);
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * bi + 4 * rq + r;
-        const float ls = __shfl(my_ls, row, 64);
+        const float l = ls[bi][r];
         const float dot = acc[bi][bj][r];
         // S_raw = dot / l_i (0 for an empty sentence); rho = min / max of lengths
-        const float sraw = ls > 0.0f ? dot * __builtin_amdgcn_rcpf(ls) : 0.0f;
-        const float mx = fmaxf(ls, lt);
-        const float rho = mx > 0.0f ? fminf(ls, lt) * __builtin_amdgcn_rcpf(mx) : 1.0f;
+        const float sraw = l > 0.0f ? dot * rls[bi][r] : 0.0f;
+        const float mx = fmaxf(l, lt[bj]);
+        const float rho = mx > 0.0f ? fminf(l, lt[bj]) * fminf(rls[bi][r], rlt[bj]) : 1.0f;
         const float z = __builtin_fmaf(sc.w0, sraw, __builtin_fmaf(sc.w1, rho, sc.b));
         // sigmoid in the overflow-free form: e = exp(-|z|), S = 1/(1+e) or e/(1+e)
         const float e = __builtin_amdgcn_exp2f(-fabsf(z) * LOG2E);
