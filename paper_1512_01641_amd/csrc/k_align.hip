@@ -61,6 +61,13 @@ static __device__ __forceinline__ float dpp_shl1(float old, float src) {
 
 static __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// A 64-bit value every lane holds the same value of, moved to scalar registers.
+static __device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // A pointer every lane holds the same value of, moved to scalar registers.
 template <typename T>
 static __device__ __forceinline__ T *uniform_ptr(T *p) {
@@ -124,6 +131,26 @@ static __device__ __forceinline__ void load_group(float *ring, const StripSrc &s
 }
 #undef NWM_S_LOAD_NEXT4
 #undef NWM_S_LOAD_NEXT
+
+// One 16-byte agent-coherent (sc1) LDS-direct load per active lane: lane l
+// writes bytes 16 l .. 16 l + 15 of buf.  Written as asm for the same reason
+// as the S loads: the compiler's own tracking of an LDS-direct load makes
+// every later LDS read (the ring included) wait for all loads in flight,
+// which would cancel the two-group prefetch.  Its readers wait with an
+// explicit vmcnt.  One wait state separates the M0 write from the load.
+static __device__ __forceinline__ void load_window_lds(uint64_t *buf, const uint64_t *src) {
+  const uint32_t la = (uint32_t)(uintptr_t)(lds_void *)buf;
+  uint32_t save;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %1\n\t"
+      "s_nop 0\n\t"
+      "global_load_lds_dwordx4 %2, off sc1\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(save)
+      : "s"(la), "v"(src)
+      : "memory");
+}
 
 struct StripState {
   float H, diag, pw, col;
@@ -262,10 +289,11 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     const int rows = min(64, n - i0);
     const float *Sb = S + A.s_off[b];
     const int64_t mstride = bnd_stride(m);
-    const uint64_t *in_row = bnd + A.bnd_off[b] + (int64_t)(s - 1) * mstride;   // used when s > 0
-    uint64_t *out_row = bnd + A.bnd_off[b] + (int64_t)s * mstride;               // used when !last
+    const int64_t bnd_off = uniform64(A.bnd_off[b]), tb_off = uniform64(A.tb_off[b]);
+    const uint64_t *in_row = bnd + bnd_off + (int64_t)(s - 1) * mstride;   // used when s > 0
+    uint64_t *out_row = bnd + bnd_off + (int64_t)s * mstride;               // used when !last
     const int nG = (m + 63 + 63) >> 6;
-    uint4 *tbs = reinterpret_cast<uint4 *>(tb + A.tb_off[b]) + (int64_t)s * nG * 64;
+    uint4 *tbs = reinterpret_cast<uint4 *>(tb + tb_off) + (int64_t)s * nG * 64;
     const int T_end = m + rows - 1;
     const int T_pad = (T_end + 15) & ~15;
     const int r_last = n - 1 - i0;   // lane of row n in the last strip
@@ -286,7 +314,10 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     st.bits = 0u;
     st.pw = 0.0f;
 
-    // S ring prologue: groups 0 and 1 in flight
+    // S ring prologue: groups 0 and 1 in flight.  The pair's offsets are
+    // pinned in scalar registers first: a wait for them placed after the
+    // prologue would also wait for its 64 loads.
+    asm volatile("" ::"s"(bnd_off), "s"(tb_off));
     load_group(ring, src, 0);
     load_group(ring, src, 1);
 
@@ -299,13 +330,23 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     // LDS-direct loads, slots tw .. tw + 63), so no register holds a load in
     // flight; the wait for one is an explicit vmcnt over the fixed sequence of
     // memory operations of a group (below).
+    // A reload waits for its value inside the same asm statement: a load the
+    // compiler tracked could still be in flight where the spin loop rejoins
+    // the sweep, and the compiler would then drain every load in flight (the
+    // S prefetch included) before each later chunk.  The reload drains the
+    // counter too, but only on this slow path.
     auto load_window = [&](int tw) -> uint64_t {
-      return __hip_atomic_load(in_row + tw + 1 + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      uint64_t v;
+      asm volatile(
+          "global_load_dwordx2 %0, %1, off sc1\n\t"
+          "s_waitcnt vmcnt(0)"
+          : "=&v"(v)
+          : "v"(in_row + tw + 1 + lane)
+          : "memory");
+      return v;
     };
     auto prefetch_window = [&](int tw, uint64_t *buf) {
-      if (lane < 32)
-        __builtin_amdgcn_global_load_lds((const void *)(in_row + tw + 2 * lane),
-                                         (__attribute__((address_space(3))) void *)buf, 16, 0, 16 /* sc1 */);
+      if (lane < 32) load_window_lds(buf, in_row + tw + 2 * lane);
     };
     // lanes 0..15 feed the next 16 steps; columns beyond m are never used
     auto window_need = [&](int tw) -> bool { return lane < 16 && tw + 1 + lane <= m; };
