@@ -123,6 +123,10 @@ def work_model(batch):
         "build_a": ("hbm", 8 * E + 4 * n_src + 8 * E + 4 * n_rt * (nch + 1),
                     "read: 8 B per merged entry + 4 B count per sentence; write: 8 B per list entry (at most one "
                     "per merged entry) + 4 B chunk offsets per row tile and 32-word chunk"),
+        "expand_a": ("hbm", 4 * T_src + 8 * T_src + 8 * E + 16 * n_src + 8 * E + 4 * n_rt * (nch + 1),
+                     "fused merge + row-tile lists: read 4 B token + 8 B dictionary row offsets per source token, "
+                     "8 B per dictionary entry, 16 B per sentence; write 8 B per list entry (at most one per "
+                     "dictionary entry) + 4 B chunk offsets per row tile and 32-word chunk"),
         "build_b": ("hbm", 4 * T_tgt + 8 * n_tgt + 4 * T_tgt + n_ct * (4 * (nch + 1) + 16 * nch) + 4 * B * nch,
                     "read: 4 B token + 8 B offset per target token / sentence; write: 4 B list entry per token, "
                     "per column tile its chunk offsets, word masks and chunk ranges (20 B per 32-word chunk), per "
@@ -156,7 +160,7 @@ def rooflines(model, kernel_ms, prec_name):
     return out
 
 
-KERNEL_NAMES = {"merge": "k_merge_src", "build_a": "k_build_a", "build_b": "k_build_b",
+KERNEL_NAMES = {"merge": "k_merge_src", "build_a": "k_build_a", "expand_a": "k_expand_a", "build_b": "k_build_b",
                 "score": "k_score_c<%s>", "nw_fill": "k_nw_fill", "walk": "k_nw_walk", "keep": "k_keep"}
 
 

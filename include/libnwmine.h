@@ -301,6 +301,17 @@ nwm_status nwm_union_kept(const nwm_plan *plan, const int32_t *kept_fwd, const i
  *                                 registers, two 16-step chunks ahead (no LDS:
  *                                 more waves per compute unit).  The same cells
  *                                 in the same order: identical results.
+ *   NWM_PARAM_EXPAND_FUSED        1 = the source-side merge and row-tile list
+ *                                 build run as one kernel per row tile (merged
+ *                                 rows stay on chip), for plans whose
+ *                                 sentences have at most 48 tokens and whose
+ *                                 dictionary rows at most 4 entries (other
+ *                                 plans take the two-kernel path); 0 = always
+ *                                 the two kernels.  Default 1.  The fused path
+ *                                 keeps list entries the two-kernel path
+ *                                 drops (words outside the pair's target
+ *                                 vocabulary, which no tile's contraction
+ *                                 reads): identical results.
  * Out-of-range values give NWM_EINVAL.  Setting DP_HOT_PERCENT uploads the
  * plan's work list (synchronous).  A graph captured by nwm_mine is captured
  * again after any change. */
@@ -314,7 +325,8 @@ typedef enum {
   NWM_PARAM_DP_TEST_HOLD = 6,
   NWM_PARAM_SCORE_KGROUP = 7,
   NWM_PARAM_FILL_STAGING = 8,
-  NWM_N_PARAMS = 9
+  NWM_PARAM_EXPAND_FUSED = 9,
+  NWM_N_PARAMS = 10
 } nwm_param;
 nwm_status nwm_plan_set_param(nwm_plan *plan, nwm_param param, int32_t value);
 nwm_status nwm_plan_get_param(const nwm_plan *plan, nwm_param param, int32_t *value);
@@ -331,7 +343,8 @@ typedef enum {
   NWM_K_WALK = 5,      /* traceback */
   NWM_K_KEEP = 6,      /* threshold filter */
   NWM_K_BACKWARD = 7,  /* nwm_align_backward */
-  NWM_N_KCLASSES = 8
+  NWM_K_EXPAND_A = 8,  /* fused merge + row-tile lists (NWM_PARAM_EXPAND_FUSED) */
+  NWM_N_KCLASSES = 9
 } nwm_kclass;
 
 /* Record HIP events around every kernel the plan launches (0 = off).  While

@@ -163,7 +163,7 @@ class Plan:
     def set_timing(self, on: bool):
         _abi.check(self.lib.nwm_plan_set_timing(self.h, int(bool(on))), "nwm_plan_set_timing")
 
-    KERNEL_CLASSES = ("merge", "build_a", "build_b", "score", "nw_fill", "walk", "keep", "backward")
+    KERNEL_CLASSES = ("merge", "build_a", "build_b", "score", "nw_fill", "walk", "keep", "backward", "expand_a")
 
     def kernel_ms(self, reset: bool = True):
         """{kernel class: (summed ms, launches)} since the last reset."""

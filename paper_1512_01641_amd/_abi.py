@@ -21,7 +21,7 @@ SYMBOLS = ["nwm_create", "nwm_destroy", "nwm_strerror", "nwm_plan_create", "nwm_
 
 PARAMS = {"fill_waves_per_cu": 0, "merge_waves_per_cu": 1, "score_xcd_map": 2, "dp_hot_percent": 3,
           "score_compact": 4, "dp_spin_limit": 5, "dp_test_hold": 6, "score_kgroup": 7,
-          "fill_staging": 8}
+          "fill_staging": 8, "expand_fused": 9}
 
 P = ctypes.c_void_p
 

@@ -25,6 +25,8 @@ SPACE = {
     # S staging tile of the NW fill: LDS ring of 64 x 32 cells, or 16 cells
     # per lane in registers
     "fill_staging": [0, 1],
+    # source-side expansion: one fused kernel per row tile, or merge + list build
+    "expand_fused": [1, 0],
 }
 
 

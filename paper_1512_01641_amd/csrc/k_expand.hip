@@ -15,10 +15,16 @@
 //                  the dense operand tile.
 // 3. k_build_b     one workgroup per column tile: the distinct tokens of each
 //                  target sentence (binary presence Y), regrouped the same way.
+// 4. k_expand_a    1 and 2 fused (one workgroup per row tile, merged rows kept
+//                  on chip), over the dictionary padded to four entries per row
+//                  (k_pack_dict); used when sentences and dictionary rows are
+//                  short enough (see expand_a_fits).
 // Positions inside a chunk come from LDS atomics and vary run to run; every
 // (row, word) pair occurs once per chunk, so the dense tiles built from the
 // lists -- and the contraction -- do not depend on that order.
 #include "nwm_internal.h"
+
+#include <algorithm>
 
 namespace nwm {
 
@@ -89,6 +95,48 @@ static __device__ __forceinline__ int64_t first_lane64(int64_t x) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
   return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// A wave's merge table in LDS: 2^hbits slots of (word, FP64 sum), and the
+// slots claimed by the current sentence in claim order (at most half the
+// slots, which the plan's bound on tokens x degree never exceeds).
+struct MergeTable {
+  double *acc;
+  uint32_t *key;
+  int *slots;
+  int hbits;
+};
+
+// One dictionary entry (u, v) per lane into the table (a lane with u >= V
+// has none): open addressing with linear probing; the FP32 term is added to
+// the slot's FP64 sum.  Words new to the table take the next slot numbers in
+// lane order; nuniq counts them (wave-uniform).  A full table drops entries.
+static __device__ __forceinline__ void table_insert(const MergeTable &T, int V, uint32_t u, float v, int lane,
+                                                    int &nuniq) {
+  const int HS = 1 << T.hbits, CAPU = HS >> 1;
+  const bool act = u < (uint32_t)V;
+  uint32_t h = act ? (u * 0x9E3779B1u) >> (32 - T.hbits) : 0u;
+  bool pending = act, claimed = false, placed = false;
+  int probes = 0;
+  while (__ballot(pending) != 0) {
+    if (pending) {
+      const uint32_t old = atomicCAS(&T.key[h], HEMPTY, u);
+      if (old == HEMPTY || old == u) {
+        claimed = old == HEMPTY;
+        placed = true;
+        pending = false;
+      } else if (++probes >= HS) {
+        pending = false;   // table full: drop
+      } else {
+        h = (h + 1) & (uint32_t)(HS - 1);
+      }
+    }
+  }
+  if (placed) atomicAdd(&T.acc[h], (double)v);
+  const uint64_t cm = __ballot(claimed);
+  const int rank = nuniq + (int)__popcll(cm & ((1ull << lane) - 1ull));
+  if (claimed && rank < CAPU) T.slots[rank] = (int)h;
+  nuniq = min(nuniq + (int)__popcll(cm), CAPU);
 }
 
 // One wave per source sentence (grid-stride): T'[i][u] = sum over the
@@ -207,32 +255,8 @@ __global__ __launch_bounds__(64) void k_merge_src(int64_t n_sent, const int64_t 
   };
 
   int nuniq = 0;
-  // one dictionary entry per lane into the table
-  auto insert = [&](uint32_t u, float v) {
-    const bool act = u < (uint32_t)V;
-    uint32_t h = act ? (u * 0x9E3779B1u) >> (32 - hbits) : 0u;
-    bool pending = act, claimed = false, placed = false;
-    int probes = 0;
-    while (__ballot(pending) != 0) {
-      if (pending) {
-        const uint32_t old = atomicCAS(&key[h], HEMPTY, u);
-        if (old == HEMPTY || old == u) {
-          claimed = old == HEMPTY;
-          placed = true;
-          pending = false;
-        } else if (++probes >= HS) {
-          pending = false;   // table full: drop
-        } else {
-          h = (h + 1) & (uint32_t)(HS - 1);
-        }
-      }
-    }
-    if (placed) atomicAdd(&acc[h], (double)v);
-    const uint64_t cm = __ballot(claimed);
-    const int rank = nuniq + __popcll(cm & ((1ull << lane) - 1ull));
-    if (claimed && rank < CAPU) slots[rank] = (int)h;
-    nuniq = min(nuniq + __popcll(cm), CAPU);
-  };
+  const MergeTable tab{acc, key, slots, hbits};
+  auto insert = [&](uint32_t u, float v) { table_insert(tab, V, u, v, lane, nuniq); };
 
   const int64_t G = gridDim.x;
   int64_t sent = blockIdx.x;
@@ -496,6 +520,247 @@ __global__ __launch_bounds__(256) void k_build_a(PlanDev P, const int64_t *__res
   }
 }
 
+// Fused source-side expansion: the merge and the row-tile list builder in one
+// kernel, so merged rows never leave the chip.  One workgroup of EXA_WAVES
+// waves per row tile; wave w merges the tile's rows w, w + EXA_WAVES, ...
+// (EXA_SENT of them) in its own LDS table of (word, FP64 sum) slots: the same
+// sums as k_merge_src's (exact FP64 sums of the FP32 terms, rounded to FP32
+// once).  A row's entries sit three per lane (token 16 q + l / 4, entry l % 4
+// of its dictionary row, for q < 3): the three compare-and-swaps of a probe go
+// out together, the lane whose swap claimed a slot owns that word, every
+// entry adds its term to its word's slot, and each owner reads its sum back
+// and clears the slot -- about two LDS round trips per row, and the merged
+// row stays where the owners are (an entry per owner, holes elsewhere).  The
+// loads of all of a wave's rows go out stage by stage (token ranges, tokens,
+// padded dictionary entries: three dependent rounds per wave).  Then
+// the workgroup counts the entries per K chunk, scans the counts and places
+// every entry, as k_build_a does.  Requires sentences of at most
+// 16 * MERGE_ROUNDS tokens and dictionary rows of at most 4 entries (the plan
+// checks); tokens past that bound (a broken contract) are ignored.  There is
+// no pair-vocabulary filter: an entry whose word no column tile holds is
+// skipped by the contraction's own lookup.
+constexpr int EXA_WAVES = 8;
+constexpr int EXA_SENT = TM / EXA_WAVES;   // rows per wave
+
+// Per wave: acc [HS + 64] (FP64) and key [HS + 64]; slot HS + l is lane l's
+// junk slot (never matched, never read back as a word).
+static __host__ __device__ inline size_t expand_a_wave_bytes(int hbits) {
+  return (((size_t)1 << hbits) + 64) * (sizeof(double) + sizeof(uint32_t));
+}
+
+// Merge state of one entry of a row, in one register: its probe slot (below
+// HS) while it probes; HS + lane (the lane's junk slot) when it has no slot
+// (no entry, or dropped by a full table); its final slot with EXA_OWN (it
+// claimed the slot) or EXA_JOIN (the slot already held its word) set.
+constexpr uint32_t EXA_OWN = 1u << 30, EXA_JOIN = 1u << 29, EXA_SLOT = EXA_JOIN - 1u;
+
+// The NQ compare-and-swaps of one probe round (entry q: word w[q] into slot
+// h[q] if it is free; an entry that is not probing swaps its lane's junk slot
+// with itself), issued back to back and waited for together -- written as
+// asm because the compiler waits for each before issuing the next.  old[q]
+// is what the slot held.
+template <int NQ>
+static __device__ __forceinline__ void cas_round(uint32_t (&old)[NQ], uint32_t base, const uint32_t (&h)[NQ],
+                                                 uint32_t HS, uint32_t junk, const uint32_t (&w)[MERGE_ROUNDS]) {
+  uint32_t a[NQ], v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const bool probing = h[q] < HS;
+    a[q] = base + 4u * (probing ? h[q] : junk);
+    v[q] = probing ? w[q] : HEMPTY;
+  }
+  if constexpr (NQ == 1) {
+    asm volatile("ds_cmpst_rtn_b32 %0, %1, %2, %3\n\ts_waitcnt lgkmcnt(0)"
+                 : "=&v"(old[0])
+                 : "v"(a[0]), "v"(HEMPTY), "v"(v[0])
+                 : "memory");
+  } else if constexpr (NQ == 2) {
+    asm volatile(
+        "ds_cmpst_rtn_b32 %0, %2, %4, %5\n\t"
+        "ds_cmpst_rtn_b32 %1, %3, %4, %6\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(old[0]), "=&v"(old[1])
+        : "v"(a[0]), "v"(a[1]), "v"(HEMPTY), "v"(v[0]), "v"(v[1])
+        : "memory");
+  } else {
+    static_assert(NQ == 3, "at most three entries per lane");
+    asm volatile(
+        "ds_cmpst_rtn_b32 %0, %3, %6, %7\n\t"
+        "ds_cmpst_rtn_b32 %1, %4, %6, %8\n\t"
+        "ds_cmpst_rtn_b32 %2, %5, %6, %9\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(old[0]), "=&v"(old[1]), "=&v"(old[2])
+        : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(HEMPTY), "v"(v[0]), "v"(v[1]), "v"(v[2])
+        : "memory");
+  }
+}
+
+// Merge one row whose entries sit in the first NQ of the lane's registers
+// (the others hold none) through the wave's table, which it leaves clear;
+// out[q] = {word, FP32 sum} for the entries that own their word, word
+// HEMPTY elsewhere.
+template <int NQ>
+static __device__ __forceinline__ void merge_row(uint32_t *key, double *acc, int hbits, int V, int lane,
+                                                 const uint32_t (&u)[MERGE_ROUNDS], const float (&v)[MERGE_ROUNDS],
+                                                 uint2 (&out)[MERGE_ROUNDS]) {
+  const uint32_t HS = 1u << hbits, mask = HS - 1u, junk = HS + (uint32_t)lane;
+  const uint32_t base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) void *)key;
+  uint32_t h[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) h[q] = u[q] < (uint32_t)V ? (__umul24(u[q], 0x9E3779u) >> (24 - hbits)) & mask : junk;
+  // probe rounds: a free slot is claimed, a slot holding the word is joined,
+  // another word moves the entry on (linear probing); after HS rounds the
+  // table is full and the entries still probing are dropped
+  for (uint32_t round = 0;; ++round) {
+    bool probing = false;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) probing = probing | (h[q] < HS);
+    if (__ballot(probing) == 0) break;
+    if (round >= HS) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) h[q] = h[q] < HS ? junk : h[q];
+      break;
+    }
+    uint32_t old[NQ];
+    cas_round<NQ>(old, base, h, HS, junk, u);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const bool free_slot = old[q] == HEMPTY;
+      const bool hit = free_slot | (old[q] == u[q]);
+      const uint32_t done = h[q] | (free_slot ? EXA_OWN : EXA_JOIN);
+      const uint32_t next = (h[q] + 1u) & mask;
+      h[q] = h[q] < HS ? (hit ? done : next) : h[q];
+    }
+  }
+  // every term into its word's slot (no slot: the lane's junk slot)
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) atomicAdd(&acc[h[q] & EXA_SLOT], u[q] < (uint32_t)V ? (double)v[q] : 0.0);
+  // owners read their word's sum (every term has landed: LDS operations of a
+  // wave complete in order) and clear the slot; the others touch their junk
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const bool own = (h[q] & EXA_OWN) != 0u;
+    const uint32_t sl = own ? (h[q] & EXA_SLOT) : junk;
+    const double a = acc[sl];
+    out[q] = make_uint2(own ? u[q] : HEMPTY, __float_as_uint((float)a));
+    key[sl] = HEMPTY;
+    acc[sl] = 0.0;
+  }
+#pragma unroll
+  for (int q = NQ; q < MERGE_ROUNDS; ++q) out[q] = make_uint2(HEMPTY, 0u);
+}
+
+size_t expand_a_lds_bytes(int hbits, int nch) {
+  return EXA_WAVES * expand_a_wave_bytes(hbits) + sizeof(int) * (size_t)(nch + 1 + 64);
+}
+
+__global__ __launch_bounds__(64 * EXA_WAVES) void k_expand_a(PlanDev P, const int64_t *__restrict__ src_off,
+                                                             const int32_t *__restrict__ src_tok,
+                                                             const uint2 *__restrict__ dpk, int V, int hbits,
+                                                             uint2 *__restrict__ a_list,
+                                                             int32_t *__restrict__ a_choff, int pitch, int esize,
+                                                             int compact, int64_t *__restrict__ a_base, int r0) {
+  extern __shared__ __align__(16) char smem[];
+  const int HS = 1 << hbits;
+  const size_t per_wave = expand_a_wave_bytes(hbits);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double *acc = reinterpret_cast<double *>(smem + wave * per_wave);   // [HS + 64]
+  uint32_t *key = reinterpret_cast<uint32_t *>(acc + HS + 64);        // [HS + 64]
+  int *off = reinterpret_cast<int *>(smem + EXA_WAVES * per_wave);    // [nch + 1], then 64 junk slots
+  const int rt = r0 + (int)blockIdx.x;
+  const TileMeta tm = P.rt_meta[rt];
+  const int rows = tm.count;
+  const int64_t s0 = tm.first;
+  const int64_t tile_base = src_off[s0] * (int64_t)P.max_deg;
+  for (int h = lane; h < HS + 64; h += 64) {
+    key[h] = HEMPTY;
+    acc[h] = 0.0;
+  }
+  for (int c = threadIdx.x; c < P.nch + 1 + 64; c += 64 * EXA_WAVES) off[c] = 0;
+
+  // stage 1: lane k (< EXA_SENT) holds row wave + EXA_WAVES k's token range
+  const int myrow = wave + EXA_WAVES * lane;
+  const bool vrow = lane < EXA_SENT && myrow < rows;
+  const int64_t srow = s0 + (vrow ? myrow : 0);
+  const int64_t q0 = src_off[srow];
+  const int qlen = vrow ? (int)min(src_off[srow + 1] - q0, (int64_t)(16 * MERGE_ROUNDS)) : 0;
+  const __amdgpu_buffer_rsrc_t r_dpk = __builtin_amdgcn_make_buffer_rsrc((void *)dpk, (short)0, V * 32, 0x00020000);
+  int len[EXA_SENT];
+  // stage 2: tokens (lane l of round q: token 16 q + l / 4 of the row)
+  int tok[EXA_SENT][MERGE_ROUNDS];
+#pragma unroll
+  for (int k = 0; k < EXA_SENT; ++k) {
+    len[k] = __builtin_amdgcn_readlane(qlen, k);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)q0, k);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)q0 >> 32), k);
+    const int64_t t0 = (int64_t)(((uint64_t)hi << 32) | lo);
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(src_tok + t0), (short)0, len[k] * 4, 0x00020000);
+#pragma unroll
+    for (int q = 0; q < MERGE_ROUNDS; ++q) tok[k][q] = (int)buf_u32(r, (uint32_t)(16 * q + (lane >> 2)) * 4u);
+  }
+  // stage 3: the entries, from the padded dictionary (lane l: entry l % 4
+  // of its token's row; padding and missing tokens read word HEMPTY)
+  uint32_t eu[EXA_SENT][MERGE_ROUNDS];
+  float ev[EXA_SENT][MERGE_ROUNDS];
+#pragma unroll
+  for (int k = 0; k < EXA_SENT; ++k)
+#pragma unroll
+    for (int q = 0; q < MERGE_ROUNDS; ++q) {
+      const bool ok = 16 * q + (lane >> 2) < len[k] && (unsigned)tok[k][q] < (unsigned)V;
+      const m_u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(
+          r_dpk, ok ? ((uint32_t)tok[k][q] * 4u + (uint32_t)(lane & 3)) * 8u : BUF_OOB, 0, 0);
+      eu[k][q] = ok ? x.x : HEMPTY;
+      ev[k][q] = __uint_as_float(x.y);
+    }
+  wave_sync();   // the table is clear
+  // merge row by row (a row of at most 16 q tokens needs only q of the
+  // lane's entries); the merged row stays in registers
+  uint2 out[EXA_SENT][MERGE_ROUNDS];
+#pragma unroll
+  for (int k = 0; k < EXA_SENT; ++k) {
+    const int rounds = (len[k] + 15) >> 4;
+    if (rounds <= 1) merge_row<1>(key, acc, hbits, V, lane, eu[k], ev[k], out[k]);
+    else if (rounds == 2) merge_row<2>(key, acc, hbits, V, lane, eu[k], ev[k], out[k]);
+    else merge_row<3>(key, acc, hbits, V, lane, eu[k], ev[k], out[k]);
+  }
+
+  // count per K chunk (lanes without an entry count into their own junk slot)
+  __syncthreads();
+  const int junk = P.nch + 1 + lane;
+#pragma unroll
+  for (int k = 0; k < EXA_SENT; ++k)
+#pragma unroll
+    for (int r = 0; r < MERGE_ROUNDS; ++r) {
+      const uint32_t u = out[k][r].x;
+      if (__ballot(u != HEMPTY) == 0) continue;   // (wave-uniform)
+      atomicAdd(&off[u != HEMPTY ? (int)(u / KC) : junk], 1);
+    }
+  __syncthreads();
+  block_exclusive_scan(off, P.nch, nullptr);
+  int32_t *choff = a_choff + (int64_t)rt * (P.nch + 1);
+  for (int c = threadIdx.x; c <= P.nch; c += 64 * EXA_WAVES) choff[c] = off[c];
+  const int total = __builtin_amdgcn_readfirstlane(off[P.nch]);
+  __syncthreads();
+  if (threadIdx.x == 0) a_base[rt] = tile_base;
+  // placement: unconditional buffer stores (no entry: an offset past the range)
+  const __amdgpu_buffer_rsrc_t r_out =
+      __builtin_amdgcn_make_buffer_rsrc((void *)(a_list + tile_base), (short)0, total * 8, 0x00020000);
+#pragma unroll
+  for (int k = 0; k < EXA_SENT; ++k) {
+    const int row = wave + EXA_WAVES * k;
+#pragma unroll
+    for (int r = 0; r < MERGE_ROUNDS; ++r) {
+      const uint2 ent = out[k][r];
+      const bool ok = ent.x != HEMPTY;
+      if (__ballot(ok) == 0) continue;   // (wave-uniform)
+      const int pos = atomicAdd(&off[ok ? (int)(ent.x / KC) : junk], 1);
+      __builtin_amdgcn_raw_buffer_store_b64((m_u32x2){a_code(ok ? ent.x : 0u, row, pitch, esize, compact), ent.y},
+                                            r_out, ok ? (uint32_t)pos * 8u : BUF_OOB, 0, 0);
+    }
+  }
+}
+
 // Compacted contraction (compact != 0): the column tile's vocabulary W (the
 // distinct words of its sentences, ascending) numbers the K positions, so the
 // contraction only walks ceil(|W| / KC) chunks.  Per global chunk c of KC
@@ -730,6 +995,50 @@ hipError_t launch_build_a(const PlanDev &P, const int64_t *src_off, const uint2 
   hipLaunchKernelGGL(k_build_a, dim3(n), dim3(256), lds, st, P, src_off, merged, cnt, a_list, a_choff, pitch, esize,
                      compact, a_base, p_voc, r0);
   return hipGetLastError();
+}
+
+// Row tiles [r0, r0 + n), fused merge and list build.
+// Merge-table size of the fused expansion: at most half full.
+static int expand_a_hbits(int max_entries) { return merge_hbits(max_entries); }
+
+hipError_t launch_expand_a(const PlanDev &P, const int64_t *src_off, const int32_t *src_tok, const uint2 *dpk, int V,
+                           int max_entries, uint2 *a_list, int32_t *a_choff, int pitch, int esize, int compact,
+                           int64_t *a_base, int r0, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int hb = expand_a_hbits(max_entries);
+  hipLaunchKernelGGL(k_expand_a, dim3(n), dim3(64 * EXA_WAVES), expand_a_lds_bytes(hb, P.nch), st, P, src_off,
+                     src_tok, dpk, V, hb, a_list, a_choff, pitch, esize, compact, a_base, r0);
+  return hipGetLastError();
+}
+
+// The dictionary padded to four entries per row: dpk[4 t + e] = entry e of
+// row t, or word HEMPTY past the row's end.  Rows are cut at max_deg (at most
+// four: the fused path only runs for such plans), as the merge cuts them.
+__global__ __launch_bounds__(256) void k_pack_dict(const int32_t *__restrict__ row_off, const int32_t *__restrict__ col,
+                                                   const float *__restrict__ val, int V, int max_deg,
+                                                   uint2 *__restrict__ dpk) {
+  for (int64_t k = blockIdx.x * (int64_t)256 + threadIdx.x; k < 4 * (int64_t)V; k += (int64_t)gridDim.x * 256) {
+    const int t = (int)(k >> 2), e = (int)(k & 3);
+    const int e0 = row_off[t], deg = min(row_off[t + 1] - e0, max_deg);
+    dpk[k] = e < deg ? make_uint2((uint32_t)col[e0 + e], __float_as_uint(val[e0 + e])) : make_uint2(HEMPTY, 0u);
+  }
+}
+
+hipError_t launch_pack_dict(const int32_t *row_off, const int32_t *col, const float *val, int V, int max_deg,
+                            uint2 *dpk, hipStream_t st) {
+  if (V <= 0) return hipSuccess;
+  const int64_t blocks = (4 * (int64_t)V + 255) / 256;
+  hipLaunchKernelGGL(k_pack_dict, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, st, row_off, col, val,
+                     V, max_deg, dpk);
+  return hipGetLastError();
+}
+
+// Whether the fused expansion covers a plan: every sentence's tokens in the
+// merge's rounds, every dictionary row within four entries, and its LDS
+// within the default dynamic limit.
+bool expand_a_fits(int max_sent_tokens, int max_deg, int nch) {
+  if (max_sent_tokens > 16 * MERGE_ROUNDS || max_deg > 4) return false;
+  return expand_a_lds_bytes(expand_a_hbits(std::max(1, max_sent_tokens * max_deg)), nch) <= 65536;
 }
 
 __global__ __launch_bounds__(256) void k_clear_u32(uint32_t *__restrict__ p, int64_t n) {

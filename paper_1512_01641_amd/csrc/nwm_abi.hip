@@ -23,6 +23,10 @@ hipError_t launch_build_a(const PlanDev &, const int64_t *, const uint2 *, const
 hipError_t launch_build_b(const PlanDev &, const int64_t *, const int32_t *, uint32_t *, int32_t *, int, int, int,
                           uint2 *, int32_t *, int2 *, int64_t *, uint32_t *, int, int, hipStream_t);
 hipError_t launch_clear_u32(uint32_t *, int64_t, hipStream_t);
+hipError_t launch_expand_a(const PlanDev &, const int64_t *, const int32_t *, const uint2 *, int, int, uint2 *,
+                           int32_t *, int, int, int, int64_t *, int, int, hipStream_t);
+bool expand_a_fits(int max_sent_tokens, int max_deg, int nch);
+hipError_t launch_pack_dict(const int32_t *, const int32_t *, const float *, int, int, uint2 *, hipStream_t);
 hipError_t build_set_attrs(int nch, int V);
 hipError_t launch_score(const PlanDev &, bool, const int64_t *, const int64_t *, const uint2 *, const int32_t *,
                         const uint32_t *, const int32_t *, nwm_scorer, float *, float *, int, int, int, const uint2 *,
@@ -65,6 +69,7 @@ enum {
   K_WALK = NWM_K_WALK,
   K_KEEP = NWM_K_KEEP,
   K_BWD = NWM_K_BACKWARD,
+  K_EXPAND_A = NWM_K_EXPAND_A,
   K_CLASSES = NWM_N_KCLASSES
 };
 
@@ -137,7 +142,8 @@ struct nwm_plan {
   int64_t n_bnd = 0;   // uint64 entries of the published-row region
   int max_entries = 1; // dictionary entries of the longest source sentence (tokens x max_deg)
   // launch parameters (nwm_param) and what re-deriving the DP priority flags needs
-  int32_t param[NWM_N_PARAMS] = {0, 0, 1, 50, 1, 0, 0, 1, 0};
+  int32_t param[NWM_N_PARAMS] = {0, 0, 1, 50, 1, 0, 0, 1, 0, 1};
+  int max_sent_tokens = 0;   // the batch's bound on tokens per sentence
   uint64_t param_version = 0;
   std::vector<int32_t> it_strip;   // strip index per DP item (no flags)
   std::vector<int64_t> it_chain;   // dependency chain of the item's pair
@@ -152,11 +158,12 @@ struct nwm_plan {
   int64_t n_sent_long = 0;
   // the first of the long pairs (chain >= TOP_CHAIN_PERCENT of the longest):
   // their contraction tiles, DP items and pairs lead the long pairs' ranges
-  int n_gt_top = 0, n_items_top = 0, n_pairs_top = 0;
+  int n_gt_top = 0, n_items_top = 0, n_pairs_top = 0, n_rt_top = 0, n_ct_top = 0;
+  int64_t n_sent_top = 0;
   hipStream_t lane_stream = nullptr;   // the top pairs' DP
   hipEvent_t ev_top = nullptr, ev_top_done = nullptr;
   hipStream_t exp_stream = nullptr;    // the other pairs' source-side expansion
-  hipEvent_t ev_long = nullptr, ev_long_done = nullptr, ev_b_long = nullptr, ev_b_rest = nullptr;
+  hipEvent_t ev_long = nullptr, ev_long_done = nullptr, ev_b_long = nullptr, ev_b_rest = nullptr, ev_b_top = nullptr;
   hipEvent_t ev_a_rest = nullptr;
   std::vector<int32_t> n, m;
   void *dmeta = nullptr;
@@ -293,6 +300,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   p->src_tokens = batch->src_tokens;
   p->tgt_tokens = batch->tgt_tokens;
   p->max_entries = std::max(1, batch->max_sent_tokens * max_deg);
+  p->max_sent_tokens = batch->max_sent_tokens;
   p->n.assign(batch->n_host, batch->n_host + B);
   p->m.assign(batch->m_host, batch->m_host + B);
   for (int b = 0; b < B; ++b) {
@@ -347,7 +355,8 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   sent_ids.reserve((size_t)sfirst[B]);
   p->n_rt_long = p->n_ct_long = p->n_gt_long = 0;
   p->n_sent_long = 0;
-  p->n_gt_top = 0;
+  p->n_gt_top = p->n_rt_top = p->n_ct_top = 0;
+  p->n_sent_top = 0;
   for (int pass = 0; pass < 2; ++pass) {
     const size_t q0 = pass == 0 ? 0 : n_long_pairs, q1 = pass == 0 ? n_long_pairs : lane_pairs.size();
     for (size_t q = q0; q < q1; ++q) {
@@ -371,7 +380,12 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
           gt_rt.push_back(rt0 + ri);
           gt_ct.push_back(ct0 + ci);
         }
-      if (is_top[b]) p->n_gt_top = (int)gt_rt.size();
+      if (is_top[b]) {
+        p->n_gt_top = (int)gt_rt.size();
+        p->n_rt_top = (int)rt_pair.size();
+        p->n_ct_top = (int)ct_pair.size();
+        p->n_sent_top = (int64_t)sent_ids.size();
+      }
     }
     if (pass == 0) {
       p->n_rt_long = (int)rt_pair.size();
@@ -561,6 +575,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   };
   const size_t a_ent = (size_t)p->src_tokens * (size_t)max_deg;
   W.a_merged = carve(8 * a_ent);
+  W.d_pack = carve(8 * 4 * (size_t)p->V);
   W.a_cnt = carve(4 * (size_t)p->n_src);
   W.a_list = carve(8 * (a_ent + LIST_SLACK_A));
   W.a_choff = carve(4 * (size_t)D.n_rt * (size_t)(nch + 1));
@@ -609,6 +624,7 @@ void nwm_plan_destroy(nwm_plan *plan) {
   if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
   if (plan->ev_long) (void)hipEventDestroy(plan->ev_long);
   if (plan->ev_b_long) (void)hipEventDestroy(plan->ev_b_long);
+  if (plan->ev_b_top) (void)hipEventDestroy(plan->ev_b_top);
   if (plan->ev_b_rest) (void)hipEventDestroy(plan->ev_b_rest);
   if (plan->lane_stream) (void)hipStreamDestroy(plan->lane_stream);
   if (plan->exp_stream) (void)hipStreamDestroy(plan->exp_stream);
@@ -643,11 +659,20 @@ static nwm_status check_score_args(const nwm_plan *p, const nwm_batch *batch, co
   return NWM_OK;
 }
 
-// The compacted contraction leaves out source entries whose word no target
-// sentence of the pair holds: the column-tile builders form each pair's
-// vocabulary, the row-tile builders of a pair wait for them.
+// The two-kernel source path of the compacted contraction leaves out source
+// entries whose word no target sentence of the pair holds: the column-tile
+// builders form each pair's vocabulary, the row-tile builders of a pair wait
+// for them.  The fused path keeps those entries (the contraction never finds
+// their words in a tile's vocabulary) and waits for nothing.
+// The source side runs as one fused kernel per row tile.
+static bool fused_a(const nwm_plan *p) {
+  return p->param[NWM_PARAM_EXPAND_FUSED] && expand_a_fits(p->max_sent_tokens, p->max_deg, p->dev.nch);
+}
+
 static uint32_t *pair_vocab(nwm_plan *p, void *ws) {
-  return p->param[NWM_PARAM_SCORE_COMPACT] ? (uint32_t *)(static_cast<char *>(ws) + p->ws.p_voc) : nullptr;
+  // only the two-kernel source path filters by the pair's target vocabulary
+  return p->param[NWM_PARAM_SCORE_COMPACT] && !fused_a(p) ? (uint32_t *)(static_cast<char *>(ws) + p->ws.p_voc)
+                                                          : nullptr;
 }
 
 // The source-side expansion of part of the batch on `st`: merged dictionary
@@ -664,6 +689,18 @@ static hipError_t expand_src(nwm_plan *p, const nwm_batch *batch, const nwm_dict
   // operand tiles
   const int pitch = bf16 ? PITCH_BF16 : PITCH_F32;
   const int esize = bf16 ? 2 : 4;
+  if (fused_a(p)) {
+    // no dependency on the target side; the wait keeps the contract that the
+    // contraction queued after this on `st` finds both sides built
+    Mark mx(p, K_EXPAND_A, st);
+    hipError_t e = launch_expand_a(p->dev, batch->src_off, batch->src_tok, (const uint2 *)(w + p->ws.d_pack), p->V,
+                                   p->max_entries, (uint2 *)(w + p->ws.a_list), (int32_t *)(w + p->ws.a_choff),
+                                   pitch, esize, p->param[NWM_PARAM_SCORE_COMPACT], (int64_t *)(w + p->ws.a_base),
+                                   r0, nr, st);
+    mx.done();
+    if (e == hipSuccess && tgt_done) e = hipStreamWaitEvent(st, tgt_done, 0);
+    return e;
+  }
   Mark mk(p, K_MERGE, st);
   hipError_t e = launch_merge_src(ns, p->dev.sent_ids, k0, batch->src_off, batch->src_tok, dict->row_off, dict->col,
                                   dict->val, p->V, p->max_deg, p->max_entries, merged, cnt,
@@ -702,8 +739,20 @@ static hipError_t expand_tgt(nwm_plan *p, const nwm_batch *batch, void *ws, int 
 // side: they are built on the plan's second stream, forked from `st` by an
 // event, while `st` merges the source rows; the row-tile lists wait for them
 // (under graph capture: a parallel branch of the graph joined there).
+// The fused source path reads the dictionary padded to four entries per row
+// (one 8-byte load per entry): packed on `st` before any expansion forks off.
+static hipError_t pack_dict(nwm_plan *p, const nwm_dict *dict, void *ws, hipStream_t st) {
+  if (!fused_a(p)) return hipSuccess;
+  Mark mk(p, K_EXPAND_A, st);
+  const hipError_t e = launch_pack_dict(dict->row_off, dict->col, dict->val, p->V, p->max_deg,
+                                        (uint2 *)(static_cast<char *>(ws) + p->ws.d_pack), st);
+  mk.done();
+  return e;
+}
+
 static hipError_t expand_lists(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, void *ws, hipStream_t st) {
-  hipError_t e = hipEventRecord(p->ev_fork, st);
+  hipError_t e = pack_dict(p, dict, ws, st);
+  if (e == hipSuccess) e = hipEventRecord(p->ev_fork, st);
   if (e == hipSuccess) e = hipStreamWaitEvent(p->aux_stream, p->ev_fork, 0);
   if (e == hipSuccess) e = expand_tgt(p, batch, ws, 0, p->dev.n_ct, true, p->aux_stream);
   if (e == hipSuccess) e = hipEventRecord(p->ev_join, p->aux_stream);
@@ -737,6 +786,7 @@ static hipError_t ensure_streams(nwm_plan *p) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_long, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_long_done, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_b_long, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_b_top, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_b_rest, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_top, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_top_done, hipEventDisableTiming);
@@ -888,6 +938,7 @@ nwm_status nwm_plan_set_param(nwm_plan *p, nwm_param param, int32_t value) {
       if (value != 1 && value != 2) return NWM_EINVAL;
       break;
     case NWM_PARAM_FILL_STAGING:
+    case NWM_PARAM_EXPAND_FUSED:
       if (value != 0 && value != 1) return NWM_EINVAL;
       break;
     default:
@@ -962,10 +1013,11 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
   const PlanDev &D = p->dev;
   const bool scored = p->sizes.S_elems > 0;
   const int gl = p->n_gt_long, il = p->n_items_long, ol = p->n_pairs_long;
-  const int rl = p->n_rt_long, cl = p->n_ct_long;
-  const int64_t kl = p->n_sent_long;
+  const int rl = p->n_rt_long, cl = p->n_ct_long, rtop = p->n_rt_top, ctop = p->n_ct_top;
+  const int64_t kl = p->n_sent_long, ktop = p->n_sent_top;
   hipError_t e = ensure_streams(p);
   hipStream_t aux = p->aux_stream, lane = p->lane_stream, xs = p->exp_stream;
+  if (e == hipSuccess && scored) e = pack_dict(p, dict, ws, st);
   // target-side lists on one side stream (the long pairs' first, each part
   // announced by an event), the other pairs' source-side expansion on a
   // second one, both from the start
@@ -973,30 +1025,43 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
   if (e == hipSuccess) e = hipStreamWaitEvent(aux, p->ev_fork, 0);
   if (e == hipSuccess) e = hipStreamWaitEvent(xs, p->ev_fork, 0);
   if (scored) {
-    if (e == hipSuccess) e = expand_tgt(p, batch, ws, 0, cl, true, aux);
+    if (e == hipSuccess) e = expand_tgt(p, batch, ws, 0, ctop, true, aux);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_b_top, aux);
+    if (e == hipSuccess) e = expand_tgt(p, batch, ws, ctop, cl - ctop, false, aux);
     if (e == hipSuccess) e = hipEventRecord(p->ev_b_long, aux);
     if (e == hipSuccess) e = expand_tgt(p, batch, ws, cl, D.n_ct - cl, false, aux);
   }
   if (e == hipSuccess) e = hipEventRecord(p->ev_b_rest, aux);
-  // the other pairs' source-side expansion, issued before any DP so that it
-  // does not queue behind one
-  if (e == hipSuccess && scored)
-    e = expand_src(p, batch, dict, ws, kl, p->n_src - kl, rl, D.n_rt - rl, p->ev_b_rest, xs);
-  if (e == hipSuccess) e = hipEventRecord(p->ev_a_rest, xs);
-  if (e == hipSuccess) e = launch_nw_reset(D, gap, score, bnd, p->n_bnd, ctl, st);
+  // the other pairs' source-side expansion on the second side stream, issued
+  // before any DP so that it does not queue behind one; with top pairs, only
+  // once their tiles are scored (a replayed graph may put it on the main
+  // stream's hardware queue, where the top pairs' contraction would wait
+  // behind it)
+  auto rest_src = [&]() {
+    if (e == hipSuccess && scored)
+      e = expand_src(p, batch, dict, ws, kl, p->n_src - kl, rl, D.n_rt - rl, p->ev_b_rest, xs);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_a_rest, xs);
+  };
   const int gtop = p->n_gt_top, itop = p->n_items_top, otop = p->n_pairs_top;
+  const bool rest_after_top = ol > 0 && gtop > 0;
+  if (!rest_after_top) rest_src();
+  if (e == hipSuccess) e = launch_nw_reset(D, gap, score, bnd, p->n_bnd, ctl, st);
   if (ol > 0) {
-    // the long pairs: expand and score on the main stream, the top pairs'
-    // tiles first; the top pairs' DP on the lane stream as soon as their
-    // tiles are scored, the other long pairs' DP after theirs on the side
-    // stream that built the column tiles (four streams in all, one hardware
-    // queue each), while the main stream goes on with the rest
+    // the long pairs: expand and score on the main stream, the top pairs
+    // first (their lists, then their tiles); the top pairs' DP on the lane
+    // stream as soon as their tiles are scored, the other long pairs' DP
+    // after theirs on the side stream that built the column tiles (four
+    // streams in all, one hardware queue each), while the main stream goes
+    // on with the rest
     if (scored) {
-      if (e == hipSuccess) e = expand_src(p, batch, dict, ws, 0, kl, 0, rl, p->ev_b_long, st);
+      if (e == hipSuccess) e = expand_src(p, batch, dict, ws, 0, ktop, 0, rtop, p->ev_b_top, st);
       if (e == hipSuccess) e = score_tiles(p, batch, sc, S, S_raw, ws, 0, gtop, st);
     }
     if (e == hipSuccess) e = hipEventRecord(p->ev_top, st);
-    if (e == hipSuccess && scored) e = score_tiles(p, batch, sc, S, S_raw, ws, gtop, gl - gtop, st);
+    if (scored) {
+      if (e == hipSuccess) e = expand_src(p, batch, dict, ws, ktop, kl - ktop, rtop, rl - rtop, p->ev_b_long, st);
+      if (e == hipSuccess) e = score_tiles(p, batch, sc, S, S_raw, ws, gtop, gl - gtop, st);
+    }
     if (e == hipSuccess) e = hipEventRecord(p->ev_long, st);
     if (otop > 0) {
       if (e == hipSuccess) e = hipStreamWaitEvent(lane, p->ev_top, 0);
@@ -1016,6 +1081,10 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
       if (e == hipSuccess)
         e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, otop, ol - otop, aux);
       if (e == hipSuccess) e = hipEventRecord(p->ev_long_done, aux);
+    }
+    if (rest_after_top) {   // issued last: the long pairs' work is queued first
+      if (e == hipSuccess) e = hipStreamWaitEvent(xs, p->ev_top, 0);
+      rest_src();
     }
   }
   if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_a_rest, 0);

@@ -115,6 +115,7 @@ struct PlanDev {
 // Workspace layout (byte offsets into the caller's ws).
 struct WsLayout {
   size_t a_merged;   // uint2 {u, f32 bits} [src_tokens * max_deg]
+  size_t d_pack;     // uint2 {u, f32 bits} [V * 4] dictionary rows padded to 4 entries (fused expansion)
   size_t a_cnt;      // int32 [sum n]
   size_t a_list;     // uint2 {lds offset, f32 bits} [src_tokens * max_deg]
   size_t a_choff;    // int32 [n_rt * (nch + 1)]

@@ -17,9 +17,11 @@ def gpu_available() -> bool:
         return False
 
 
-def run_gpu(batch, prec=0, scorer=None, gap=None, threshold=None, device="cuda:0", want_raw=True, params=None):
+def run_gpu(batch, prec=0, scorer=None, gap=None, threshold=None, device="cuda:0", want_raw=True, params=None,
+            timing=False):
     """Score + align a synth batch on the GPU; returns host numpy results.
-    `params`: launch parameters set on the plan first ({name: value})."""
+    `params`: launch parameters set on the plan first ({name: value});
+    `timing`: also return the launches per kernel class ("launches")."""
     import paper_1512_01641_amd as nw
     ctx = nw.Context(0)
     db = nw.DeviceBatch.from_host(batch, device)
@@ -28,6 +30,8 @@ def run_gpu(batch, prec=0, scorer=None, gap=None, threshold=None, device="cuda:0
     for k, v in (params or {}).items():
         mn.plan.set_param(k, v)
     w = batch.scorer if scorer is None else np.asarray(scorer, np.float32)
+    if timing:
+        mn.plan.set_timing(True)
     mn.score_pairs(w, want_raw=want_raw)
     mn.align(batch.gap if gap is None else gap, batch.threshold if threshold is None else threshold)
     import torch
@@ -37,6 +41,9 @@ def run_gpu(batch, prec=0, scorer=None, gap=None, threshold=None, device="cuda:0
                score=mn.score[:batch.B].cpu().numpy(), n_diag=mn.n_diag[:batch.B].cpu().numpy(),
                n_kept=mn.n_kept[:batch.B].cpu().numpy(), kept=mn.kept.cpu().numpy(), p_off=mn.p_off,
                miner=mn, ctx=ctx)
+    if timing:
+        out["launches"] = {k: v[1] for k, v in mn.plan.kernel_ms(reset=True).items()}
+        mn.plan.set_timing(False)
     return out
 
 

@@ -251,6 +251,54 @@ def test_scores_compacted_and_dense_contraction(compact):
     _check_scores(w, 1, tol_abs=2e-2, params=p)
 
 
+def _fused_edge_batch():
+    """Five pairs whose row tiles are full, partial and of one row, over a
+    dictionary with rows of 0 to 4 entries, with source sentences of 0 to 48
+    tokens (the bound of the fused expansion, reached exactly) and repeated
+    tokens inside a sentence (merged entries)."""
+    import dataclasses
+    b = corpus.make_batch(2, pairs=5, sizes=([1, 63, 64, 65, 130], [7, 70, 64, 1, 129]))
+    rng = np.random.default_rng(13)
+    V = b.V
+    deg = rng.integers(0, 5, size=V)
+    deg[:8] = [0, 4, 3, 2, 1, 0, 4, 4]
+    cols = [np.sort(rng.choice(V, int(k), replace=False)) for k in deg]
+    d_row_off = np.concatenate([[0], np.cumsum(deg)]).astype(np.int32)
+    d_col = np.concatenate(cols).astype(np.int32)
+    d_val = rng.random(int(deg.sum())).astype(np.float32)
+    n_src = int(b.n.sum())
+    s_len = rng.integers(0, 49, size=n_src)
+    s_len[:6] = [0, 1, 16, 47, 48, 48]
+    src_tok = rng.integers(0, 64, size=int(s_len.sum())).astype(np.int32)   # few words: repeats
+    src_tok[: int(s_len[:8].sum())] = rng.integers(0, 8, size=int(s_len[:8].sum()))
+    return dataclasses.replace(b, src_off=np.concatenate([[0], np.cumsum(s_len)]).astype(np.int64),
+                               src_tok=src_tok, d_row_off=d_row_off, d_col=d_col, d_val=d_val, d_deg=4)
+
+
+@pytest.mark.parametrize("compact", [1, 0])
+def test_fused_expansion_matches_two_kernel_path(compact):
+    # the fused source-side expansion (merge and row-tile lists in one kernel)
+    # against merge + list build: S and S_raw bit for bit (its lists keep
+    # entries the two-kernel path drops, which no tile's contraction reads),
+    # and the oracle bars; a batch past its bounds takes the two kernels
+    for b in (_fused_edge_batch(), corpus.make_batch(2, pairs=40)):
+        for prec in (0, 1):
+            p = {"score_compact": compact}
+            two = H.run_gpu(b, prec=prec, params=dict(p, expand_fused=0), timing=True)
+            one = H.run_gpu(b, prec=prec, params=dict(p, expand_fused=1), timing=True)
+            assert one["launches"]["expand_a"] > 0 and one["launches"]["merge"] == 0
+            assert two["launches"]["expand_a"] == 0 and two["launches"]["merge"] > 0
+            np.testing.assert_array_equal(one["S"].view(np.uint32), two["S"].view(np.uint32))
+            np.testing.assert_array_equal(one["S_raw"].view(np.uint32), two["S_raw"].view(np.uint32))
+            ora = oracle.score(b)
+            if prec == 0:
+                assert H.s_rel_err(one["S"], ora["S64"]).max() <= 1e-5
+            else:
+                assert np.abs(one["S"].astype(np.float64) - ora["S64"]).max() <= 2e-2
+    wide = H.run_gpu(_varying_degree_batch(), params={"score_compact": compact, "expand_fused": 1}, timing=True)
+    assert wide["launches"]["expand_a"] == 0 and wide["launches"]["merge"] > 0
+
+
 def test_contraction_k_width_two_chunks_per_round():
     # the compacted contraction with two 32-word chunks per round: the same
     # bits as one chunk per round (same summation order) and the oracle bars,
