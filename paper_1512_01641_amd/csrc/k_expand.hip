@@ -543,7 +543,8 @@ constexpr int EXA_WAVES = 8;
 constexpr int EXA_SENT = TM / EXA_WAVES;   // rows per wave
 
 // Per wave: acc [HS + 64] (FP64) and key [HS + 64]; slot HS + l is lane l's
-// junk slot (never matched, never read back as a word).
+// junk slot (never matched).  Only the keys need clearing: an owner writes
+// its slot's sum before any other term is added.
 static __host__ __device__ inline size_t expand_a_wave_bytes(int hbits) {
   return (((size_t)1 << hbits) + 64) * (sizeof(double) + sizeof(uint32_t));
 }
@@ -632,19 +633,25 @@ static __device__ __forceinline__ void merge_row(uint32_t *key, double *acc, int
       h[q] = h[q] < HS ? (hit ? done : next) : h[q];
     }
   }
-  // every term into its word's slot (no slot: the lane's junk slot)
+  // each owner starts its word's sum with its own term, then the entries
+  // that joined add theirs (FP64 atomics, only where a word repeats); the
+  // owners read the sums back (every term has landed: LDS operations of a
+  // wave complete in order) and free their slots
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) atomicAdd(&acc[h[q] & EXA_SLOT], u[q] < (uint32_t)V ? (double)v[q] : 0.0);
-  // owners read their word's sum (every term has landed: LDS operations of a
-  // wave complete in order) and clear the slot; the others touch their junk
+  for (int q = 0; q < NQ; ++q)
+    if (h[q] & EXA_OWN) acc[h[q] & EXA_SLOT] = (double)v[q];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+    if (h[q] & EXA_JOIN) atomicAdd(&acc[h[q] & EXA_SLOT], (double)v[q]);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const bool own = (h[q] & EXA_OWN) != 0u;
-    const uint32_t sl = own ? (h[q] & EXA_SLOT) : junk;
-    const double a = acc[sl];
-    out[q] = make_uint2(own ? u[q] : HEMPTY, __float_as_uint((float)a));
-    key[sl] = HEMPTY;
-    acc[sl] = 0.0;
+    uint2 o = make_uint2(HEMPTY, 0u);
+    if (h[q] & EXA_OWN) {
+      const uint32_t sl = h[q] & EXA_SLOT;
+      o = make_uint2(u[q], __float_as_uint((float)acc[sl]));
+      key[sl] = HEMPTY;
+    }
+    out[q] = o;
   }
 #pragma unroll
   for (int q = NQ; q < MERGE_ROUNDS; ++q) out[q] = make_uint2(HEMPTY, 0u);
@@ -672,10 +679,7 @@ __global__ __launch_bounds__(64 * EXA_WAVES) void k_expand_a(PlanDev P, const in
   const int rows = tm.count;
   const int64_t s0 = tm.first;
   const int64_t tile_base = src_off[s0] * (int64_t)P.max_deg;
-  for (int h = lane; h < HS + 64; h += 64) {
-    key[h] = HEMPTY;
-    acc[h] = 0.0;
-  }
+  for (int h = lane; h < HS + 64; h += 64) key[h] = HEMPTY;
   for (int c = threadIdx.x; c < P.nch + 1 + 64; c += 64 * EXA_WAVES) off[c] = 0;
 
   // stage 1: lane k (< EXA_SENT) holds row wave + EXA_WAVES k's token range
