@@ -22,6 +22,8 @@
 #include "nwm_internal.h"
 #include "libnwmine.h"
 
+#include <type_traits>
+
 namespace nwm {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -272,6 +274,29 @@ struct ScoreLds {
   static constexpr int BYTES = OPS > RED ? OPS : RED;
 };
 
+// Features and logistic score of one cell (Sec. 4): S_raw = dot / l (0 for an
+// empty source sentence), rho = min(l, l') / max(l, l') (1 when both
+// sentences are empty), z = w0 S_raw + w1 rho + b, S = 1 / (1 + exp(-z)).
+// rl, rlt are the reciprocals of l, l' (inf for 0), so rho = min(l / l',
+// l' / l) = min(l rlt, l' rl); positive floats order as their bit patterns,
+// so that minimum is an integer one.  An exponent past the FP32 range gives
+// exp = inf and S = 0 (1 / inf), exp = 0 gives S = 1.  CHECKED = false drops
+// the tests for empty sentences (every length of the tile is positive).
+template <bool CHECKED>
+static __device__ __forceinline__ float logistic_cell(float dot, float l, float rl, float lt, float rlt,
+                                                      const nwm_scorer &sc, float &sraw) {
+  const float LOG2E = 1.4426950408889634f;
+  float sr = dot * rl;
+  float rho = __uint_as_float(min(__float_as_uint(l * rlt), __float_as_uint(lt * rl)));
+  if (CHECKED) {
+    sr = l > 0.0f ? sr : 0.0f;
+    rho = (l > 0.0f || lt > 0.0f) ? rho : 1.0f;
+  }
+  sraw = sr;
+  const float z = __builtin_fmaf(sc.w0, sr, __builtin_fmaf(sc.w1, rho, sc.b));
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-z * LOG2E));
+}
+
 // Epilogue of a tile: accumulators -> LDS (transpose) -> per row the
 // logistic scorer and coalesced stores of S (and S_raw).
 static __device__ __forceinline__ void score_epilogue(const f32x4 (&acc)[4][4], float *red, const PlanDev &P,
@@ -295,21 +320,11 @@ static __device__ __forceinline__ void score_epilogue(const f32x4 (&acc)[4][4], 
   const float rlt = __builtin_amdgcn_rcpf(lt);
   float *Sp = S + P.s_off[pair];
   float *Rp = S_raw ? S_raw + P.s_off[pair] : nullptr;
-  const float LOG2E = 1.4426950408889634f;
   for (int row = 0; row < rows; ++row) {
     const float dot = red[row * RP + col];
     const float ls = (float)(src_off[s_first + row + 1] - src_off[s_first + row]);
-    const float rls = __builtin_amdgcn_rcpf(ls);
-    // S_raw = dot / l_i (0 for an empty sentence); rho = min / max of lengths,
-    // 1 / max(l_i, l'_j) = min(1 / l_i, 1 / l'_j)
-    const float sraw = ls > 0.0f ? dot * rls : 0.0f;
-    const float mx = fmaxf(ls, lt);
-    const float rho = mx > 0.0f ? fminf(ls, lt) * fminf(rls, rlt) : 1.0f;
-    const float z = __builtin_fmaf(sc.w0, sraw, __builtin_fmaf(sc.w1, rho, sc.b));
-    // sigmoid in the overflow-free form: e = exp(-|z|), S = 1/(1+e) or e/(1+e)
-    const float e = __builtin_amdgcn_exp2f(-fabsf(z) * LOG2E);
-    const float inv = __builtin_amdgcn_rcpf(1.0f + e);
-    const float sv = z >= 0.0f ? inv : e * inv;
+    float sraw;
+    const float sv = logistic_cell<true>(dot, ls, __builtin_amdgcn_rcpf(ls), lt, rlt, sc, sraw);
     if (vcol) {
       const int64_t o = (int64_t)(row0 + row) * m + col0 + col;
       Sp[o] = sv;
@@ -320,7 +335,10 @@ static __device__ __forceinline__ void score_epilogue(const f32x4 (&acc)[4][4], 
 
 // Epilogue straight from the accumulators (no LDS): lane l holds rows
 // 16 bi + 4 (l >> 4) + r, column 16 bj + (l & 15) of the tile.  Sentence
-// lengths come from the lane that owns that row / column index.
+// lengths come from the lane that owns that row / column index.  A full tile
+// whose sentences are all non-empty (the common case) takes a path without
+// per-cell tests whose stores address rows by a scalar offset and columns by
+// the instruction's immediate offset: no address arithmetic per cell.
 static __device__ __forceinline__ void score_epilogue_regs(const f32x4 (&acc)[4][4],
                                                            const int64_t *__restrict__ src_off,
                                                            const int64_t *__restrict__ tgt_off, const nwm_scorer &sc,
@@ -332,12 +350,8 @@ static __device__ __forceinline__ void score_epilogue_regs(const f32x4 (&acc)[4]
   const float my_lt = lane < cols ? (float)(tgt_off[t_first + lane + 1] - tgt_off[t_first + lane]) : 0.0f;
   float *Sp = Sb + (int64_t)row0 * m + col0;
   float *Rp = Rb ? Rb + (int64_t)row0 * m + col0 : nullptr;
-  const float LOG2E = 1.4426950408889634f;
   const int r16 = lane & 15, rq = lane >> 4;
-  // the lengths of this lane's 16 rows and 4 columns and their reciprocals,
-  // once: 1 / max(l_i, l'_j) = min(1 / l_i, 1 / l'_j) (the reciprocal is
-  // decreasing; 1 / 0 = inf leaves the other), so no reciprocal per cell but
-  // the sigmoid's
+  // the lengths of this lane's 16 rows and 4 columns and their reciprocals
   float ls[4][4], rls[4][4], lt[4], rlt[4];
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
@@ -351,6 +365,33 @@ static __device__ __forceinline__ void score_epilogue_regs(const f32x4 (&acc)[4]
     lt[bj] = __shfl(my_lt, 16 * bj + r16, 64);
     rlt[bj] = __builtin_amdgcn_rcpf(lt[bj]);
   }
+  const bool full = rows == TM && cols == TN && __ballot(my_ls > 0.0f && my_lt > 0.0f) == ~0ull;
+  if (full) {
+    const __amdgpu_buffer_rsrc_t rS = __builtin_amdgcn_make_buffer_rsrc((void *)Sp, (short)0, 0x7FFFFFFF, 0x00020000);
+    const uint32_t vbase = (uint32_t)((4 * rq * m + r16) * 4);   // row 4 rq, column r16
+    auto sweep = [&](auto with_raw) {
+      const __amdgpu_buffer_rsrc_t rR =
+          __builtin_amdgcn_make_buffer_rsrc((void *)(Rp ? Rp : Sp), (short)0, 0x7FFFFFFF, 0x00020000);
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int srow = __builtin_amdgcn_readfirstlane((16 * bi + r) * m * 4);   // row offset, bytes
+#pragma unroll
+          for (int bj = 0; bj < 4; ++bj) {
+            float sraw;
+            const float sv =
+                logistic_cell<false>(acc[bi][bj][r], ls[bi][r], rls[bi][r], lt[bj], rlt[bj], sc, sraw);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(sv), rS, vbase + 64u * bj, srow, 0);
+            if (decltype(with_raw)::value)
+              __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(sraw), rR, vbase + 64u * bj, srow, 0);
+          }
+        }
+    };
+    if (Rp) sweep(std::true_type{});
+    else sweep(std::false_type{});
+    return;
+  }
 #pragma unroll
   for (int bj = 0; bj < 4; ++bj) {
     const int col = 16 * bj + r16;
@@ -359,17 +400,8 @@ static __device__ __forceinline__ void score_epilogue_regs(const f32x4 (&acc)[4]
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * bi + 4 * rq + r;
-        const float l = ls[bi][r];
-        const float dot = acc[bi][bj][r];
-        // S_raw = dot / l_i (0 for an empty sentence); rho = min / max of lengths
-        const float sraw = l > 0.0f ? dot * rls[bi][r] : 0.0f;
-        const float mx = fmaxf(l, lt[bj]);
-        const float rho = mx > 0.0f ? fminf(l, lt[bj]) * fminf(rls[bi][r], rlt[bj]) : 1.0f;
-        const float z = __builtin_fmaf(sc.w0, sraw, __builtin_fmaf(sc.w1, rho, sc.b));
-        // sigmoid in the overflow-free form: e = exp(-|z|), S = 1/(1+e) or e/(1+e)
-        const float e = __builtin_amdgcn_exp2f(-fabsf(z) * LOG2E);
-        const float inv = __builtin_amdgcn_rcpf(1.0f + e);
-        const float sv = z >= 0.0f ? inv : e * inv;
+        float sraw;
+        const float sv = logistic_cell<true>(acc[bi][bj][r], ls[bi][r], rls[bi][r], lt[bj], rlt[bj], sc, sraw);
         if (row < rows && col < cols) {
           const int64_t o = (int64_t)row * m + col;
           Sp[o] = sv;
