@@ -186,11 +186,11 @@ nwm_status nwm_align_check(const nwm_plan *plan, const void *ws, int32_t *failed
  * that forbid hipMalloc.  Same arguments, outputs and layouts as
  * nwm_align_batch, without `ws`; it calls no allocating routine.  Its
  * scratch (the DP's queue heads and error flag, the boundary rows handed
- * between the strips of a pair, the fill waves' sink lines) is a fixed
+ * between the strips of a pair) is a fixed
  * device array of the library, 32 MiB on every GPU the library runs on, held
  * until the process ends and reached through its device address, taken once
  * per device by nwm_create.  A plan needs 256 + 8 * (published-row slots +
- * 16400) bytes of it, where a pair of n_b x m_b sentences publishes
+ * 2) bytes of it, where a pair of n_b x m_b sentences publishes
  * (ceil(n_b / 64) - 1) rows of about m_b + 194 slots; larger plans return
  * NWM_EUNSUPPORTED (a batch of 4096 pairs of median 60 sentences needs about
  * 17 MiB).  Every call on a GPU shares that GPU's array and leaves its

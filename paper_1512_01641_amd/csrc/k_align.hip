@@ -23,11 +23,12 @@
 //             (tag TAG_FAIL, so the strips below give up at once instead of
 //             waiting out their own limits) and, in a pair's last strip,
 //             writes NaN as the score; the walk then leaves the pair empty.
-//             S is staged through an LDS ring whose slot index equals the step
-//             index (row r of column c lands in slot c + r), so every lane reads
-//             the same slot and one ds_read_b128 serves four steps; the ring
-//             holds two 32-step groups and is filled a group ahead by
-//             LDS-direct buffer loads (no register holds S).  Each lane packs
+//             S is staged through an LDS ring of three 32-step groups (8 KiB
+//             each: 64 rows x 128 bytes), filled two groups ahead by 16-byte
+//             LDS-direct buffer loads (no register holds S); each lane reads
+//             the four steps of one 16-byte chunk of its own row with one
+//             ds_read_b128, placed so that the lanes of a quarter-wave hit
+//             different banks.  Each lane packs
 //             its 2-bit directions, 16 steps per word, and every 64 steps the
 //             wave writes one coalesced 1 KiB block.  H never reaches HBM.
 // k_nw_reset  clears the published-row region and the queue; scores of
@@ -44,9 +45,9 @@
 
 namespace nwm {
 
-constexpr int PAIR_PITCH = 68;        // ring floats per row pair: 2 x 32 steps + 4 padding
-constexpr int HALF = 32 * PAIR_PITCH;  // ring floats per group of 32 steps (64 rows)
 constexpr int GROUP = 32;             // steps per S staging group
+constexpr int GROUP_FLOATS = 64 * GROUP;   // ring floats per group (64 rows)
+constexpr int RING_GROUPS = 3;        // groups in the S ring: two in flight while one is read
 constexpr int SPIN_LIMIT = 1 << 22;   // default polls before a wave gives up (error flag)
 constexpr uint32_t TAG_FAIL = 2u;     // tag of a boundary value whose producer gave up
 
@@ -78,59 +79,92 @@ static __device__ __forceinline__ T *uniform_ptr(T *p) {
 }
 
 // The parallelogram of S used by steps [GROUP*q, GROUP*q + GROUP): row r,
-// columns GROUP*q - r + [0, GROUP).  It goes straight from memory into ring
-// half (q & 1) by 32 LDS-direct buffer loads, one per row pair (lanes 0..31
-// row 2k, lanes 32..63 row 2k + 1, one step each), so row r of the half
-// starts at float (r >> 1) * PAIR_PITCH + (r & 1) * 32 and step t of the
-// group is float t of the row.  No register holds S.
+// columns GROUP*q - r + [0, GROUP), 128 bytes per row.  It goes straight
+// from memory into one ring slot of 8 KiB by 8 LDS-direct 16-byte buffer
+// loads; load k brings rows 8k .. 8k + 7 into the slot's k-th KiB.  Within
+// that KiB, lane l of the load writes bytes 16 l .. 16 l + 15, so the lane
+// that loads 16-byte chunk c (steps 4c .. 4c + 3) of row 8k + rho is the
+// one that puts it where the reader wants it:
+//    lane = 16 (c >> 1) + ((c + 2 rho + (k & 1)) & 15).
+// Every lane of the reader (lane = row) then reads chunk c of its own row
+// with one ds_read_b128, and the 16 lanes of each quarter-wave fall on 16
+// different 16-byte bank groups (the offset 2 rho + (k & 1) runs over all 16
+// values across two loads' rows).  Two lanes of a load read 32 adjacent
+// bytes of one row.  No register holds S.
 //
-// Lane l of load k reads strip element (2k + h) m + GROUP q + c - 2k - h
-// (h = l >> 5, c = l & 31), i.e. lane_off + k (2m - 2) + GROUP q: one linear
-// address for every group.  A cell outside the strip's m columns (the first
-// steps of a row, the steps after its last column) reads another cell of the
-// strip, or 0 past the strip's end through the buffer range check: a finite
-// value that only the masked steps see, and those leave H unchanged there.
-// Rows at or beyond `rows` (the last strip of a pair) lie past the end.
+// Lane l of load k reads strip bytes 4 (r (m - 1) + GROUP q) + 16 c for its
+// row r = 8k + rho and chunk c: base_{k & 1} + (k >> 1) 64 (m - 1) + 128 q,
+// with the group offset in the VGPR offset so that the range check covers it.
+// A cell outside the strip's m columns (the first steps of a row, the steps
+// after its last column) reads another cell of the strip, or 0 past the
+// strip's end through the buffer range check: a value that only the masked
+// steps see, and those leave H unchanged there.  Rows at or beyond `rows`
+// (the last strip of a pair) lie past the end.  Groups past the strip's
+// last step are loaded from an offset past the range (no memory access), so
+// every group issues the same 8 loads.
 struct StripSrc {
   __amdgpu_buffer_rsrc_t rs;
-  int m, rows;
-  int lane_off;   // bytes: row (lane >> 5), column (lane & 31) - (lane >> 5)
+  uint32_t base0, base1;   // bytes, this lane's (row, chunk) in even and odd loads
+  uint32_t step;           // bytes from load k to load k + 2: 64 (m - 1)
+  int n_groups;            // groups holding steps of the strip
 };
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-#define NWM_S_LOAD_NEXT                 \
-  "s_add_u32 m0, m0, 272\n\t"            \
-  "v_add_u32 %1, %6, %1\n\t"             \
-  "buffer_load_dword %1, %4, %5 offen lds\n\t"
-#define NWM_S_LOAD_NEXT4 NWM_S_LOAD_NEXT NWM_S_LOAD_NEXT NWM_S_LOAD_NEXT NWM_S_LOAD_NEXT
+typedef unsigned int u32x2v __attribute__((ext_vector_type(2)));
+constexpr int CPOL_SC1 = 16;          // cache-policy bit of an agent-coherent access
+constexpr int PUB_NONE = 0x40000000;  // buffer offset past any boundary row: the store is dropped
 
-// The 32 loads of group q, in one asm statement so that the compiler neither
-// reorders them with other memory accesses nor adds waits for them: every
-// read of the ring waits for them with an explicit vmcnt (below).  M0 (the
-// LDS address of a load) is saved, stepped by one row pair (PAIR_PITCH
-// floats) per load and restored; the address VGPR steps by 2m - 2 elements.
-static_assert(PAIR_PITCH * 4 == 272, "ring row-pair pitch");
-static __device__ __forceinline__ void load_group(float *ring, const StripSrc &src, int q) {
-  const uint32_t la = (uint32_t)(uintptr_t)(lds_void *)(ring + (q & 1) * HALF);
-  const int soff = GROUP * q * 4;
-  const uint32_t step = (uint32_t)(2 * src.m - 2) * 4u;
-  uint32_t save, vo;
+// The strip's last row: one tagged 64-bit agent-coherent store per lane into
+// the boundary row `rs` (slot j at byte 8 j).  Every lane issues the store, so
+// each chunk issues the same memory operations; a lane with nothing to
+// publish stores at PUB_NONE, past the buffer's range, and the range check
+// drops it without a memory access.
+static __device__ __forceinline__ void publish(__amdgpu_buffer_rsrc_t rs, bool pub, int j, uint64_t v) {
+  const u32x2v d = {(uint32_t)v, (uint32_t)(v >> 32)};
+  __builtin_amdgcn_raw_buffer_store_b64(d, rs, pub ? 8 * j : PUB_NONE, 0, CPOL_SC1);
+}
+
+constexpr uint32_t S_NONE = 0x40000000u;   // buffer offset past any strip (S stays below 1 GiB per strip)
+
+// The lane's two byte bases (see StripSrc): row rho_b of load b and chunk c_b,
+// inverting lane = 16 (c >> 1) + ((c + 2 rho + b) & 15).
+static __device__ __forceinline__ uint32_t s_lane_base(int lane, int b, int m) {
+  const int v = lane & 15;
+  const int c = 2 * (lane >> 4) + ((v - b) & 1);
+  const int rho = ((v - b - c) & 15) >> 1;
+  return (uint32_t)(8 * b + rho) * (uint32_t)(m - 1) * 4u + 16u * (uint32_t)c;
+}
+
+#define NWM_S_LOAD(A)                               \
+  "buffer_load_dwordx4 " A ", %7, 0 offen lds\n\t"  \
+  "s_add_u32 m0, m0, 1024\n\t"                      \
+  "v_add_u32 " A ", %8, " A "\n\t"
+#define NWM_S_LOAD2 NWM_S_LOAD("%1") NWM_S_LOAD("%2")
+
+// The 8 loads of group q into ring slot `slot`, in one asm statement so that
+// the compiler neither reorders them with other memory accesses nor adds
+// waits for them: every read of the ring waits for them with an explicit
+// vmcnt (below).  M0 (the LDS address of a load) is saved, stepped by 1 KiB
+// per load and restored; a VALU instruction separates each M0 write from the
+// load that uses it.
+static __device__ __forceinline__ void load_group(float *ring, const StripSrc &src, int q, int slot) {
+  const uint32_t la = (uint32_t)uniform((int)(uint32_t)(uintptr_t)(lds_void *)(ring + slot * GROUP_FLOATS));
+  const uint32_t goff = (uint32_t)uniform(q < src.n_groups ? (int)(GROUP * 4 * q) : (int)S_NONE);
+  uint32_t save, a0, a1;
   asm volatile(
       "s_mov_b32 %0, m0\n\t"
-      "s_mov_b32 m0, %2\n\t"
-      "v_mov_b32 %1, %3\n\t"
-      "buffer_load_dword %1, %4, %5 offen lds\n\t"
-      NWM_S_LOAD_NEXT NWM_S_LOAD_NEXT NWM_S_LOAD_NEXT
-      NWM_S_LOAD_NEXT4 NWM_S_LOAD_NEXT4 NWM_S_LOAD_NEXT4 NWM_S_LOAD_NEXT4
-      NWM_S_LOAD_NEXT4 NWM_S_LOAD_NEXT4 NWM_S_LOAD_NEXT4
+      "s_mov_b32 m0, %3\n\t"
+      "v_add_u32 %1, %6, %4\n\t"
+      "v_add_u32 %2, %6, %5\n\t"
+      NWM_S_LOAD2 NWM_S_LOAD2 NWM_S_LOAD2 NWM_S_LOAD2
       "s_mov_b32 m0, %0"
-      : "=&s"(save), "=&v"(vo)
-      : "s"(la), "v"(src.lane_off), "s"(src.rs), "s"(soff), "s"(step)
+      : "=&s"(save), "=&v"(a0), "=&v"(a1)
+      : "s"(la), "v"(src.base0), "v"(src.base1), "s"(goff), "s"(src.rs), "s"(src.step)
       : "memory", "scc");
 }
-#undef NWM_S_LOAD_NEXT4
-#undef NWM_S_LOAD_NEXT
+#undef NWM_S_LOAD2
+#undef NWM_S_LOAD
 
 // One 16-byte agent-coherent (sc1) LDS-direct load per active lane: lane l
 // writes bytes 16 l .. 16 l + 15 of buf.  Written as asm for the same reason
@@ -225,15 +259,20 @@ static __device__ __forceinline__ void run16v(StripState &st, const float4 (&sv)
   st.bits = bits;
 }
 
-// The 16 S values of lane `lane` for the steps [t0, t0 + 16) from the LDS ring.
+// The float offset, within a ring slot, of chunk c (steps 4c .. 4c + 3) of
+// row `lane` (see StripSrc).
+static __device__ __forceinline__ uint32_t chunk_off(int lane, int c) {
+  return (uint32_t)(256 * (lane >> 3) + 4 * (16 * (c >> 1) + ((c + 2 * (lane & 7) + ((lane >> 3) & 1)) & 15)));
+}
+
+// The 16 S values of lane `lane` for the steps [t0, t0 + 16) from the ring
+// slot `grp`; `off` holds the lane's offsets of the four chunks.
 template <bool MASKED, bool MAX3>
-static __device__ __forceinline__ void run16(StripState &st, const float *ring, int t0, int m, float g,
-                                             int lane) {
+static __device__ __forceinline__ void run16(StripState &st, const float *grp, const uint32_t (&off)[4], int t0,
+                                             int m, float g, int lane) {
   float4 sv[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-    sv[q] = *reinterpret_cast<const float4 *>(ring + ((t0 >> 5) & 1) * HALF + (lane >> 1) * PAIR_PITCH +
-                                               (lane & 1) * 32 + (t0 & 31) + 4 * q);
+  for (int q = 0; q < 4; ++q) sv[q] = *reinterpret_cast<const float4 *>(grp + off[q]);
   run16v<MASKED, MAX3>(st, sv, t0, m, g, lane);
 }
 
@@ -264,13 +303,20 @@ __global__ __launch_bounds__(256) void k_nw_reset(FillArgs A, uint4 *__restrict_
 template <bool MAX3>
 __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restrict__ S, float g,
                                                 float *__restrict__ score, char *__restrict__ tb,
-                                                uint64_t *__restrict__ bnd, uint64_t *__restrict__ sink,
-                                                int32_t *__restrict__ head, int32_t *__restrict__ err) {
+                                                uint64_t *__restrict__ bnd, int32_t *__restrict__ head,
+                                                int32_t *__restrict__ err) {
   constexpr uint32_t epoch = 1u;   // tag of a published value (the reset clears to 0)
-  __shared__ __align__(16) float ring[2 * HALF];
-  __shared__ __align__(16) uint64_t winbufA[64], winbufB[64];   // boundary windows (LDS-direct loads)
+  __shared__ __align__(16) float ring[RING_GROUPS * GROUP_FLOATS];
+  __shared__ __align__(16) uint64_t winbufA[32], winbufB[32];   // boundary windows (LDS-direct loads)
   const int lane = threadIdx.x;
-  uint64_t *my_sink = sink + (int64_t)(blockIdx.x & (FILL_SINK_WAVES - 1)) * 16;   // this wave's line
+  // this lane's ring offsets of the four chunks of the first and second
+  // 16 steps of a group
+  uint32_t offA[4], offB[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    offA[c] = chunk_off(lane, c);
+    offB[c] = chunk_off(lane, c + 4);
+  }
   for (;;) {
     int item = 0;
     if (lane == 0) item = atomicAdd(head, 1);
@@ -299,12 +345,17 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     const int r_last = n - 1 - i0;   // lane of row n in the last strip
     bool failed = false;
 
+    // slots 1..m of this strip's published row (nothing when it is the last)
+    const __amdgpu_buffer_rsrc_t pub_rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)uniform_ptr(out_row), (short)0, last ? 0 : uniform((m + 1) * 8), 0x00020000);
+
     StripSrc src;
     src.rs = __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(Sb + (int64_t)i0 * m), (short)0,
                                                uniform(rows * m * 4), 0x00020000);
-    src.m = m;
-    src.rows = rows;
-    src.lane_off = ((lane >> 5) * m + (lane & (GROUP - 1)) - (lane >> 5)) * 4;
+    src.base0 = s_lane_base(lane, 0, m);
+    src.base1 = s_lane_base(lane, 1, m);
+    src.step = (uint32_t)uniform(64 * (m - 1));
+    src.n_groups = (T_pad + GROUP - 1) / GROUP;
 
     StripState st;
     const int i = i0 + 1 + lane;
@@ -314,12 +365,9 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     st.bits = 0u;
     st.pw = 0.0f;
 
-    // S ring prologue: groups 0 and 1 in flight.  The pair's offsets are
-    // pinned in scalar registers first: a wait for them placed after the
-    // prologue would also wait for its 64 loads.
+    // The pair's offsets are pinned in scalar registers before the S
+    // prologue: a wait for them placed after it would also wait for its loads.
     asm volatile("" ::"s"(bnd_off), "s"(tb_off));
-    load_group(ring, src, 0);
-    load_group(ring, src, 1);
 
     // Boundary window prev[tw + 1 + lane]: the first row, or the previous
     // strip's last row published by another wave.  Every published value is
@@ -345,9 +393,13 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
           : "memory");
       return v;
     };
+    // lanes 0..8 bring slots tw .. tw + 17 (16 bytes each), which hold the
+    // 16 values a chunk uses
     auto prefetch_window = [&](int tw, uint64_t *buf) {
-      if (lane < 32) load_window_lds(buf, in_row + tw + 2 * lane);
+      if (lane < 9) load_window_lds(buf, in_row + tw + 2 * lane);
     };
+    // slot tw + 1 + lane of a window buffer (lanes 0..15 matter)
+    const int wslot = 1 + (lane & 15);
     // lanes 0..15 feed the next 16 steps; columns beyond m are never used
     auto window_need = [&](int tw) -> bool { return lane < 16 && tw + 1 + lane <= m; };
     auto window_ready = [&](uint64_t v, int tw) -> bool {
@@ -374,20 +426,17 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
       return v;
     };
     // One chunk of 16 steps from its boundary window.  The publish of the
-    // strip's last row is one unconditional store (lanes with nothing to
-    // publish write the wave's own sink line), so every chunk issues the same
-    // memory operations and the explicit wait counts stay exact.
-    auto chunk = [&](int t0, uint64_t win) {
+    // strip's last row is one store instruction in every chunk (see
+    // publish), so the explicit wait counts stay exact.
+    auto chunk = [&](int t0, uint64_t win, const float *grp, const uint32_t(&off)[4]) {
       st.pw = s > 0 ? __uint_as_float((uint32_t)win) : (float)(t0 + 1 + lane) * g;
-      if (t0 < 64 || t0 + 16 > m) run16<true, MAX3>(st, ring, t0, m, g, lane);
-      else run16<false, MAX3>(st, ring, t0, m, g, lane);
+      if (t0 < 64 || t0 + 16 > m) run16<true, MAX3>(st, grp, off, t0, m, g, lane);
+      else run16<false, MAX3>(st, grp, off, t0, m, g, lane);
       // lane l of the collector holds H of row 64 at step t0 + 15 - 63 + l,
       // i.e. column t0 - 110 + l; lanes 48.. publish
       const int j = t0 - 110 + lane;
       const bool pub = !last && lane >= 48 && j >= 1 && j <= m && !(A.hold && s == 0);
-      uint64_t *dst = pub ? out_row + j : my_sink + (lane & 15);
-      __hip_atomic_store(dst, ((uint64_t)epoch << 32) | __float_as_uint(st.col), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      publish(pub_rs, pub, j, ((uint64_t)epoch << 32) | __float_as_uint(st.col));
       return st.bits;
     };
 
@@ -395,38 +444,44 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     // memory operations: [chunk A: window of the next group's A, publish]
     // [chunk B: window of the next group's B, publish] [direction words of
     // the group: one 8-byte store, half of the block's 16-byte word] [S of
-    // the group after next: 32 loads into the half just consumed].  A window
-    // is therefore followed by exactly 36 memory operations when its chunk
-    // comes (1 and 2 in the first group, whose windows the prologue issued
-    // last), which is the vmcnt it waits for.  The window of chunk A was
-    // issued after the S of its group, so its wait also covers the ring;
-    // without windows (first strip) the ring's own wait is 35 operations (32
-    // in the first group).  A drained counter (after a reload) only makes a
-    // wait shorter.
+    // the group RING_GROUPS ahead: 8 loads into the slot just consumed].  The
+    // prologue issues S of group 0, the first two windows, then S of groups
+    // 1 and 2.  A window is therefore followed by exactly 12 memory
+    // operations when its chunk comes (17 and 18 in the first group), which
+    // is the vmcnt it waits for; a group's S was issued before the window of
+    // its chunk A, so that wait also covers the ring.  Without windows (first
+    // strip) the ring's own wait is 16, 19, then 22 operations.  A drained
+    // counter (after a reload) only makes a wait shorter.
+    static_assert(RING_GROUPS == 3, "wait counts below assume three ring groups");
+    load_group(ring, src, 0, 0);
     if (s > 0) {
       prefetch_window(0, winbufA);
       prefetch_window(16, winbufB);
     }
+    load_group(ring, src, 1, 1);
+    load_group(ring, src, 2, 2);
     uint2 *tbh = reinterpret_cast<uint2 *>(tbs);
     int t0 = 0;
-    bool first = true;
+    int slot = 0;   // ring slot of the group at t0
     auto take_window = [&](int tw, const uint64_t *buf, int ahead) -> uint64_t {
       // ahead: memory operations issued after this window's load
-      if (ahead == 36) asm volatile("s_waitcnt vmcnt(36)" ::: "memory");
-      else if (ahead == 2) asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
-      else asm volatile("s_waitcnt vmcnt(1)" ::: "memory");
-      uint64_t v = buf[1 + lane];   // slot tw + 1 + lane (lanes 0..15 matter)
+      if (ahead == 12) asm volatile("s_waitcnt vmcnt(12)" ::: "memory");
+      else if (ahead == 17) asm volatile("s_waitcnt vmcnt(17)" ::: "memory");
+      else asm volatile("s_waitcnt vmcnt(18)" ::: "memory");
+      uint64_t v = buf[wslot];
       if (!window_ready(v, tw)) v = wait_window(tw, v);
       return v;
     };
-    // the ring half of the group at t0 has landed (chunk A of a group)
+    // the ring slot of the group at t0 has landed (chunk A of a group)
     auto take_group = [&]() -> uint64_t {
-      if (s > 0) return take_window(t0, winbufA, first ? 1 : 36);
-      if (first) asm volatile("s_waitcnt vmcnt(32)" ::: "memory");
-      else asm volatile("s_waitcnt vmcnt(35)" ::: "memory");
+      if (s > 0) return take_window(t0, winbufA, t0 == 0 ? 17 : 12);
+      if (t0 == 0) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+      else if (t0 == GROUP) asm volatile("s_waitcnt vmcnt(19)" ::: "memory");
+      else asm volatile("s_waitcnt vmcnt(22)" ::: "memory");
       return 0ull;
     };
     for (; t0 + 32 <= T_pad; t0 += 32) {
+      const float *grp = ring + slot * GROUP_FLOATS;
       uint64_t wb = 0ull;
       const uint64_t wa = take_group();
       if (s > 0) {
@@ -434,25 +489,25 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
         prefetch_window(t0 + 32, winbufA);
       }
       if (failed) break;
-      const uint32_t bitsA = chunk(t0, wa);
+      const uint32_t bitsA = chunk(t0, wa, grp, offA);
       if (s > 0) {
-        wb = take_window(t0 + 16, winbufB, first ? 2 : 36);
+        wb = take_window(t0 + 16, winbufB, t0 == 0 ? 18 : 12);
         __builtin_amdgcn_s_waitcnt(0xc07f);
         prefetch_window(t0 + 48, winbufB);
       }
       if (failed) break;
-      const uint32_t bitsB = chunk(t0 + 16, wb);
+      const uint32_t bitsB = chunk(t0 + 16, wb, grp, offB);
       tbh[((t0 >> 6) * 64 + lane) * 2 + ((t0 >> 5) & 1)] = make_uint2(bitsA, bitsB);
       // every ring read of this group has returned (lgkmcnt(0)) before its
-      // half is refilled with the group after next
+      // slot is refilled with the group RING_GROUPS ahead
       __builtin_amdgcn_s_waitcnt(0xc07f);
-      load_group(ring, src, t0 / GROUP + 2);
-      first = false;
+      load_group(ring, src, t0 / GROUP + RING_GROUPS, slot);
+      slot = slot == RING_GROUPS - 1 ? 0 : slot + 1;
     }
     if (t0 < T_pad && !failed) {   // a last single chunk
       const uint64_t wa = take_group();
       if (!failed) {
-        const uint32_t bitsA = chunk(t0, wa);
+        const uint32_t bitsA = chunk(t0, wa, ring + slot * GROUP_FLOATS, offA);
         tbh[((t0 >> 6) * 64 + lane) * 2 + ((t0 >> 5) & 1)] = make_uint2(bitsA, 0u);
       }
     }
@@ -496,11 +551,10 @@ static __device__ __forceinline__ void load_s16(float4 (&d)[4], __amdgpu_buffer_
 template <bool MAX3>
 __global__ __launch_bounds__(64) void k_nw_fill_r(FillArgs A, const float *__restrict__ S, float g,
                                                   float *__restrict__ score, char *__restrict__ tb,
-                                                  uint64_t *__restrict__ bnd, uint64_t *__restrict__ sink,
-                                                  int32_t *__restrict__ head, int32_t *__restrict__ err) {
+                                                  uint64_t *__restrict__ bnd, int32_t *__restrict__ head,
+                                                  int32_t *__restrict__ err) {
   constexpr uint32_t epoch = 1u;   // tag of a published value (the reset clears to 0)
   const int lane = threadIdx.x;
-  uint64_t *my_sink = sink + (int64_t)(blockIdx.x & (FILL_SINK_WAVES - 1)) * 16;   // this wave's line
   for (;;) {
     int item = 0;
     if (lane == 0) item = atomicAdd(head, 1);
@@ -530,6 +584,8 @@ __global__ __launch_bounds__(64) void k_nw_fill_r(FillArgs A, const float *__res
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         (void *)uniform_ptr(Sb + (int64_t)i0 * m), (short)0, uniform(rows * m * 4), 0x00020000);
     const uint32_t lo = (uint32_t)lane * (uint32_t)(m - 1) * 4u;
+    const __amdgpu_buffer_rsrc_t pub_rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)uniform_ptr(out_row), (short)0, last ? 0 : uniform((m + 1) * 8), 0x00020000);
 
     StripState st;
     const int i = i0 + 1 + lane;
@@ -588,9 +644,7 @@ __global__ __launch_bounds__(64) void k_nw_fill_r(FillArgs A, const float *__res
     {                                                                                              \
       const int j = t0 - 110 + lane;                                                               \
       const bool pub = !last && lane >= 48 && j >= 1 && j <= m && !(A.hold && s == 0);             \
-      uint64_t *dst = pub ? out_row + j : my_sink + (lane & 15);                                   \
-      __hip_atomic_store(dst, ((uint64_t)epoch << 32) | __float_as_uint(st.col), __ATOMIC_RELAXED,  \
-                         __HIP_MEMORY_SCOPE_AGENT);                                                \
+      publish(pub_rs, pub, j, ((uint64_t)epoch << 32) | __float_as_uint(st.col));                  \
     }                                                                                              \
     tbw[((t0 >> 6) * 64 + lane) * 4 + ((t0 >> 4) & 3)] = st.bits;                                  \
     t0 += 16;                                                                                      \
@@ -864,20 +918,18 @@ hipError_t launch_nw_fill_items(const PlanDev &P, const float *S, float g, float
   const int per = (waves_per_cu > 0 && waves_per_cu < fit) ? waves_per_cu : fit;
   const int full = g_fill_cus * per;
   const int grid = n < full ? n : full;
-  // the sink: FILL_SINK_WAVES 128-byte lines after the published rows
-  uint64_t *sink = reinterpret_cast<uint64_t *>((reinterpret_cast<uintptr_t>(bnd + n_bnd) + 127) & ~(uintptr_t)127);
   // a gap of -0 keeps the compare chain (see run16v)
   const bool max3 = !(g == 0.0f && std::signbit(g));
   if (staging) {
     if (max3)
-      hipLaunchKernelGGL(k_nw_fill_r<true>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, sink, head, err);
+      hipLaunchKernelGGL(k_nw_fill_r<true>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, head, err);
     else
-      hipLaunchKernelGGL(k_nw_fill_r<false>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, sink, head, err);
+      hipLaunchKernelGGL(k_nw_fill_r<false>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, head, err);
   } else {
     if (max3)
-      hipLaunchKernelGGL(k_nw_fill<true>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, sink, head, err);
+      hipLaunchKernelGGL(k_nw_fill<true>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, head, err);
     else
-      hipLaunchKernelGGL(k_nw_fill<false>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, sink, head, err);
+      hipLaunchKernelGGL(k_nw_fill<false>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, head, err);
   }
   return hipGetLastError();
 }

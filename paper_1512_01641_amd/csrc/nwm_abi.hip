@@ -100,8 +100,8 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 }  // namespace
 
 // Device scratch of nwm_align_batch_noalloc: the DP's queue heads and error
-// flag (first 256 bytes), then the published boundary rows between strips and
-// the fill waves' sink lines.  Every GPU the library runs on holds its own
+// flag (first 256 bytes), then the published boundary rows between strips.
+// Every GPU the library runs on holds its own
 // copy until the process ends; the host reaches it only through the address
 // hipGetSymbolAddress gives on that device (the array's name in host code is
 // not a device address).
@@ -588,8 +588,8 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   W.b_base = carve(8 * (size_t)D.n_ct);
   W.p_voc = carve(4 * (size_t)B * (size_t)nch);
   W.bwd = carve(16 * ((size_t)B + (size_t)D.n_rt));
-  // published rows, + 2 entries (cleared in 16-byte units), + the sink
-  W.bnd = carve(8 * ((size_t)bnd_off[B] + 2 + FILL_SINK_SLOTS));
+  // published rows, + 2 entries (cleared in 16-byte units)
+  W.bnd = carve(8 * ((size_t)bnd_off[B] + 2));
   p->n_bnd = bnd_off[B] + 2;
   W.ctl = carve(16);
   W.total = o;
@@ -864,8 +864,8 @@ nwm_status nwm_align_batch_noalloc(nwm_plan *p, const float *S, float gap, float
   if (!score || !n_diag || !n_kept) return NWM_EINVAL;
   if (p->sizes.S_elems > 0 && !S) return NWM_EINVAL;
   if (p->sizes.kept_cap > 0 && (!kept || !tb)) return NWM_EINVAL;
-  // [256 B: queue heads, error flag][published rows][sink lines (128-byte aligned)]
-  const size_t need = 256 + 8 * ((size_t)p->n_bnd + FILL_SINK_SLOTS);
+  // [256 B: queue heads, error flag][published rows]
+  const size_t need = 256 + 8 * (size_t)p->n_bnd;
   if (need > NOALLOC_SCRATCH_BYTES) return NWM_EUNSUPPORTED;
   char *base = static_cast<char *>(scratch_ptr(p->device));
   if (!base) return NWM_EDEVICE;

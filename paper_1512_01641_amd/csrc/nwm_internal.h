@@ -40,11 +40,6 @@ constexpr int MAX_DEG = 64;           // dictionary entries per word
 constexpr int BND_PAD = 192;          // slack slots after each published boundary row
 // slots per published boundary row: even, so every row starts 16-byte aligned
 __host__ __device__ inline int64_t bnd_stride(int m) { return ((int64_t)m + BND_PAD + 1) & ~(int64_t)1; }
-// Fill waves with nothing to publish in a chunk write a private 128-byte
-// sink line instead (written, never read); waves beyond FILL_SINK_WAVES share
-// lines.  The sink follows the published rows, 128-byte aligned.
-constexpr int FILL_SINK_WAVES = 1024;
-constexpr int64_t FILL_SINK_SLOTS = (int64_t)FILL_SINK_WAVES * 16 + 16;   // uint64 entries, incl. alignment slack
 constexpr int MAX_M = 1 << 22;           // target sentences per pair (a 64-row strip of S stays below 1 GiB)
 constexpr int32_t ITEM_HOT = 1 << 30;   // DP item flag: strip of a critical-chain pair
 // Steps a strip trails the strip above it (the 63-step skew of a 64-row
