@@ -442,15 +442,16 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
 
     // Two chunks (one group of 32 steps) per iteration, in a fixed order of
     // memory operations: [chunk A: window of the next group's A, publish]
-    // [chunk B: window of the next group's B, publish] [direction words of
-    // the group: one 8-byte store, half of the block's 16-byte word] [S of
-    // the group RING_GROUPS ahead: 8 loads into the slot just consumed].  The
-    // prologue issues S of group 0, the first two windows, then S of groups
-    // 1 and 2.  A window is therefore followed by exactly 12 memory
-    // operations when its chunk comes (17 and 18 in the first group), which
-    // is the vmcnt it waits for; a group's S was issued before the window of
-    // its chunk A, so that wait also covers the ring.  Without windows (first
-    // strip) the ring's own wait is 16, 19, then 22 operations.  A drained
+    // [chunk B: window of the next group's B, publish] [odd groups only: the
+    // direction words of this group and the one before, one 16-byte store
+    // per lane, 1 KiB per wave] [S of the group RING_GROUPS ahead: 8 loads
+    // into the slot just consumed].  The prologue issues S of group 0, the
+    // first two windows, then S of groups 1 and 2.  A window is therefore
+    // followed by exactly 11 memory operations when its chunk comes, 12 when
+    // the group before was odd (17 and 18 in the first group), which is the
+    // vmcnt it waits for; a group's S was issued before the window of its
+    // chunk A, so that wait also covers the ring.  Without windows (first
+    // strip) the ring's own wait is 16, 18, then 21 operations.  A drained
     // counter (after a reload) only makes a wait shorter.
     static_assert(RING_GROUPS == 3, "wait counts below assume three ring groups");
     load_group(ring, src, 0, 0);
@@ -460,12 +461,13 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     }
     load_group(ring, src, 1, 1);
     load_group(ring, src, 2, 2);
-    uint2 *tbh = reinterpret_cast<uint2 *>(tbs);
+    uint32_t keepA = 0u, keepB = 0u;   // directions of an even group, stored with the next
     int t0 = 0;
     int slot = 0;   // ring slot of the group at t0
     auto take_window = [&](int tw, const uint64_t *buf, int ahead) -> uint64_t {
       // ahead: memory operations issued after this window's load
-      if (ahead == 12) asm volatile("s_waitcnt vmcnt(12)" ::: "memory");
+      if (ahead == 11) asm volatile("s_waitcnt vmcnt(11)" ::: "memory");
+      else if (ahead == 12) asm volatile("s_waitcnt vmcnt(12)" ::: "memory");
       else if (ahead == 17) asm volatile("s_waitcnt vmcnt(17)" ::: "memory");
       else asm volatile("s_waitcnt vmcnt(18)" ::: "memory");
       uint64_t v = buf[wslot];
@@ -473,11 +475,13 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
       return v;
     };
     // the ring slot of the group at t0 has landed (chunk A of a group)
+    // operations after the window of a chunk of the group at t0 > 0
+    auto ahead_of = [&]() -> int { return ((t0 >> 5) & 1) ? 11 : 12; };
     auto take_group = [&]() -> uint64_t {
-      if (s > 0) return take_window(t0, winbufA, t0 == 0 ? 17 : 12);
+      if (s > 0) return take_window(t0, winbufA, t0 == 0 ? 17 : ahead_of());
       if (t0 == 0) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
-      else if (t0 == GROUP) asm volatile("s_waitcnt vmcnt(19)" ::: "memory");
-      else asm volatile("s_waitcnt vmcnt(22)" ::: "memory");
+      else if (t0 == GROUP) asm volatile("s_waitcnt vmcnt(18)" ::: "memory");
+      else asm volatile("s_waitcnt vmcnt(21)" ::: "memory");
       return 0ull;
     };
     for (; t0 + 32 <= T_pad; t0 += 32) {
@@ -491,13 +495,18 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
       if (failed) break;
       const uint32_t bitsA = chunk(t0, wa, grp, offA);
       if (s > 0) {
-        wb = take_window(t0 + 16, winbufB, t0 == 0 ? 18 : 12);
+        wb = take_window(t0 + 16, winbufB, t0 == 0 ? 18 : ahead_of());
         __builtin_amdgcn_s_waitcnt(0xc07f);
         prefetch_window(t0 + 48, winbufB);
       }
       if (failed) break;
       const uint32_t bitsB = chunk(t0 + 16, wb, grp, offB);
-      tbh[((t0 >> 6) * 64 + lane) * 2 + ((t0 >> 5) & 1)] = make_uint2(bitsA, bitsB);
+      if ((t0 >> 5) & 1) {
+        tbs[(t0 >> 6) * 64 + lane] = make_uint4(keepA, keepB, bitsA, bitsB);
+      } else {
+        keepA = bitsA;
+        keepB = bitsB;
+      }
       // every ring read of this group has returned (lgkmcnt(0)) before its
       // slot is refilled with the group RING_GROUPS ahead
       __builtin_amdgcn_s_waitcnt(0xc07f);
@@ -508,8 +517,12 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
       const uint64_t wa = take_group();
       if (!failed) {
         const uint32_t bitsA = chunk(t0, wa, ring + slot * GROUP_FLOATS, offA);
-        tbh[((t0 >> 6) * 64 + lane) * 2 + ((t0 >> 5) & 1)] = make_uint2(bitsA, 0u);
+        tbs[(t0 >> 6) * 64 + lane] =
+            ((t0 >> 5) & 1) ? make_uint4(keepA, keepB, bitsA, 0u) : make_uint4(bitsA, 0u, 0u, 0u);
       }
+    } else if (!failed && ((t0 >> 5) & 1)) {
+      // the last group was even: its directions are still held
+      tbs[((t0 - GROUP) >> 6) * 64 + lane] = make_uint4(keepA, keepB, 0u, 0u);
     }
     // no LDS-direct load may still be writing LDS when the next item starts
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
