@@ -22,7 +22,7 @@ SPACE = {
     "dp_hot_percent": [50, 0, 25, 75],
     # tile shape of the compacted contraction: K words per round (32 or 64)
     "score_kgroup": [1, 2],
-    # S staging tile of the NW fill: LDS ring of 64 x 32 cells, or 16 cells
+    # S staging tile of the NW fill: LDS ring of 64 x 64 cells, or 16 cells
     # per lane in registers
     "fill_staging": [0, 1],
     # source-side expansion: one fused kernel per row tile, or merge + list build

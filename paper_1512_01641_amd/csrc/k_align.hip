@@ -23,8 +23,8 @@
 //             (tag TAG_FAIL, so the strips below give up at once instead of
 //             waiting out their own limits) and, in a pair's last strip,
 //             writes NaN as the score; the walk then leaves the pair empty.
-//             S is staged through an LDS ring of three 32-step groups (8 KiB
-//             each: 64 rows x 128 bytes), filled two groups ahead by 16-byte
+//             S is staged through an LDS ring of two 64-step groups (16 KiB
+//             each: 64 rows x 256 bytes), filled a group ahead by 16-byte
 //             LDS-direct buffer loads (no register holds S); each lane reads
 //             the four steps of one 16-byte chunk of its own row with one
 //             ds_read_b128, placed so that the lanes of a quarter-wave hit
@@ -45,9 +45,9 @@
 
 namespace nwm {
 
-constexpr int GROUP = 32;             // steps per S staging group
-constexpr int GROUP_FLOATS = 64 * GROUP;   // ring floats per group (64 rows)
-constexpr int RING_GROUPS = 3;        // groups in the S ring: two in flight while one is read
+constexpr int GROUP = 64;             // steps per S staging group (four chunks of 16)
+constexpr int GROUP_FLOATS = 64 * GROUP;   // ring floats per group (64 rows x 256 bytes)
+constexpr int RING_GROUPS = 2;        // groups in the S ring: one in flight while one is read
 constexpr int SPIN_LIMIT = 1 << 22;   // default polls before a wave gives up (error flag)
 constexpr uint32_t TAG_FAIL = 2u;     // tag of a boundary value whose producer gave up
 
@@ -79,21 +79,21 @@ static __device__ __forceinline__ T *uniform_ptr(T *p) {
 }
 
 // The parallelogram of S used by steps [GROUP*q, GROUP*q + GROUP): row r,
-// columns GROUP*q - r + [0, GROUP), 128 bytes per row.  It goes straight
-// from memory into one ring slot of 8 KiB by 8 LDS-direct 16-byte buffer
-// loads; load k brings rows 8k .. 8k + 7 into the slot's k-th KiB.  Within
+// columns GROUP*q - r + [0, GROUP), 256 bytes per row.  It goes straight
+// from memory into one ring slot of 16 KiB by 16 LDS-direct 16-byte buffer
+// loads; load k brings rows 4k .. 4k + 3 into the slot's k-th KiB.  Within
 // that KiB, lane l of the load writes bytes 16 l .. 16 l + 15, so the lane
-// that loads 16-byte chunk c (steps 4c .. 4c + 3) of row 8k + rho is the
+// that loads 16-byte chunk c (steps 4c .. 4c + 3) of row 4k + rho is the
 // one that puts it where the reader wants it:
-//    lane = 16 (c >> 1) + ((c + 2 rho + (k & 1)) & 15).
+//    lane = 16 rho + ((c + 4 (k & 3) + rho) & 15).
 // Every lane of the reader (lane = row) then reads chunk c of its own row
-// with one ds_read_b128, and the 16 lanes of each quarter-wave fall on 16
-// different 16-byte bank groups (the offset 2 rho + (k & 1) runs over all 16
-// values across two loads' rows).  Two lanes of a load read 32 adjacent
-// bytes of one row.  No register holds S.
+// with one ds_read_b128, and the 16 lanes of each quarter-wave (rows
+// 16p + j) fall on 16 different 16-byte bank groups ((c + j) & 15).  The 16
+// lanes of a load that share rho read one row's 256 contiguous bytes.  No
+// register holds S.
 //
 // Lane l of load k reads strip bytes 4 (r (m - 1) + GROUP q) + 16 c for its
-// row r = 8k + rho and chunk c: base_{k & 1} + (k >> 1) 64 (m - 1) + 128 q,
+// row r = 4k + rho and chunk c: base_{k & 3} + (k >> 2) 64 (m - 1) + 256 q,
 // with the group offset in the VGPR offset so that the range check covers it.
 // A cell outside the strip's m columns (the first steps of a row, the steps
 // after its last column) reads another cell of the strip, or 0 past the
@@ -101,11 +101,11 @@ static __device__ __forceinline__ T *uniform_ptr(T *p) {
 // steps see, and those leave H unchanged there.  Rows at or beyond `rows`
 // (the last strip of a pair) lie past the end.  Groups past the strip's
 // last step are loaded from an offset past the range (no memory access), so
-// every group issues the same 8 loads.
+// every group issues the same 16 loads.
 struct StripSrc {
   __amdgpu_buffer_rsrc_t rs;
-  uint32_t base0, base1;   // bytes, this lane's (row, chunk) in even and odd loads
-  uint32_t step;           // bytes from load k to load k + 2: 64 (m - 1)
+  uint32_t base[4];        // bytes, this lane's (row, chunk) in loads 0..3
+  uint32_t step;           // bytes from load k to load k + 4: 64 (m - 1)
   int n_groups;            // groups holding steps of the strip
 };
 
@@ -127,22 +127,21 @@ static __device__ __forceinline__ void publish(__amdgpu_buffer_rsrc_t rs, bool p
 
 constexpr uint32_t S_NONE = 0x40000000u;   // buffer offset past any strip (S stays below 1 GiB per strip)
 
-// The lane's two byte bases (see StripSrc): row rho_b of load b and chunk c_b,
-// inverting lane = 16 (c >> 1) + ((c + 2 rho + b) & 15).
-static __device__ __forceinline__ uint32_t s_lane_base(int lane, int b, int m) {
-  const int v = lane & 15;
-  const int c = 2 * (lane >> 4) + ((v - b) & 1);
-  const int rho = ((v - b - c) & 15) >> 1;
-  return (uint32_t)(8 * b + rho) * (uint32_t)(m - 1) * 4u + 16u * (uint32_t)c;
+// The lane's byte base for load j < 4 (see StripSrc): row rho of the load
+// and chunk c, inverting lane = 16 rho + ((c + 4 j + rho) & 15).
+static __device__ __forceinline__ uint32_t s_lane_base(int lane, int j, int m) {
+  const int rho = lane >> 4;
+  const int c = ((lane & 15) - 4 * j - rho) & 15;
+  return (uint32_t)(4 * j + rho) * (uint32_t)(m - 1) * 4u + 16u * (uint32_t)c;
 }
 
 #define NWM_S_LOAD(A)                               \
-  "buffer_load_dwordx4 " A ", %7, 0 offen lds\n\t"  \
+  "buffer_load_dwordx4 " A ", %9, 0 offen lds\n\t"  \
   "s_add_u32 m0, m0, 1024\n\t"                      \
-  "v_add_u32 " A ", %8, " A "\n\t"
-#define NWM_S_LOAD2 NWM_S_LOAD("%1") NWM_S_LOAD("%2")
+  "v_add_u32 " A ", %10, " A "\n\t"
+#define NWM_S_LOAD4 NWM_S_LOAD("%1") NWM_S_LOAD("%2") NWM_S_LOAD("%3") NWM_S_LOAD("%4")
 
-// The 8 loads of group q into ring slot `slot`, in one asm statement so that
+// The 16 loads of group q into ring slot `slot`, in one asm statement so that
 // the compiler neither reorders them with other memory accesses nor adds
 // waits for them: every read of the ring waits for them with an explicit
 // vmcnt (below).  M0 (the LDS address of a load) is saved, stepped by 1 KiB
@@ -151,19 +150,22 @@ static __device__ __forceinline__ uint32_t s_lane_base(int lane, int b, int m) {
 static __device__ __forceinline__ void load_group(float *ring, const StripSrc &src, int q, int slot) {
   const uint32_t la = (uint32_t)uniform((int)(uint32_t)(uintptr_t)(lds_void *)(ring + slot * GROUP_FLOATS));
   const uint32_t goff = (uint32_t)uniform(q < src.n_groups ? (int)(GROUP * 4 * q) : (int)S_NONE);
-  uint32_t save, a0, a1;
+  uint32_t save, a0, a1, a2, a3;
   asm volatile(
       "s_mov_b32 %0, m0\n\t"
-      "s_mov_b32 m0, %3\n\t"
-      "v_add_u32 %1, %6, %4\n\t"
-      "v_add_u32 %2, %6, %5\n\t"
-      NWM_S_LOAD2 NWM_S_LOAD2 NWM_S_LOAD2 NWM_S_LOAD2
+      "s_mov_b32 m0, %5\n\t"
+      "v_add_u32 %1, %8, %6\n\t"
+      "v_add_u32 %2, %8, %7\n\t"
+      "v_add_u32 %3, %8, %11\n\t"
+      "v_add_u32 %4, %8, %12\n\t"
+      NWM_S_LOAD4 NWM_S_LOAD4 NWM_S_LOAD4 NWM_S_LOAD4
       "s_mov_b32 m0, %0"
-      : "=&s"(save), "=&v"(a0), "=&v"(a1)
-      : "s"(la), "v"(src.base0), "v"(src.base1), "s"(goff), "s"(src.rs), "s"(src.step)
+      : "=&s"(save), "=&v"(a0), "=&v"(a1), "=&v"(a2), "=&v"(a3)
+      : "s"(la), "v"(src.base[0]), "v"(src.base[1]), "s"(goff), "s"(src.rs), "s"(src.step), "v"(src.base[2]),
+        "v"(src.base[3])
       : "memory", "scc");
 }
-#undef NWM_S_LOAD2
+#undef NWM_S_LOAD4
 #undef NWM_S_LOAD
 
 // One 16-byte agent-coherent (sc1) LDS-direct load per active lane: lane l
@@ -262,7 +264,7 @@ static __device__ __forceinline__ void run16v(StripState &st, const float4 (&sv)
 // The float offset, within a ring slot, of chunk c (steps 4c .. 4c + 3) of
 // row `lane` (see StripSrc).
 static __device__ __forceinline__ uint32_t chunk_off(int lane, int c) {
-  return (uint32_t)(256 * (lane >> 3) + 4 * (16 * (c >> 1) + ((c + 2 * (lane & 7) + ((lane >> 3) & 1)) & 15)));
+  return (uint32_t)(256 * (lane >> 2) + 4 * (16 * (lane & 3) + ((c + 4 * ((lane >> 2) & 3) + (lane & 3)) & 15)));
 }
 
 // The 16 S values of lane `lane` for the steps [t0, t0 + 16) from the ring
@@ -309,14 +311,13 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
   __shared__ __align__(16) float ring[RING_GROUPS * GROUP_FLOATS];
   __shared__ __align__(16) uint64_t winbufA[32], winbufB[32];   // boundary windows (LDS-direct loads)
   const int lane = threadIdx.x;
-  // this lane's ring offsets of the four chunks of the first and second
-  // 16 steps of a group
-  uint32_t offA[4], offB[4];
+  // this lane's ring offsets of the four 16-byte chunks of each 16 steps of
+  // a group
+  uint32_t off[4][4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    offA[c] = chunk_off(lane, c);
-    offB[c] = chunk_off(lane, c + 4);
-  }
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) off[i][c] = chunk_off(lane, 4 * i + c);
   for (;;) {
     int item = 0;
     if (lane == 0) item = atomicAdd(head, 1);
@@ -352,8 +353,8 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     StripSrc src;
     src.rs = __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(Sb + (int64_t)i0 * m), (short)0,
                                                uniform(rows * m * 4), 0x00020000);
-    src.base0 = s_lane_base(lane, 0, m);
-    src.base1 = s_lane_base(lane, 1, m);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) src.base[j] = s_lane_base(lane, j, m);
     src.step = (uint32_t)uniform(64 * (m - 1));
     src.n_groups = (T_pad + GROUP - 1) / GROUP;
 
@@ -440,89 +441,67 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
       return st.bits;
     };
 
-    // Two chunks (one group of 32 steps) per iteration, in a fixed order of
-    // memory operations: [chunk A: window of the next group's A, publish]
-    // [chunk B: window of the next group's B, publish] [odd groups only: the
-    // direction words of this group and the one before, one 16-byte store
-    // per lane, 1 KiB per wave] [S of the group RING_GROUPS ahead: 8 loads
-    // into the slot just consumed].  The prologue issues S of group 0, the
-    // first two windows, then S of groups 1 and 2.  A window is therefore
-    // followed by exactly 11 memory operations when its chunk comes, 12 when
-    // the group before was odd (17 and 18 in the first group), which is the
-    // vmcnt it waits for; a group's S was issued before the window of its
-    // chunk A, so that wait also covers the ring.  Without windows (first
-    // strip) the ring's own wait is 16, 18, then 21 operations.  A drained
-    // counter (after a reload) only makes a wait shorter.
-    static_assert(RING_GROUPS == 3, "wait counts below assume three ring groups");
+    // One group of 64 steps (four chunks) per iteration, in a fixed order of
+    // memory operations: per chunk [window of the chunk two ahead, publish],
+    // then [the direction words of the group: one 16-byte store per lane,
+    // 1 KiB per wave] [S of the group after next: 16 loads into the slot just
+    // consumed].  The prologue issues S of group 0, the first two windows,
+    // then S of group 1.  A window is therefore followed by exactly 3 memory
+    // operations when its chunk comes, 20 for the first two chunks of a group
+    // (17 and 18 in the first group), which is the vmcnt it waits for; a
+    // group's S was issued before the window of its first chunk, so that
+    // wait also covers the ring.  Without windows (first strip) the ring's
+    // own wait is 16, then 21 operations.  A drained counter (after a
+    // reload) only makes a wait shorter.  A last group of fewer than four
+    // chunks stops after its last chunk; nothing waits after it but the
+    // final drain.
+    static_assert(RING_GROUPS == 2 && GROUP == 64, "wait counts below assume two ring groups of 64 steps");
     load_group(ring, src, 0, 0);
     if (s > 0) {
       prefetch_window(0, winbufA);
       prefetch_window(16, winbufB);
     }
     load_group(ring, src, 1, 1);
-    load_group(ring, src, 2, 2);
-    uint32_t keepA = 0u, keepB = 0u;   // directions of an even group, stored with the next
-    int t0 = 0;
-    int slot = 0;   // ring slot of the group at t0
     auto take_window = [&](int tw, const uint64_t *buf, int ahead) -> uint64_t {
       // ahead: memory operations issued after this window's load
-      if (ahead == 11) asm volatile("s_waitcnt vmcnt(11)" ::: "memory");
-      else if (ahead == 12) asm volatile("s_waitcnt vmcnt(12)" ::: "memory");
+      if (ahead == 3) asm volatile("s_waitcnt vmcnt(3)" ::: "memory");
+      else if (ahead == 20) asm volatile("s_waitcnt vmcnt(20)" ::: "memory");
       else if (ahead == 17) asm volatile("s_waitcnt vmcnt(17)" ::: "memory");
       else asm volatile("s_waitcnt vmcnt(18)" ::: "memory");
       uint64_t v = buf[wslot];
       if (!window_ready(v, tw)) v = wait_window(tw, v);
       return v;
     };
-    // the ring slot of the group at t0 has landed (chunk A of a group)
-    // operations after the window of a chunk of the group at t0 > 0
-    auto ahead_of = [&]() -> int { return ((t0 >> 5) & 1) ? 11 : 12; };
-    auto take_group = [&]() -> uint64_t {
-      if (s > 0) return take_window(t0, winbufA, t0 == 0 ? 17 : ahead_of());
-      if (t0 == 0) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
-      else if (t0 == GROUP) asm volatile("s_waitcnt vmcnt(18)" ::: "memory");
-      else asm volatile("s_waitcnt vmcnt(21)" ::: "memory");
-      return 0ull;
-    };
-    for (; t0 + 32 <= T_pad; t0 += 32) {
+    const int n_groups = src.n_groups;
+    int slot = 0;   // ring slot of group q
+    for (int q = 0; q < n_groups; ++q) {
       const float *grp = ring + slot * GROUP_FLOATS;
-      uint64_t wb = 0ull;
-      const uint64_t wa = take_group();
-      if (s > 0) {
-        __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the slot is read before it is refilled
-        prefetch_window(t0 + 32, winbufA);
+      if (s == 0) {   // the ring slot of group q has landed
+        if (q == 0) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+        else asm volatile("s_waitcnt vmcnt(21)" ::: "memory");
+      }
+      uint32_t bits[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int t0 = GROUP * q + 16 * i;
+        if (t0 >= T_pad) break;
+        uint64_t win = 0ull;
+        uint64_t *wbuf = (i & 1) ? winbufB : winbufA;
+        if (s > 0) {
+          win = take_window(t0, wbuf, q == 0 ? (i == 0 ? 17 : i == 1 ? 18 : 3) : (i < 2 ? 20 : 3));
+          __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the slot is read before it is refilled
+          prefetch_window(t0 + 32, wbuf);
+        }
+        if (failed) break;
+        bits[i] = chunk(t0, win, grp, off[i]);
       }
       if (failed) break;
-      const uint32_t bitsA = chunk(t0, wa, grp, offA);
-      if (s > 0) {
-        wb = take_window(t0 + 16, winbufB, t0 == 0 ? 18 : ahead_of());
-        __builtin_amdgcn_s_waitcnt(0xc07f);
-        prefetch_window(t0 + 48, winbufB);
-      }
-      if (failed) break;
-      const uint32_t bitsB = chunk(t0 + 16, wb, grp, offB);
-      if ((t0 >> 5) & 1) {
-        tbs[(t0 >> 6) * 64 + lane] = make_uint4(keepA, keepB, bitsA, bitsB);
-      } else {
-        keepA = bitsA;
-        keepB = bitsB;
-      }
+      tbs[q * 64 + lane] = make_uint4(bits[0], bits[1], bits[2], bits[3]);
       // every ring read of this group has returned (lgkmcnt(0)) before its
-      // slot is refilled with the group RING_GROUPS ahead
+      // slot is refilled with the group after next
       __builtin_amdgcn_s_waitcnt(0xc07f);
-      load_group(ring, src, t0 / GROUP + RING_GROUPS, slot);
-      slot = slot == RING_GROUPS - 1 ? 0 : slot + 1;
-    }
-    if (t0 < T_pad && !failed) {   // a last single chunk
-      const uint64_t wa = take_group();
-      if (!failed) {
-        const uint32_t bitsA = chunk(t0, wa, ring + slot * GROUP_FLOATS, offA);
-        tbs[(t0 >> 6) * 64 + lane] =
-            ((t0 >> 5) & 1) ? make_uint4(keepA, keepB, bitsA, 0u) : make_uint4(bitsA, 0u, 0u, 0u);
-      }
-    } else if (!failed && ((t0 >> 5) & 1)) {
-      // the last group was even: its directions are still held
-      tbs[((t0 - GROUP) >> 6) * 64 + lane] = make_uint4(keepA, keepB, 0u, 0u);
+      load_group(ring, src, q + RING_GROUPS, slot);
+      slot ^= 1;
     }
     // no LDS-direct load may still be writing LDS when the next item starts
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
