@@ -391,6 +391,15 @@ static __device__ __forceinline__ uint32_t a_code(uint32_t u, int r, int pitch, 
   return compact ? (u << 6) | (uint32_t)r : (uint32_t)((r * pitch + (int)(u % KC)) * esize);
 }
 
+// Entry value: the FP32 term, except for the compacted BF16 contraction,
+// which gets the row's byte offset in the operand tile in the high half and
+// the BF16 operand (the same conversion the dense path does) in the low half.
+static __device__ __forceinline__ uint32_t a_val(uint32_t v, int r, int pitch, int esize, int compact) {
+  if (!(compact && esize == 2)) return v;
+  const __bf16 h = (__bf16)__uint_as_float(v);
+  return ((uint32_t)(r * pitch * 2) << 16) | (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+
 __global__ __launch_bounds__(256) void k_build_a(PlanDev P, const int64_t *__restrict__ src_off,
                                                  const uint2 *__restrict__ merged,
                                                  const int32_t *__restrict__ cnt, uint2 *__restrict__ a_list,
@@ -501,8 +510,9 @@ __global__ __launch_bounds__(256) void k_build_a(PlanDev P, const int64_t *__res
     for (int q = 0; q < 2; ++q) {
       const uint2 ent = e[k][q];
       const bool ok = ent.x != 0xFFFFFFFFu;
-      __builtin_amdgcn_raw_buffer_store_b64((m_u32x2){a_code(ok ? ent.x : 0u, r, pitch, esize, compact), ent.y},
-                                            r_out, ok ? (uint32_t)pos[k][q] * 8u : BUF_OOB, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b64(
+          (m_u32x2){a_code(ok ? ent.x : 0u, r, pitch, esize, compact), a_val(ent.y, r, pitch, esize, compact)}, r_out,
+          ok ? (uint32_t)pos[k][q] * 8u : BUF_OOB, 0, 0);
     }
   }
 #pragma unroll
@@ -514,7 +524,8 @@ __global__ __launch_bounds__(256) void k_build_a(PlanDev P, const int64_t *__res
       const uint2 ent = merged[base + x];
       if (in_voc(ent.x)) {
         const int p = atomicAdd(&off[ent.x / KC], 1);
-        a_list[tile_base + p] = make_uint2(a_code(ent.x, r, pitch, esize, compact), ent.y);
+        a_list[tile_base + p] =
+            make_uint2(a_code(ent.x, r, pitch, esize, compact), a_val(ent.y, r, pitch, esize, compact));
       }
     }
   }
@@ -759,8 +770,9 @@ __global__ __launch_bounds__(64 * EXA_WAVES) void k_expand_a(PlanDev P, const in
       const bool ok = ent.x != HEMPTY;
       if (__ballot(ok) == 0) continue;   // (wave-uniform)
       const int pos = atomicAdd(&off[ok ? (int)(ent.x / KC) : junk], 1);
-      __builtin_amdgcn_raw_buffer_store_b64((m_u32x2){a_code(ok ? ent.x : 0u, row, pitch, esize, compact), ent.y},
-                                            r_out, ok ? (uint32_t)pos * 8u : BUF_OOB, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b64(
+          (m_u32x2){a_code(ok ? ent.x : 0u, row, pitch, esize, compact), a_val(ent.y, row, pitch, esize, compact)},
+          r_out, ok ? (uint32_t)pos * 8u : BUF_OOB, 0, 0);
     }
   }
 }

@@ -619,20 +619,28 @@ static __device__ __forceinline__ void cscatter(const CChunk &C, char *At, char 
     const uint32_t u = lane + 64 * q < C.na ? C.a[q].x >> 6 : 0u;
     mm[q] = mtl[u >> 5];
   }
+  // BF16 entries carry the row's byte offset and the operand (see a_val in
+  // the list builders); FP32 entries the row and the FP32 term
+  auto put = [&](uint32_t x, uint32_t y, uint32_t pos) {
+    if constexpr (BF16)
+      lds_put<uint16_t>(At, (y >> 16) + (pos & 31u) * 2u, (uint16_t)y);
+    else
+      lds_put<T>(At, ((x & 63u) * P + (pos & 31u)) * (uint32_t)sizeof(T), T(__uint_as_float(y)));
+  };
 #pragma unroll
   for (int q = 0; q < CREG_A; ++q) {
     const uint32_t x = C.a[q].x, u = x >> 6, bit = u & 31u;
     const uint32_t pos = mm[q].y + (uint32_t)__popc(mm[q].x & ((1u << bit) - 1u));
-    const bool hit = lane + 64 * q < C.na && ((mm[q].x >> bit) & 1u) && (pos >> 5) == (uint32_t)kc;
-    if (hit) lds_put<T>(At, ((x & 63u) * P + (pos & 31u)) * (uint32_t)sizeof(T), T(__uint_as_float(C.a[q].y)));
+    const bool hit =
+        lane + 64 * q < C.na && __builtin_amdgcn_ubfe(mm[q].x, bit, 1u) != 0u && (pos >> 5) == (uint32_t)kc;
+    if (hit) put(x, C.a[q].y, pos);
   }
   for (int e = CREG_A * 64 + lane; e < C.na; e += 64) {
     const uint2 v = pa[C.a0 + e];
     const uint32_t u = v.x >> 6, bit = u & 31u;
     const uint2 w = mtl[u >> 5];
     const uint32_t pos = w.y + (uint32_t)__popc(w.x & ((1u << bit) - 1u));
-    if (((w.x >> bit) & 1u) && (pos >> 5) == (uint32_t)kc)
-      lds_put<T>(At, ((v.x & 63u) * P + (pos & 31u)) * (uint32_t)sizeof(T), T(__uint_as_float(v.y)));
+    if (__builtin_amdgcn_ubfe(w.x, bit, 1u) != 0u && (pos >> 5) == (uint32_t)kc) put(v.x, v.y, pos);
   }
 #pragma unroll
   for (int q = 0; q < CREG_B; ++q) lds_put<T>(Bt, lane + 64 * q < C.nb ? C.b[q] : junk, T(1.0f));
@@ -703,8 +711,14 @@ __global__ __launch_bounds__(64) void k_score_c(PlanDev P, const int64_t *__rest
   // padding element (row 0, column KC) no fragment reads: where lanes with
   // nothing to write go, all to one address
   const uint32_t junk = (uint32_t)(KC * (int)sizeof(typename Op<BF16>::T));
-  constexpr int NCLR = ScoreLdsC<BF16, KG>::OPS / 16 / 64;   // per tile pair
-  static_assert(ScoreLdsC<BF16, KG>::OPS % (16 * 64) == 0, "tile clear");
+  // the clear after a chunk: only the KC columns of each of the pair's 2 TM
+  // rows (the padding columns hold nothing a fragment reads), U 16-byte
+  // units per row, lane l taking units l, l + 64, ...
+  constexpr int RB = Op<BF16>::PITCH * (int)sizeof(typename Op<BF16>::T);   // bytes per tile row
+  constexpr int U = KC * (int)sizeof(typename Op<BF16>::T) / 16;
+  constexpr int NCLR = 2 * TM * U / 64;   // per lane, per tile pair
+  static_assert(64 % U == 0 && (2 * TM * U) % 64 == 0 && 2 * TB == 2 * TM * RB, "tile clear");
+  const int clr0 = (lane / U) * RB + (lane % U) * 16;
   Frags<BF16> F;
 
   // chunk kc from register set Cur while the chunk after next (of the same
@@ -717,7 +731,7 @@ __global__ __launch_bounds__(64) void k_score_c(PlanDev P, const int64_t *__rest
     wave_sync();                                                               \
     read_frags<BF16>(F, At, Bt, lane);                                         \
     _Pragma("unroll") for (int e_ = 0; e_ < NCLR; ++e_)                        \
-      reinterpret_cast<uint4 *>(smem)[e_ * 64 + lane] = make_uint4(0u, 0u, 0u, 0u); \
+      *reinterpret_cast<uint4 *>(smem + clr0 + e_ * (64 / U) * RB) = make_uint4(0u, 0u, 0u, 0u); \
     mfma_frags<BF16>(F, acc);                                                  \
   }
   // windows of 64 compacted chunks (one almost always covers the tile); the
@@ -755,12 +769,12 @@ __global__ __launch_bounds__(64) void k_score_c(PlanDev P, const int64_t *__rest
     wave_sync();                                                                       \
     read_frags<BF16>(F, At, Bt, lane);                                                 \
     _Pragma("unroll") for (int e_ = 0; e_ < NCLR; ++e_)                                \
-      reinterpret_cast<uint4 *>(smem)[e_ * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);    \
+      *reinterpret_cast<uint4 *>(smem + clr0 + e_ * (64 / U) * RB) = make_uint4(0u, 0u, 0u, 0u); \
     mfma_frags<BF16>(F, acc);                                                          \
     if (has2) {                                                                        \
       read_frags<BF16>(F, At1, Bt1, lane);                                             \
       _Pragma("unroll") for (int e_ = 0; e_ < NCLR; ++e_)                              \
-        reinterpret_cast<uint4 *>(smem + 2 * TB)[e_ * 64 + lane] = make_uint4(0u, 0u, 0u, 0u); \
+        *reinterpret_cast<uint4 *>(smem + 2 * TB + clr0 + e_ * (64 / U) * RB) = make_uint4(0u, 0u, 0u, 0u); \
       mfma_frags<BF16>(F, acc);                                                        \
     }                                                                                  \
   }
