@@ -270,7 +270,8 @@ nwm_status nwm_union_kept(const nwm_plan *plan, const int32_t *kept_fwd, const i
 /* Launch shapes that do not change any result, only the time (all but
  * SCORE_COMPACT):
  *   NWM_PARAM_FILL_WAVES_PER_CU   persistent DP waves per compute unit
- *                                 (0 = as many as fit; default 0)
+ *                                 (0 = as many as fit; default 0; the LDS-ring
+ *                                 fill runs whole workgroups of four waves)
  *   NWM_PARAM_MERGE_WAVES_PER_CU  dictionary-merge waves per compute unit
  *                                 (0 = as many as the LDS allows; default 0)
  *   NWM_PARAM_SCORE_XCD_MAP       1 = contraction tiles of one pair on one XCD

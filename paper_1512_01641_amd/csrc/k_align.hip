@@ -2,34 +2,38 @@
 // document pair (Sec. 5.1, Figs. 1-2, eq. (1)) and the threshold filter
 // (Sec. 4).
 //
-// k_nw_fill   persistent work-queue kernel, one wave per workgroup.  A work
-//             item is one 64-row strip of one pair's DP lattice; items are
-//             ordered longest pair first, strips top to bottom.  Lane r owns
-//             row r of the strip and at step t computes column j = t - r + 1,
-//             so each step is one anti-diagonal of the strip, computed by
-//             all lanes at once (Sec. 5.1, Fig. 2).  Per cell, in FP32 without
-//             contraction:
+// k_nw_fill   persistent work-queue kernel, four waves per workgroup.  A
+//             strip is 64 rows of one pair's DP lattice; a task is four
+//             strips, one per wave: four consecutive strips of one pair (fewer
+//             at its end) or strips of one-strip pairs, in queue order
+//             (longest chains first).  Lane r owns row r of the strip and at
+//             step t computes column j = t - r + 1, so each step is one
+//             anti-diagonal of the strip, computed by all lanes at once
+//             (Sec. 5.1, Fig. 2).  Per cell, in FP32 without contraction:
 //                up = H[i-1][j] + g, left = H[i][j-1] + g, diag = H[i-1][j-1] + S
 //                first maximum of (up, left, diag) with '>' (UP > LEFT > DIAG)
 //             The value from the row above moves one lane per step by a DPP
 //             wave shift.  The strip's top boundary (the previous strip's last
 //             row) enters lane 0 through a 64-lane register window shifted one
 //             lane per step; the strip's own last row leaves through a second
-//             shifted window and is published every 16 steps as tagged 64-bit
-//             agent-coherent stores (no counters, no cache flushes), so the
-//             next strip runs concurrently on another wave about 100 steps
-//             behind (bounded re-read).  A wave that gives up waiting (its
-//             poll limit) sets the error flag, marks its own last row failed
-//             (tag TAG_FAIL, so the strips below give up at once instead of
-//             waiting out their own limits) and, in a pair's last strip,
-//             writes NaN as the score; the walk then leaves the pair empty.
-//             S is staged through an LDS ring of two 64-step groups (16 KiB
-//             each: 64 rows x 256 bytes), filled a group ahead by 16-byte
-//             LDS-direct buffer loads (no register holds S); each lane reads
-//             the four steps of one 16-byte chunk of its own row with one
-//             ds_read_b128, placed so that the lanes of a quarter-wave hit
-//             different banks.  Each lane packs
-//             its 2-bit directions, 16 steps per word, and every 64 steps the
+//             shifted window every 16 steps.  Between the strips of one task
+//             the row passes through an LDS ring with a count of columns put
+//             and taken (about 80 steps behind); the last strip of a task
+//             publishes it as tagged 64-bit agent-coherent stores (no
+//             counters, no cache flushes) for the first strip of the next
+//             task, which runs on another workgroup about 150 steps behind
+//             (bounded re-read).  A wave that gives up waiting (its poll
+//             limit) sets the error flag, marks its own last row failed (tag
+//             TAG_FAIL in memory, count -1 in LDS, so the strips below give up
+//             at once instead of waiting out their own limits) and, in a
+//             pair's last strip, writes NaN as the score; the walk then leaves
+//             the pair empty.  S is staged through an LDS ring of two 64-step
+//             groups per wave (16 KiB each: 64 rows x 256 bytes), filled a
+//             group ahead by 16-byte LDS-direct buffer loads (no register
+//             holds S); each lane reads the four steps of one 16-byte chunk
+//             of its own row with one ds_read_b128, placed so that the lanes
+//             of a quarter-wave hit different banks.  Each lane packs its
+//             2-bit directions, 16 steps per word, and every 64 steps the
 //             wave writes one coalesced 1 KiB block.  H never reaches HBM.
 // k_nw_reset  clears the published-row region and the queue; scores of
 //             empty pairs.
@@ -41,6 +45,7 @@
 // k_keep      keeps the aligned pairs with S >= threshold, ascending.
 #include "nwm_internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace nwm {
@@ -175,7 +180,7 @@ static __device__ __forceinline__ void load_group(float *ring, const StripSrc &s
 // which would cancel the two-group prefetch.  Its readers wait with an
 // explicit vmcnt.  One wait state separates the M0 write from the load.
 static __device__ __forceinline__ void load_window_lds(uint64_t *buf, const uint64_t *src) {
-  const uint32_t la = (uint32_t)(uintptr_t)(lds_void *)buf;
+  const uint32_t la = (uint32_t)uniform((int)(uint32_t)(uintptr_t)(lds_void *)buf);
   uint32_t save;
   asm volatile(
       "s_mov_b32 %0, m0\n\t"
@@ -281,11 +286,25 @@ static __device__ __forceinline__ void run16(StripState &st, const float *grp, c
 struct FillArgs {
   int n_items, B;
   int item0;        // first work item of this launch (its queue counts from 0)
+  int n_tasks;      // tasks of this launch (the LDS-ring fill)
+  int task0;        // its first task
   int spin_limit;   // polls of a boundary window before the wave gives up
   int hold;         // testing: the first strip of a pair publishes nothing
   const int32_t *it_pair, *it_strip, *n, *m;
+  const int32_t *tk_pair, *tk_slot;
   const int64_t *s_off, *tb_off, *bnd_off;
 };
+
+// LDS of the LDS-ring fill, per workgroup of FILL_SLOTS waves: each wave's S
+// ring and window buffers, then a link ring per pair of neighbouring waves
+// (the upper strip's last row, LINK_COLS columns, column j in slot
+// j % LINK_COLS), then the counters: [k] columns wave k has put into link k
+// (-1: it gave up), [FILL_SLOTS + k] columns wave k + 1 has taken from it,
+// [2 FILL_SLOTS] the task.
+constexpr int FILL_WAVE_LDS = RING_GROUPS * GROUP_FLOATS * 4 + 2 * 32 * 8;
+constexpr int LINK_COLS = 512;
+constexpr int FILL_LDS = FILL_SLOTS * FILL_WAVE_LDS + (FILL_SLOTS - 1) * LINK_COLS * 4 + 4 * (2 * FILL_SLOTS + 1);
+static_assert((LINK_COLS & (LINK_COLS - 1)) == 0 && LINK_COLS >= 256, "link ring");
 
 __global__ __launch_bounds__(256) void k_nw_reset(FillArgs A, uint4 *__restrict__ bnd16, int64_t n_bnd16,
                                                   int32_t *__restrict__ ctl, float g, float *__restrict__ score) {
@@ -303,14 +322,20 @@ __global__ __launch_bounds__(256) void k_nw_reset(FillArgs A, uint4 *__restrict_
 }
 
 template <bool MAX3>
-__global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restrict__ S, float g,
-                                                float *__restrict__ score, char *__restrict__ tb,
-                                                uint64_t *__restrict__ bnd, int32_t *__restrict__ head,
-                                                int32_t *__restrict__ err) {
+__global__ __launch_bounds__(64 * FILL_SLOTS) void k_nw_fill(FillArgs A, const float *__restrict__ S, float g,
+                                                             float *__restrict__ score, char *__restrict__ tb,
+                                                             uint64_t *__restrict__ bnd, int32_t *__restrict__ head,
+                                                             int32_t *__restrict__ err) {
   constexpr uint32_t epoch = 1u;   // tag of a published value (the reset clears to 0)
-  __shared__ __align__(16) float ring[RING_GROUPS * GROUP_FLOATS];
-  __shared__ __align__(16) uint64_t winbufA[32], winbufB[32];   // boundary windows (LDS-direct loads)
-  const int lane = threadIdx.x;
+  extern __shared__ __align__(16) char fill_lds[];   // FILL_LDS bytes
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float *ring = reinterpret_cast<float *>(fill_lds + wave * FILL_WAVE_LDS);
+  uint64_t *winbufA = reinterpret_cast<uint64_t *>(fill_lds + wave * FILL_WAVE_LDS + RING_GROUPS * GROUP_FLOATS * 4);
+  uint64_t *winbufB = winbufA + 32;   // boundary windows (LDS-direct loads)
+  float *links = reinterpret_cast<float *>(fill_lds + FILL_SLOTS * FILL_WAVE_LDS);
+  int *ctr = reinterpret_cast<int *>(fill_lds + FILL_SLOTS * FILL_WAVE_LDS + (FILL_SLOTS - 1) * LINK_COLS * 4);
+  float *link_in = links + (wave - 1) * LINK_COLS;   // from the wave above (wave > 0)
+  float *link_out = links + wave * LINK_COLS;        // to the wave below (wave < FILL_SLOTS - 1)
   // this lane's ring offsets of the four 16-byte chunks of each 16 steps of
   // a group
   uint32_t off[4][4];
@@ -318,16 +343,26 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int c = 0; c < 4; ++c) off[i][c] = chunk_off(lane, 4 * i + c);
+  // One task (FILL_SLOTS strips, one per wave) at a time: the whole
+  // workgroup takes the next task once every wave is done with the last one,
+  // so the link rings and counters start clear.  Every wave passes both
+  // barriers of every task and leaves the loop at the same task.
   for (;;) {
-    int item = 0;
-    if (lane == 0) item = atomicAdd(head, 1);
-    item = uniform(item);
-    if (item >= A.n_items) break;
-    item += A.item0;
-    const int b = uniform(A.it_pair[item]);
-    const int s_tag = uniform(A.it_strip[item]);
-    const int s = s_tag & ~ITEM_HOT;
+    __syncthreads();
+    if (threadIdx.x < 2 * FILL_SLOTS) ctr[threadIdx.x] = 0;
+    if (threadIdx.x == 0) ctr[2 * FILL_SLOTS] = atomicAdd(head, 1);
+    __syncthreads();
+    const int task = uniform(ctr[2 * FILL_SLOTS]);
+    if (task >= A.n_tasks) break;
+    const int ts = (A.task0 + task) * FILL_SLOTS + wave;   // this wave's task slot
+    const int b = uniform(A.tk_pair[ts]);
+    if (b < 0) continue;   // an empty slot
+    const int s_tag = uniform(A.tk_slot[ts]);
+    const int s = s_tag & ITEM_STRIP;
     const bool hot = (s_tag & ITEM_HOT) != 0;
+    const bool link_up = (s_tag & ITEM_LINK_IN) != 0;     // the boundary comes from the wave above, in LDS
+    const bool link_down = (s_tag & ITEM_LINK_OUT) != 0;  // the last row goes to the wave below, in LDS
+    const bool in_global = s > 0 && !link_up;             // the boundary comes from memory
     if (hot) __builtin_amdgcn_s_setprio(2);
     const int n = uniform(A.n[b]), m = uniform(A.m[b]);
     const int nstrips = (n + 63) >> 6;
@@ -346,9 +381,10 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     const int r_last = n - 1 - i0;   // lane of row n in the last strip
     bool failed = false;
 
-    // slots 1..m of this strip's published row (nothing when it is the last)
+    // slots 1..m of this strip's published row (nothing when it is the last
+    // or hands its row on through LDS: the store instruction still issues)
     const __amdgpu_buffer_rsrc_t pub_rs = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)uniform_ptr(out_row), (short)0, last ? 0 : uniform((m + 1) * 8), 0x00020000);
+        (void *)uniform_ptr(out_row), (short)0, (last || link_down) ? 0 : uniform((m + 1) * 8), 0x00020000);
 
     StripSrc src;
     src.rs = __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(Sb + (int64_t)i0 * m), (short)0,
@@ -426,6 +462,53 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
       }
       return v;
     };
+    // A bounded wait on a link counter (LDS, written by another wave of the
+    // workgroup) until it reaches `need`; `seen` keeps the last value read,
+    // so most chunks need no read at all.  False if the writer gave up (-1)
+    // or the poll limit passed.  LDS accesses only: no vector memory counts.
+    // A wave's LDS operations are performed in order, so a count written
+    // after its values (or after the reads of the slots it frees) is never
+    // seen before them; only the compiler is kept from reordering.
+    auto link_wait = [&](const int *c, int need, int &seen) -> bool {
+      for (int spins = 0; seen < need; ++spins) {
+        if (spins > A.spin_limit) return false;
+        if (spins > 0) __builtin_amdgcn_s_sleep(1);
+        seen = uniform(__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+        if (seen < 0) return false;
+      }
+      return true;
+    };
+    int up_put = 0;      // columns the wave above had put, as last read
+    int down_taken = 0;  // columns the wave below had taken, as last read
+    // the boundary of the 16 steps from tw, columns tw + 1 .. tw + 16, from
+    // the wave above; then the columns taken are counted
+    auto link_take = [&](int tw) -> uint64_t {
+      if (!link_wait(&ctr[wave - 1], min(tw + 16, m), up_put)) {
+        failed = true;
+        return 0ull;
+      }
+      asm volatile("" ::: "memory");
+      const float v = link_in[(tw + 1 + (lane & 15)) & (LINK_COLS - 1)];
+      asm volatile("" ::: "memory");
+      if (lane == 0)
+        __hip_atomic_store(&ctr[FILL_SLOTS + wave - 1], tw + 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      return ((uint64_t)epoch << 32) | __float_as_uint(v);
+    };
+    // the columns of the strip's last row finished in the chunk at t0 (lanes
+    // 48.. of the collector) to the wave below, once it has taken what they
+    // overwrite; then the count of columns put
+    auto link_put = [&](int t0) {
+      const int jhi = min(t0 - 47, m);
+      if (jhi < 1 || (A.hold && s == 0)) return;
+      if (!link_wait(&ctr[FILL_SLOTS + wave], jhi - LINK_COLS, down_taken)) {
+        failed = true;
+        return;
+      }
+      const int j = t0 - 110 + lane;
+      if (lane >= 48 && j >= 1 && j <= m) link_out[j & (LINK_COLS - 1)] = st.col;
+      asm volatile("" ::: "memory");
+      if (lane == 0) __hip_atomic_store(&ctr[wave], jhi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
     // One chunk of 16 steps from its boundary window.  The publish of the
     // strip's last row is one store instruction in every chunk (see
     // publish), so the explicit wait counts stay exact.
@@ -436,8 +519,9 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
       // lane l of the collector holds H of row 64 at step t0 + 15 - 63 + l,
       // i.e. column t0 - 110 + l; lanes 48.. publish
       const int j = t0 - 110 + lane;
-      const bool pub = !last && lane >= 48 && j >= 1 && j <= m && !(A.hold && s == 0);
+      const bool pub = !last && !link_down && lane >= 48 && j >= 1 && j <= m && !(A.hold && s == 0);
       publish(pub_rs, pub, j, ((uint64_t)epoch << 32) | __float_as_uint(st.col));
+      if (link_down) link_put(t0);
       return st.bits;
     };
 
@@ -457,7 +541,7 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     // final drain.
     static_assert(RING_GROUPS == 2 && GROUP == 64, "wait counts below assume two ring groups of 64 steps");
     load_group(ring, src, 0, 0);
-    if (s > 0) {
+    if (in_global) {
       prefetch_window(0, winbufA);
       prefetch_window(16, winbufB);
     }
@@ -476,7 +560,7 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
     int slot = 0;   // ring slot of group q
     for (int q = 0; q < n_groups; ++q) {
       const float *grp = ring + slot * GROUP_FLOATS;
-      if (s == 0) {   // the ring slot of group q has landed
+      if (!in_global) {   // the ring slot of group q has landed
         if (q == 0) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
         else asm volatile("s_waitcnt vmcnt(21)" ::: "memory");
       }
@@ -487,10 +571,12 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
         if (t0 >= T_pad) break;
         uint64_t win = 0ull;
         uint64_t *wbuf = (i & 1) ? winbufB : winbufA;
-        if (s > 0) {
+        if (in_global) {
           win = take_window(t0, wbuf, q == 0 ? (i == 0 ? 17 : i == 1 ? 18 : 3) : (i < 2 ? 20 : 3));
           __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the slot is read before it is refilled
           prefetch_window(t0 + 32, wbuf);
+        } else if (link_up) {
+          win = link_take(t0);
         }
         if (failed) break;
         bits[i] = chunk(t0, win, grp, off[i]);
@@ -511,8 +597,12 @@ __global__ __launch_bounds__(64) void k_nw_fill(FillArgs A, const float *__restr
       if (lane == 0) score[b] = failed ? __builtin_nanf("") : v;
     } else if (failed) {
       // the strip below must not wait for a row that will never come
-      for (int j = 1 + lane; j <= m; j += 64)
-        __hip_atomic_store(out_row + j, (uint64_t)TAG_FAIL << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (link_down) {
+        if (lane == 0) __hip_atomic_store(&ctr[wave], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else {
+        for (int j = 1 + lane; j <= m; j += 64)
+          __hip_atomic_store(out_row + j, (uint64_t)TAG_FAIL << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     if (failed && lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (hot) __builtin_amdgcn_s_setprio(0);
@@ -838,8 +928,8 @@ __global__ __launch_bounds__(64) void k_keep(PlanDev P, const float *__restrict_
   if (lane == 0) n_kept[b] = nk;
 }
 
-// compute units; resident fill waves per unit for the LDS-ring and the
-// register staging
+// compute units; resident fill workgroups per unit for the LDS-ring fill
+// (FILL_SLOTS waves each) and resident waves for the register staging
 static int g_fill_cus = 0, g_fill_per = 0, g_fill_per_r = 0;
 
 hipError_t fill_set_attrs(int) {
@@ -847,8 +937,15 @@ hipError_t fill_set_attrs(int) {
     int dev = 0, cus = 0, per = 0, per3 = 0, pr = 0, pr3 = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_nw_fill<false>, 64, 0);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per3, k_nw_fill<true>, 64, 0);
+    // the LDS-ring fill takes more than the default 64 KiB of LDS per workgroup
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void *)k_nw_fill<false>, hipFuncAttributeMaxDynamicSharedMemorySize, FILL_LDS);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void *)k_nw_fill<true>, hipFuncAttributeMaxDynamicSharedMemorySize, FILL_LDS);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_nw_fill<false>, 64 * FILL_SLOTS, FILL_LDS);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per3, k_nw_fill<true>, 64 * FILL_SLOTS, FILL_LDS);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pr, k_nw_fill_r<false>, 64, 0);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pr3, k_nw_fill_r<true>, 64, 0);
     if (e != hipSuccess) return e;
@@ -866,10 +963,14 @@ static FillArgs fill_args(const PlanDev &P) {
   A.n_items = P.n_items;
   A.B = P.B;
   A.item0 = 0;
+  A.n_tasks = P.n_tasks;
+  A.task0 = 0;
   A.spin_limit = SPIN_LIMIT;
   A.hold = 0;
   A.it_pair = P.it_pair;
   A.it_strip = P.it_strip;
+  A.tk_pair = P.tk_pair;
+  A.tk_slot = P.tk_slot;
   A.n = P.n;
   A.m = P.m;
   A.s_off = P.s_off;
@@ -889,11 +990,13 @@ hipError_t launch_nw_reset(const PlanDev &P, float g, float *score, uint64_t *bn
   return hipGetLastError();
 }
 
-// DP items [item0, item0 + n) of the plan, popped from the queue head `head`
-// (cleared by the reset).  Strips of one pair must all be in one launch.
+// DP items [item0, item0 + n) of the plan (the register staging) or the same
+// strips as tasks [task0, task0 + nt) (the LDS ring), popped from the queue
+// head `head` (cleared by the reset).  Strips of one pair must all be in one
+// launch.
 hipError_t launch_nw_fill_items(const PlanDev &P, const float *S, float g, float *score, char *tb, uint64_t *bnd,
-                                int64_t n_bnd, int32_t *head, int32_t *err, int item0, int n, int waves_per_cu,
-                                int spin_limit, int hold, int staging, hipStream_t st) {
+                                int64_t n_bnd, int32_t *head, int32_t *err, int item0, int n, int task0, int nt,
+                                int waves_per_cu, int spin_limit, int hold, int staging, hipStream_t st) {
   if (P.B <= 0 || n <= 0) return hipSuccess;
   if (g_fill_cus == 0) {
     hipError_t e = fill_set_attrs(0);
@@ -902,14 +1005,22 @@ hipError_t launch_nw_fill_items(const PlanDev &P, const float *S, float g, float
   FillArgs A = fill_args(P);
   A.item0 = item0;
   A.n_items = n;
+  A.task0 = task0;
+  A.n_tasks = nt;
   A.spin_limit = spin_limit > 0 ? spin_limit : SPIN_LIMIT;
   A.hold = hold;
   // every wave of the grid is resident at once (the hand-off between strips
-  // waits on other waves), so the grid never exceeds the occupancy
-  const int fit = staging ? g_fill_per_r : g_fill_per;
-  const int per = (waves_per_cu > 0 && waves_per_cu < fit) ? waves_per_cu : fit;
-  const int full = g_fill_cus * per;
-  const int grid = n < full ? n : full;
+  // waits on other waves), so the grid never exceeds the occupancy; for the
+  // LDS ring, waves_per_cu counts the waves of whole workgroups
+  int grid;
+  if (staging) {
+    const int per = (waves_per_cu > 0 && waves_per_cu < g_fill_per_r) ? waves_per_cu : g_fill_per_r;
+    grid = std::min(n, g_fill_cus * per);
+  } else {
+    int groups = g_fill_cus * g_fill_per;
+    if (waves_per_cu > 0) groups = std::min(groups, std::max(1, g_fill_cus * waves_per_cu / FILL_SLOTS));
+    grid = std::min(nt, groups);
+  }
   // a gap of -0 keeps the compare chain (see run16v)
   const bool max3 = !(g == 0.0f && std::signbit(g));
   if (staging) {
@@ -919,9 +1030,11 @@ hipError_t launch_nw_fill_items(const PlanDev &P, const float *S, float g, float
       hipLaunchKernelGGL(k_nw_fill_r<false>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, head, err);
   } else {
     if (max3)
-      hipLaunchKernelGGL(k_nw_fill<true>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, head, err);
+      hipLaunchKernelGGL(k_nw_fill<true>, dim3(grid), dim3(64 * FILL_SLOTS), FILL_LDS, st, A, S, g, score, tb, bnd,
+                         head, err);
     else
-      hipLaunchKernelGGL(k_nw_fill<false>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, head, err);
+      hipLaunchKernelGGL(k_nw_fill<false>, dim3(grid), dim3(64 * FILL_SLOTS), FILL_LDS, st, A, S, g, score, tb, bnd,
+                         head, err);
   }
   return hipGetLastError();
 }
@@ -931,8 +1044,8 @@ hipError_t launch_nw_fill(const PlanDev &P, const float *S, float g, float *scor
                           hipStream_t st) {
   hipError_t e = launch_nw_reset(P, g, score, bnd, n_bnd, ctl, st);
   if (e != hipSuccess) return e;
-  return launch_nw_fill_items(P, S, g, score, tb, bnd, n_bnd, ctl, ctl + 1, 0, P.n_items, waves_per_cu, spin_limit,
-                              hold, staging, st);
+  return launch_nw_fill_items(P, S, g, score, tb, bnd, n_bnd, ctl, ctl + 1, 0, P.n_items, 0, P.n_tasks, waves_per_cu,
+                              spin_limit, hold, staging, st);
 }
 
 // pairs dp_order[o0 .. o0 + n)

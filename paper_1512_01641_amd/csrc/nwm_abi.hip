@@ -38,7 +38,7 @@ hipError_t launch_nw_fill(const PlanDev &, const float *, float, float *, char *
 hipError_t fill_set_attrs(int);
 hipError_t launch_nw_reset(const PlanDev &, float, float *, uint64_t *, int64_t, int32_t *, hipStream_t);
 hipError_t launch_nw_fill_items(const PlanDev &, const float *, float, float *, char *, uint64_t *, int64_t,
-                                int32_t *, int32_t *, int, int, int, int, int, int, hipStream_t);
+                                int32_t *, int32_t *, int, int, int, int, int, int, int, int, hipStream_t);
 hipError_t launch_nw_walk(const PlanDev &, const char *, const float *, int2 *, int32_t *, int, int, hipStream_t);
 hipError_t launch_keep(const PlanDev &, const float *, float, const int2 *, const int32_t *, int2 *, int32_t *, int,
                        int, hipStream_t);
@@ -147,6 +147,8 @@ struct nwm_plan {
   uint64_t param_version = 0;
   std::vector<int32_t> it_strip;   // strip index per DP item (no flags)
   std::vector<int64_t> it_chain;   // dependency chain of the item's pair
+  std::vector<int32_t> tk_slot;    // strip index and link flags per task slot (no priority flag)
+  std::vector<int64_t> tk_chain;   // dependency chain of the slot's pair (0: empty slot)
   int64_t max_chain = 0;
   int max_m = 0;
   // the pairs whose DP dependency chain is at least LONG_CHAIN_PERCENT of
@@ -159,6 +161,7 @@ struct nwm_plan {
   // the first of the long pairs (chain >= TOP_CHAIN_PERCENT of the longest):
   // their contraction tiles, DP items and pairs lead the long pairs' ranges
   int n_gt_top = 0, n_items_top = 0, n_pairs_top = 0, n_rt_top = 0, n_ct_top = 0;
+  int n_tasks_top = 0, n_tasks_long = 0;   // the same ranges in tasks
   int64_t n_sent_top = 0;
   hipStream_t lane_stream = nullptr;   // the top pairs' DP
   hipEvent_t ev_top = nullptr, ev_top_done = nullptr;
@@ -201,13 +204,13 @@ void clear_stale_error() { (void)hipGetLastError(); }
 
 // DP item words: strip index, plus ITEM_HOT for pairs whose dependency chain
 // is at least NWM_PARAM_DP_HOT_PERCENT of the longest
-void hot_flags(const nwm_plan *p, std::vector<int32_t> &out) {
+void hot_flags(const nwm_plan *p, std::vector<int32_t> &out, std::vector<int32_t> &tasks) {
   const int64_t pct = p->param[NWM_PARAM_DP_HOT_PERCENT];
+  auto hot = [&](int64_t chain) { return pct > 0 && chain > 0 && chain * 100 >= pct * p->max_chain; };
   out.resize(p->it_strip.size());
-  for (size_t k = 0; k < out.size(); ++k) {
-    const bool hot = pct > 0 && p->it_chain[k] * 100 >= pct * p->max_chain;
-    out[k] = p->it_strip[k] | (hot ? ITEM_HOT : 0);
-  }
+  for (size_t k = 0; k < out.size(); ++k) out[k] = p->it_strip[k] | (hot(p->it_chain[k]) ? ITEM_HOT : 0);
+  tasks.resize(p->tk_slot.size());
+  for (size_t k = 0; k < tasks.size(); ++k) tasks[k] = p->tk_slot[k] | (hot(p->tk_chain[k]) ? ITEM_HOT : 0);
 }
 
 struct Mark {
@@ -484,7 +487,43 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
     p->it_strip.swap(is);
     p->it_chain.swap(ic);
   }
-  hot_flags(p, it_strip);
+  // Tasks of the LDS-ring fill, FILL_SLOTS strips each, in the same queue
+  // order and the same three ranges.  Strips 4g .. 4g + 3 of a pair (fewer
+  // at its end) form one linked group, placed where strip 4g stands in the
+  // queue into consecutive slots of one task, each handing its last row to
+  // the next through LDS; strips of one-strip pairs take single slots.  A
+  // group that does not fit in the open task's free slots closes it (its
+  // empty slots, pair -1, wait for the task's end).
+  std::vector<int32_t> tk_pair;
+  {
+    const size_t cut[4] = {0, (size_t)p->n_items_top, (size_t)p->n_items_long, it_pair.size()};
+    for (int r = 0; r < 3; ++r) {
+      int fill = 0;   // used slots of the open task
+      auto push_slot = [&](int32_t pb, int32_t word, int64_t chain) {
+        tk_pair.push_back(pb);
+        p->tk_slot.push_back(word);
+        p->tk_chain.push_back(chain);
+        if (++fill == FILL_SLOTS) fill = 0;
+      };
+      auto close_task = [&]() {
+        while (fill > 0) push_slot(-1, 0, 0);
+      };
+      for (size_t k = cut[r]; k < cut[r + 1]; ++k) {
+        const int32_t pb = it_pair[k], st = p->it_strip[k];
+        const int32_t ns = (p->n[pb] + 63) / 64;
+        if (st % FILL_SLOTS != 0) continue;   // placed with strip st - st % FILL_SLOTS
+        const int cnt = std::min(FILL_SLOTS, ns - st);
+        if (fill + cnt > FILL_SLOTS) close_task();
+        for (int q = 0; q < cnt; ++q)
+          push_slot(pb, (st + q) | (q > 0 ? ITEM_LINK_IN : 0) | (q + 1 < cnt ? ITEM_LINK_OUT : 0), p->it_chain[k]);
+      }
+      close_task();
+      if (r == 0) p->n_tasks_top = (int)(tk_pair.size() / FILL_SLOTS);
+      if (r == 1) p->n_tasks_long = (int)(tk_pair.size() / FILL_SLOTS);
+    }
+  }
+  std::vector<int32_t> tk_words;
+  hot_flags(p, it_strip, tk_words);
   // ---- device metadata: one allocation -----------------------------------------
   struct Piece {
     const void *src;
@@ -513,6 +552,7 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   size_t i_do = add(order.data(), 4 * order.size());
   size_t i_si = add(sent_ids.data(), 8 * sent_ids.size());
   size_t i_ip = add(it_pair.data(), 4 * it_pair.size()), i_is = add(it_strip.data(), 4 * it_strip.size());
+  size_t i_tp = add(tk_pair.data(), 4 * tk_pair.size()), i_ts = add(tk_words.data(), 4 * tk_words.size());
   size_t i_bo = add(bnd_off.data(), 8 * (size_t)(B + 1));
   if (hipSetDevice(ctx->device) != hipSuccess) {
     delete p;
@@ -563,6 +603,9 @@ nwm_status nwm_plan_create(nwm_ctx *ctx, const nwm_batch *batch, int32_t max_deg
   D.n_items = (int)it_pair.size();
   D.it_pair = (const int32_t *)at(i_ip);
   D.it_strip = (const int32_t *)at(i_is);
+  D.n_tasks = (int)(tk_pair.size() / FILL_SLOTS);
+  D.tk_pair = (const int32_t *)at(i_tp);
+  D.tk_slot = (const int32_t *)at(i_ts);
   D.bnd_off = (const int64_t *)at(i_bo);
   D.path_base = (int64_t)align_up((size_t)tb_off[B], 256);
   // ---- workspace layout ------------------------------------------------------------
@@ -947,10 +990,12 @@ nwm_status nwm_plan_set_param(nwm_plan *p, nwm_param param, int32_t value) {
   p->param[param] = value;
   ++p->param_version;
   if (param == NWM_PARAM_DP_HOT_PERCENT && !p->it_strip.empty()) {
-    std::vector<int32_t> words;
-    hot_flags(p, words);
+    std::vector<int32_t> words, tasks;
+    hot_flags(p, words, tasks);
     if (hipSetDevice(p->device) != hipSuccess ||
         hipMemcpy(const_cast<int32_t *>(p->dev.it_strip), words.data(), 4 * words.size(), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(const_cast<int32_t *>(p->dev.tk_slot), tasks.data(), 4 * tasks.size(), hipMemcpyHostToDevice) !=
             hipSuccess)
       return NWM_EDEVICE;
   }
@@ -1042,6 +1087,7 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
     if (e == hipSuccess) e = hipEventRecord(p->ev_a_rest, xs);
   };
   const int gtop = p->n_gt_top, itop = p->n_items_top, otop = p->n_pairs_top;
+  const int ttop = p->n_tasks_top, tl = p->n_tasks_long;
   const bool rest_after_top = ol > 0 && gtop > 0;
   if (!rest_after_top) rest_src();
   if (e == hipSuccess) e = launch_nw_reset(D, gap, score, bnd, p->n_bnd, ctl, st);
@@ -1065,8 +1111,8 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
     if (otop > 0) {
       if (e == hipSuccess) e = hipStreamWaitEvent(lane, p->ev_top, 0);
       if (e == hipSuccess)
-        e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl + 2, ctl + 1, 0, itop, wpc, spin, hold,
-                                 stg, lane);
+        e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl + 2, ctl + 1, 0, itop, 0, ttop, wpc, spin,
+                                 hold, stg, lane);
       if (e == hipSuccess) e = launch_nw_walk(D, tbc, score, path, n_diag, 0, otop, lane);
       if (e == hipSuccess) e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, 0, otop, lane);
       if (e == hipSuccess) e = hipEventRecord(p->ev_top_done, lane);
@@ -1074,8 +1120,8 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
     if (ol > otop) {
       if (e == hipSuccess) e = hipStreamWaitEvent(aux, p->ev_long, 0);
       if (e == hipSuccess)
-        e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl + 3, ctl + 1, itop, il - itop, wpc, spin,
-                                 hold, stg, aux);
+        e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl + 3, ctl + 1, itop, il - itop, ttop,
+                                 tl - ttop, wpc, spin, hold, stg, aux);
       if (e == hipSuccess) e = launch_nw_walk(D, tbc, score, path, n_diag, otop, ol - otop, aux);
       if (e == hipSuccess)
         e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, otop, ol - otop, aux);
@@ -1090,8 +1136,8 @@ static nwm_status mine_path(nwm_plan *p, const nwm_batch *batch, const nwm_dict 
   if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_b_rest, 0);
   if (e == hipSuccess && scored) e = score_tiles(p, batch, sc, S, S_raw, ws, gl, D.n_gt - gl, st);
   if (e == hipSuccess)
-    e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl, ctl + 1, il, D.n_items - il, wpc, spin, hold,
-                             stg, st);
+    e = launch_nw_fill_items(D, S, gap, score, tbc, bnd, p->n_bnd, ctl, ctl + 1, il, D.n_items - il, tl,
+                             D.n_tasks - tl, wpc, spin, hold, stg, st);
   if (e == hipSuccess) e = launch_nw_walk(D, tbc, score, path, n_diag, ol, p->B - ol, st);
   if (e == hipSuccess) e = launch_keep(D, S, threshold, path, n_diag, (int2 *)kept, n_kept, ol, p->B - ol, st);
   if (e == hipSuccess && ol > 0 && otop > 0) e = hipStreamWaitEvent(st, p->ev_top_done, 0);

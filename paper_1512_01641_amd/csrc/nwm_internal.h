@@ -42,6 +42,13 @@ constexpr int BND_PAD = 192;          // slack slots after each published bounda
 __host__ __device__ inline int64_t bnd_stride(int m) { return ((int64_t)m + BND_PAD + 1) & ~(int64_t)1; }
 constexpr int MAX_M = 1 << 22;           // target sentences per pair (a 64-row strip of S stays below 1 GiB)
 constexpr int32_t ITEM_HOT = 1 << 30;   // DP item flag: strip of a critical-chain pair
+// DP task slot flags (the LDS-ring fill runs four strips per workgroup): the
+// strip's top boundary comes from the slot before it through LDS, and its
+// last row goes to the slot after it through LDS
+constexpr int32_t ITEM_LINK_IN = 1 << 29;
+constexpr int32_t ITEM_LINK_OUT = 1 << 28;
+constexpr int32_t ITEM_STRIP = ITEM_LINK_OUT - 1;   // the strip index bits
+constexpr int FILL_SLOTS = 4;                        // strips (waves) per task of the LDS-ring fill
 // Steps a strip trails the strip above it (the 63-step skew of a 64-row
 // strip, a 16-step publish chunk, the two-chunk window prefetch and the
 // hand-off's memory round trip): the queue order spaces a pair's strips by it.
@@ -104,6 +111,9 @@ struct PlanDev {
   const int64_t *sent_ids;   // [sum n] source sentences, long pairs' first
   int n_items;
   const int32_t *it_pair, *it_strip;
+  // the same strips as tasks of FILL_SLOTS slots (pair -1: an empty slot)
+  int n_tasks;
+  const int32_t *tk_pair, *tk_slot;
   const int64_t *bnd_off;   // [B+1] offset of a pair's published boundary rows (uint64 units)
 };
 
