@@ -297,11 +297,16 @@ nwm_status nwm_union_kept(const nwm_plan *plan, const int32_t *kept_fwd, const i
  *                                 barrier; the same sums in the same order, so
  *                                 the results are identical.  Default 1.
  *   NWM_PARAM_FILL_STAGING        how the NW fill stages S: 0 = a two-group LDS
- *                                 ring filled by LDS-direct loads (64 rows x 32
- *                                 steps per group), 1 = 16 cells per lane in
- *                                 registers, two 16-step chunks ahead (no LDS:
- *                                 more waves per compute unit).  The same cells
- *                                 in the same order: identical results.
+ *                                 ring per wave filled by LDS-direct loads (64
+ *                                 rows x 64 steps per group), four waves per
+ *                                 workgroup sweeping four strips, consecutive
+ *                                 strips of a pair handing their boundary row
+ *                                 on through LDS; 2 = the same ring, one strip
+ *                                 per workgroup (every hand-off through
+ *                                 memory); 1 = 16 cells per lane in registers,
+ *                                 two 16-step chunks ahead (no LDS: more waves
+ *                                 per compute unit).  The same cells in the
+ *                                 same order: identical results.  Default 0.
  *   NWM_PARAM_EXPAND_FUSED        1 = the source-side merge and row-tile list
  *                                 build run as one kernel per row tile (merged
  *                                 rows stay on chip), for plans whose

@@ -22,9 +22,10 @@ SPACE = {
     "dp_hot_percent": [50, 0, 25, 75],
     # tile shape of the compacted contraction: K words per round (32 or 64)
     "score_kgroup": [1, 2],
-    # S staging tile of the NW fill: LDS ring of 64 x 64 cells, or 16 cells
-    # per lane in registers
-    "fill_staging": [0, 1],
+    # S staging of the NW fill: LDS ring of 64 x 64 cells per wave with four
+    # strips per workgroup (hand-offs in LDS), the same ring one strip per
+    # workgroup, or 16 cells per lane in registers
+    "fill_staging": [0, 2, 1],
     # source-side expansion: one fused kernel per row tile, or merge + list build
     "expand_fused": [1, 0],
 }

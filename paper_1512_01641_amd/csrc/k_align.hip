@@ -295,15 +295,17 @@ struct FillArgs {
   const int64_t *s_off, *tb_off, *bnd_off;
 };
 
-// LDS of the LDS-ring fill, per workgroup of FILL_SLOTS waves: each wave's S
+// LDS of the LDS-ring fill, per workgroup of SLOTS waves: each wave's S
 // ring and window buffers, then a link ring per pair of neighbouring waves
 // (the upper strip's last row, LINK_COLS columns, column j in slot
 // j % LINK_COLS), then the counters: [k] columns wave k has put into link k
-// (-1: it gave up), [FILL_SLOTS + k] columns wave k + 1 has taken from it,
-// [2 FILL_SLOTS] the task.
+// (-1: it gave up), [SLOTS + k] columns wave k + 1 has taken from it,
+// [2 SLOTS] the task.  SLOTS = 1: one strip per workgroup, no links.
 constexpr int FILL_WAVE_LDS = RING_GROUPS * GROUP_FLOATS * 4 + 2 * 32 * 8;
 constexpr int LINK_COLS = 512;
-constexpr int FILL_LDS = FILL_SLOTS * FILL_WAVE_LDS + (FILL_SLOTS - 1) * LINK_COLS * 4 + 4 * (2 * FILL_SLOTS + 1);
+constexpr int fill_lds_bytes(int slots) {
+  return slots * FILL_WAVE_LDS + (slots - 1) * LINK_COLS * 4 + 4 * (2 * slots + 1);
+}
 static_assert((LINK_COLS & (LINK_COLS - 1)) == 0 && LINK_COLS >= 256, "link ring");
 
 __global__ __launch_bounds__(256) void k_nw_reset(FillArgs A, uint4 *__restrict__ bnd16, int64_t n_bnd16,
@@ -321,21 +323,21 @@ __global__ __launch_bounds__(256) void k_nw_reset(FillArgs A, uint4 *__restrict_
   }
 }
 
-template <bool MAX3>
-__global__ __launch_bounds__(64 * FILL_SLOTS) void k_nw_fill(FillArgs A, const float *__restrict__ S, float g,
-                                                             float *__restrict__ score, char *__restrict__ tb,
-                                                             uint64_t *__restrict__ bnd, int32_t *__restrict__ head,
-                                                             int32_t *__restrict__ err) {
+template <bool MAX3, int SLOTS>
+__global__ __launch_bounds__(64 * SLOTS) void k_nw_fill(FillArgs A, const float *__restrict__ S, float g,
+                                                        float *__restrict__ score, char *__restrict__ tb,
+                                                        uint64_t *__restrict__ bnd, int32_t *__restrict__ head,
+                                                        int32_t *__restrict__ err) {
   constexpr uint32_t epoch = 1u;   // tag of a published value (the reset clears to 0)
-  extern __shared__ __align__(16) char fill_lds[];   // FILL_LDS bytes
+  extern __shared__ __align__(16) char fill_lds[];   // fill_lds_bytes(SLOTS) bytes
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float *ring = reinterpret_cast<float *>(fill_lds + wave * FILL_WAVE_LDS);
   uint64_t *winbufA = reinterpret_cast<uint64_t *>(fill_lds + wave * FILL_WAVE_LDS + RING_GROUPS * GROUP_FLOATS * 4);
   uint64_t *winbufB = winbufA + 32;   // boundary windows (LDS-direct loads)
-  float *links = reinterpret_cast<float *>(fill_lds + FILL_SLOTS * FILL_WAVE_LDS);
-  int *ctr = reinterpret_cast<int *>(fill_lds + FILL_SLOTS * FILL_WAVE_LDS + (FILL_SLOTS - 1) * LINK_COLS * 4);
+  float *links = reinterpret_cast<float *>(fill_lds + SLOTS * FILL_WAVE_LDS);
+  int *ctr = reinterpret_cast<int *>(fill_lds + SLOTS * FILL_WAVE_LDS + (SLOTS - 1) * LINK_COLS * 4);
   float *link_in = links + (wave - 1) * LINK_COLS;   // from the wave above (wave > 0)
-  float *link_out = links + wave * LINK_COLS;        // to the wave below (wave < FILL_SLOTS - 1)
+  float *link_out = links + wave * LINK_COLS;        // to the wave below (wave < SLOTS - 1)
   // this lane's ring offsets of the four 16-byte chunks of each 16 steps of
   // a group
   uint32_t off[4][4];
@@ -343,18 +345,18 @@ __global__ __launch_bounds__(64 * FILL_SLOTS) void k_nw_fill(FillArgs A, const f
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int c = 0; c < 4; ++c) off[i][c] = chunk_off(lane, 4 * i + c);
-  // One task (FILL_SLOTS strips, one per wave) at a time: the whole
+  // One task (SLOTS strips, one per wave) at a time: the whole
   // workgroup takes the next task once every wave is done with the last one,
   // so the link rings and counters start clear.  Every wave passes both
   // barriers of every task and leaves the loop at the same task.
   for (;;) {
     __syncthreads();
-    if (threadIdx.x < 2 * FILL_SLOTS) ctr[threadIdx.x] = 0;
-    if (threadIdx.x == 0) ctr[2 * FILL_SLOTS] = atomicAdd(head, 1);
+    if (threadIdx.x < 2 * SLOTS) ctr[threadIdx.x] = 0;
+    if (threadIdx.x == 0) ctr[2 * SLOTS] = atomicAdd(head, 1);
     __syncthreads();
-    const int task = uniform(ctr[2 * FILL_SLOTS]);
+    const int task = uniform(ctr[2 * SLOTS]);
     if (task >= A.n_tasks) break;
-    const int ts = (A.task0 + task) * FILL_SLOTS + wave;   // this wave's task slot
+    const int ts = (A.task0 + task) * SLOTS + wave;   // this wave's task slot
     const int b = uniform(A.tk_pair[ts]);
     if (b < 0) continue;   // an empty slot
     const int s_tag = uniform(A.tk_slot[ts]);
@@ -491,7 +493,7 @@ __global__ __launch_bounds__(64 * FILL_SLOTS) void k_nw_fill(FillArgs A, const f
       const float v = link_in[(tw + 1 + (lane & 15)) & (LINK_COLS - 1)];
       asm volatile("" ::: "memory");
       if (lane == 0)
-        __hip_atomic_store(&ctr[FILL_SLOTS + wave - 1], tw + 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_store(&ctr[SLOTS + wave - 1], tw + 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       return ((uint64_t)epoch << 32) | __float_as_uint(v);
     };
     // the columns of the strip's last row finished in the chunk at t0 (lanes
@@ -500,7 +502,7 @@ __global__ __launch_bounds__(64 * FILL_SLOTS) void k_nw_fill(FillArgs A, const f
     auto link_put = [&](int t0) {
       const int jhi = min(t0 - 47, m);
       if (jhi < 1 || (A.hold && s == 0)) return;
-      if (!link_wait(&ctr[FILL_SLOTS + wave], jhi - LINK_COLS, down_taken)) {
+      if (!link_wait(&ctr[SLOTS + wave], jhi - LINK_COLS, down_taken)) {
         failed = true;
         return;
       }
@@ -929,29 +931,41 @@ __global__ __launch_bounds__(64) void k_keep(PlanDev P, const float *__restrict_
 }
 
 // compute units; resident fill workgroups per unit for the LDS-ring fill
-// (FILL_SLOTS waves each) and resident waves for the register staging
-static int g_fill_cus = 0, g_fill_per = 0, g_fill_per_r = 0;
+// with tasks of FILL_SLOTS strips and with single strips, and resident waves
+// for the register staging
+static int g_fill_cus = 0, g_fill_per = 0, g_fill_per1 = 0, g_fill_per_r = 0;
+
+template <int SLOTS>
+static hipError_t fill_ring_attrs(int &per) {
+  int a = 0, c = 0;
+  hipError_t e = hipFuncSetAttribute((const void *)k_nw_fill<false, SLOTS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     fill_lds_bytes(SLOTS));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_nw_fill<true, SLOTS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            fill_lds_bytes(SLOTS));
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_nw_fill<false, SLOTS>, 64 * SLOTS, fill_lds_bytes(SLOTS));
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_nw_fill<true, SLOTS>, 64 * SLOTS, fill_lds_bytes(SLOTS));
+  per = a < c ? a : c;   // either variant's grid is resident at once
+  if (per < 1) per = 1;
+  return e;
+}
 
 hipError_t fill_set_attrs(int) {
   if (g_fill_cus == 0) {
-    int dev = 0, cus = 0, per = 0, per3 = 0, pr = 0, pr3 = 0;
+    int dev = 0, cus = 0, per = 0, per1 = 0, pr = 0, pr3 = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    // the LDS-ring fill takes more than the default 64 KiB of LDS per workgroup
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void *)k_nw_fill<false>, hipFuncAttributeMaxDynamicSharedMemorySize, FILL_LDS);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void *)k_nw_fill<true>, hipFuncAttributeMaxDynamicSharedMemorySize, FILL_LDS);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_nw_fill<false>, 64 * FILL_SLOTS, FILL_LDS);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per3, k_nw_fill<true>, 64 * FILL_SLOTS, FILL_LDS);
+    // the four-strip fill takes more than the default 64 KiB of LDS per workgroup
+    if (e == hipSuccess) e = fill_ring_attrs<FILL_SLOTS>(per);
+    if (e == hipSuccess) e = fill_ring_attrs<1>(per1);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pr, k_nw_fill_r<false>, 64, 0);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pr3, k_nw_fill_r<true>, 64, 0);
     if (e != hipSuccess) return e;
-    per = per < per3 ? per : per3;   // either variant's grid is resident at once
-    pr = pr < pr3 ? pr : pr3;
-    g_fill_per = per > 0 ? per : 1;
+    pr = pr < pr3 ? pr : pr3;   // either variant's grid is resident at once
+    g_fill_per = per;
+    g_fill_per1 = per1;
     g_fill_per_r = pr > 0 ? pr : 1;
     g_fill_cus = cus > 0 ? cus : 1;
   }
@@ -1011,30 +1025,41 @@ hipError_t launch_nw_fill_items(const PlanDev &P, const float *S, float g, float
   A.hold = hold;
   // every wave of the grid is resident at once (the hand-off between strips
   // waits on other waves), so the grid never exceeds the occupancy; for the
-  // LDS ring, waves_per_cu counts the waves of whole workgroups
-  int grid;
-  if (staging) {
+  // LDS ring, waves_per_cu counts the waves of whole workgroups.  Staging 0:
+  // LDS ring, tasks of FILL_SLOTS strips; 2: LDS ring, one strip per
+  // workgroup (the plan's items as tasks of one); 1: registers.
+  const bool max3 = !(g == 0.0f && std::signbit(g));   // a gap of -0 keeps the compare chain (see run16v)
+  if (staging == 1) {
     const int per = (waves_per_cu > 0 && waves_per_cu < g_fill_per_r) ? waves_per_cu : g_fill_per_r;
-    grid = std::min(n, g_fill_cus * per);
-  } else {
-    int groups = g_fill_cus * g_fill_per;
-    if (waves_per_cu > 0) groups = std::min(groups, std::max(1, g_fill_cus * waves_per_cu / FILL_SLOTS));
-    grid = std::min(nt, groups);
-  }
-  // a gap of -0 keeps the compare chain (see run16v)
-  const bool max3 = !(g == 0.0f && std::signbit(g));
-  if (staging) {
+    const int grid = std::min(n, g_fill_cus * per);
     if (max3)
       hipLaunchKernelGGL(k_nw_fill_r<true>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, head, err);
     else
       hipLaunchKernelGGL(k_nw_fill_r<false>, dim3(grid), dim3(64), 0, st, A, S, g, score, tb, bnd, head, err);
-  } else {
+  } else if (staging == 2) {
+    A.tk_pair = P.it_pair;
+    A.tk_slot = P.it_strip;
+    A.task0 = item0;
+    A.n_tasks = n;
+    int per = g_fill_per1;
+    if (waves_per_cu > 0 && waves_per_cu < per) per = waves_per_cu;
+    const int grid = std::min(n, g_fill_cus * per);
+    constexpr int lds = fill_lds_bytes(1);
     if (max3)
-      hipLaunchKernelGGL(k_nw_fill<true>, dim3(grid), dim3(64 * FILL_SLOTS), FILL_LDS, st, A, S, g, score, tb, bnd,
-                         head, err);
+      hipLaunchKernelGGL((k_nw_fill<true, 1>), dim3(grid), dim3(64), lds, st, A, S, g, score, tb, bnd, head, err);
     else
-      hipLaunchKernelGGL(k_nw_fill<false>, dim3(grid), dim3(64 * FILL_SLOTS), FILL_LDS, st, A, S, g, score, tb, bnd,
-                         head, err);
+      hipLaunchKernelGGL((k_nw_fill<false, 1>), dim3(grid), dim3(64), lds, st, A, S, g, score, tb, bnd, head, err);
+  } else {
+    int groups = g_fill_cus * g_fill_per;
+    if (waves_per_cu > 0) groups = std::min(groups, std::max(1, g_fill_cus * waves_per_cu / FILL_SLOTS));
+    const int grid = std::min(nt, groups);
+    constexpr int lds = fill_lds_bytes(FILL_SLOTS);
+    if (max3)
+      hipLaunchKernelGGL((k_nw_fill<true, FILL_SLOTS>), dim3(grid), dim3(64 * FILL_SLOTS), lds, st, A, S, g, score, tb,
+                         bnd, head, err);
+    else
+      hipLaunchKernelGGL((k_nw_fill<false, FILL_SLOTS>), dim3(grid), dim3(64 * FILL_SLOTS), lds, st, A, S, g, score,
+                         tb, bnd, head, err);
   }
   return hipGetLastError();
 }

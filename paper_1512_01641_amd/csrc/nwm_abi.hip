@@ -980,6 +980,8 @@ nwm_status nwm_plan_set_param(nwm_plan *p, nwm_param param, int32_t value) {
       if (value != 1 && value != 2) return NWM_EINVAL;
       break;
     case NWM_PARAM_FILL_STAGING:
+      if (value < 0 || value > 2) return NWM_EINVAL;
+      break;
     case NWM_PARAM_EXPAND_FUSED:
       if (value != 0 && value != 1) return NWM_EINVAL;
       break;

@@ -97,9 +97,12 @@ def test_dp_empty_sides():
 
 
 @pytest.mark.parametrize("g", [-0.2, -0.0])
-def test_dp_register_staging_bitexact(g):
-    # the fill with S staged in registers: brute-force sizes, ragged strips
-    # with exact ties, empty sides and tall pairs (hand-offs), bit-exact
+@pytest.mark.parametrize("staging", [1, 2])
+def test_dp_register_staging_bitexact(g, staging):
+    # the fill's other S stagings (1: registers, 2: the LDS ring one strip
+    # per workgroup, every hand-off through memory): brute-force sizes,
+    # ragged strips with exact ties, empty sides and tall pairs (hand-offs),
+    # bit-exact
     rng = np.random.default_rng(7)
     sizes = [(0, 4), (5, 0), (1, 1), (3, 6), (6, 3), (1, 300), (300, 1), (63, 64), (64, 63), (65, 65), (127, 33),
              (129, 31), (200, 220), (2, 500), (500, 2), (700, 650), (1300, 90)]
@@ -111,7 +114,7 @@ def test_dp_register_staging_bitexact(g):
         else:
             blocks = [rng.random(n * m).astype(np.float32) for n, m in sizes]
         S = np.concatenate(blocks)
-        gpu = H.gpu_align_only(ns, ms, S, g, 0.5, params={"fill_staging": 1})
+        gpu = H.gpu_align_only(ns, ms, S, g, 0.5, params={"fill_staging": staging})
         ora = oracle.align(ns, ms, S, g, 0.5)
         H.assert_align_equal(gpu, ora, ns, ms)
 
