@@ -752,17 +752,24 @@ __global__ __launch_bounds__(64) void k_nw_fill_r(FillArgs A, const float *__res
   }
 }
 
-constexpr int WALK_LDS = 4096;   // path cells buffered in LDS per pair before a flush
+constexpr int WALK_LDS = 2048;   // path cells buffered in LDS per pair before a flush
 
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-// A block load the compiler does not track: the walk waits for it itself
-// (below), at the next block change, and keeps the destination live until
-// then, so no step between two block changes waits on memory.
-static __device__ __forceinline__ u32x4 load_block_async(const uint4 *p) {
-  u32x4 v;
-  asm volatile("global_load_dwordx4 %0, %1, off" : "=v"(v) : "v"(p) : "memory");
-  return v;
+// One 1 KiB block of direction words into LDS (lane l: bytes 16 l .. 16 l +
+// 15 of blk), LDS-direct so that no register is written while the load is in
+// flight (the compiler takes an asm load's outputs as written at issue and
+// may copy them).  Readers wait with an explicit vmcnt.
+static __device__ __forceinline__ void load_block_lds(uint4 *blk, const uint4 *src) {
+  const uint32_t la = (uint32_t)uniform((int)(uint32_t)(uintptr_t)(lds_void *)blk);
+  uint32_t save;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %1\n\t"
+      "s_nop 0\n\t"
+      "global_load_lds_dwordx4 %2, off\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(save)
+      : "s"(la), "v"(src)
+      : "memory");
 }
 
 // The 2-bit code at position p (0..63) of a block row held as four words of
@@ -773,25 +780,46 @@ static __device__ __forceinline__ uint32_t code_at(uint32_t w0, uint32_t w1, uin
   return (w >> (2 * (15 - (p & 15)))) & 3u;
 }
 
+// The 16 flags at even bit positions 2 m of x (bits 2 m + 1 ignored) packed
+// into bits m.
+static __device__ __forceinline__ uint32_t pack_even(uint32_t x) {
+  x &= 0x55555555u;
+  x = (x | (x >> 1)) & 0x33333333u;
+  x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+  x = (x | (x >> 4)) & 0x00FF00FFu;
+  return (x | (x >> 8)) & 0x0000FFFFu;
+}
+
 // Traceback (Sec. 5.1): from (n, m) back to the first row or column,
 // following the stored directions; every DIAG step emits the aligned pair.
 // One wave per pair (longest pair first).  Position: strip s, row r of the
 // strip (lane r), anti-diagonal step t = j - 1 + r; the walk holds the 1 KiB
 // block of codes covering steps [64 G, 64 G + 64) of the strip (lane l: row
-// l's four words).  It moves by runs: at a cell whose code is DIAG or UP,
-// every lane evaluates the code on the line the path follows (rows below r,
-// steps t - 2 (r - row) or t - (r - row)), a ballot finds the first row where
-// the code differs or the block ends, and the whole run is one iteration; a
-// LEFT run is found the same way along the row.  The cells of a DIAG run are
-// written to LDS by their lanes at once.  On entering a block the walk
-// prefetches the three blocks it can enter next (the previous block of the
-// strip, the block above and the one above-right in the strip above), loads
-// it waits for itself at the next block change.  Path cells reach memory in
-// coalesced stores.
+// l's four words), and each lane turns its row into two 64-bit masks, bit
+// 63 - p for step 64 G + p: codes other than LEFT, and DIAG codes.  The walk
+// then moves by runs: from step t of row r the path goes LEFT up to the
+// first code that is not LEFT at or before t (the lowest set bit of the
+// row's mask above bit 63 - (t - 64 G), found on the scalar unit) and leaves
+// the row there by DIAG (step - 2) or UP (step - 1); every lane below tests
+// its row's code where that move enters it, and a ballot finds the first row
+// where the run of the same move ends, so a LEFT run and the DIAG or UP run
+// after it are one iteration.  The DIAG cells are recorded per lane (one per
+// row and strip) and written to LDS together, in path order, when the walk
+// leaves the strip.  The walk is bound by the latency
+// of its steps, and of its block loads, so each strip's blocks are
+// requested a whole strip ahead: the wave holds four blocks of its strip in
+// LDS and, on entering a strip, requests the four blocks of the strip above
+// that the path will cross if it keeps the pair's average slope (m / n
+// columns per row; within a strip the step only decreases, by one block at
+// a time).  A block outside those four is loaded when it is reached, and
+// from then on the block to its left is prefetched.  Path cells reach memory
+// in coalesced stores.
 __global__ __launch_bounds__(64) void k_nw_walk(PlanDev P, const char *__restrict__ tb_bits,
                                                 const float *__restrict__ score, int2 *__restrict__ path,
                                                 int32_t *__restrict__ n_diag, int o0) {
   __shared__ int2 lbuf[WALK_LDS];
+  // two sets of four blocks (slots 4 k .. 4 k + 3), then the block on the left
+  __shared__ uint4 wblk[9 * 64];
   const int b = P.dp_order[o0 + blockIdx.x];
   const int n = P.n[b], m = P.m[b];
   const int lane = threadIdx.x;
@@ -813,12 +841,20 @@ __global__ __launch_bounds__(64) void k_nw_walk(PlanDev P, const char *__restric
   // position: strip s, row r, step t  (i = 64 s + r + 1, j = t - r + 1)
   int s = (n - 1) >> 6, r = (n - 1) & 63, t = m - 1 + r;
   int k = 0, kb = 0, flushed = 0;   // cells emitted; cells in lbuf; cells stored
+  // set hs holds blocks ob .. ob + 3 of strip cs; the other set blocks
+  // ab .. ab + 3 of strip cs - 1 (in flight until the strip changes); slot 8
+  // block cG - 1 of strip cs, in flight while pa_live
   int cs = s, cG = t >> 6;
-  u32x4 cur = load_block_async(blk_ptr(cs, cG));
-  u32x4 pA = load_block_async(blk_ptr(cs, cG - 1));
-  u32x4 pB = load_block_async(blk_ptr(cs - 1, cG));
-  u32x4 pC = load_block_async(blk_ptr(cs - 1, cG + 1));
-  asm volatile("s_waitcnt vmcnt(3)" : "+v"(cur));
+  // the entry step of the strip above, relative to this strip's, for a path
+  // of the average slope: one row up (+64 steps) after 64 rows of slope m / n
+  const int d = 1 - (int)(((int64_t)64 * m) / n);
+  auto load_slot = [&](int slot, int bs, int bG) { load_block_lds(&wblk[slot * 64], blk_ptr(bs, bG)); };
+  // the four blocks ending with the one 32 steps right of the predicted entry
+  auto above_base = [&](int t_in) { return ((t_in + d + 32) >> 6) - 3; };
+  int hs = 0, ob = cG - 3, ab = above_base(t);
+  for (int q = 0; q < 4; ++q) load_slot(q, cs, ob + q);
+  for (int q = 0; q < 4; ++q) load_slot(4 + q, cs - 1, ab + q);
+  asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
   auto flush = [&]() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -831,74 +867,112 @@ __global__ __launch_bounds__(64) void k_nw_walk(PlanDev P, const char *__restric
     flushed += kb;
     kb = 0;
   };
+  bool pa_live = false;
+  // this lane's row of the current block as masks (bit 63 - p: step 64 G + p):
+  // codes other than LEFT, DIAG codes, the other codes (UP)
+  uint64_t nl = 0ull, dg = 0ull, up = 0ull;
+  auto row_masks = [&](const uint4 &w) {
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+    nl = 0ull;
+    dg = 0ull;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      // code at position k of word q in bits 2 (15 - k) + 1 .. 2 (15 - k):
+      // DIAG 0, UP 1, LEFT 2
+      const uint32_t hi = ws[q] >> 1, lo = ws[q];
+      nl |= (uint64_t)pack_even(~hi | lo) << (16 * (3 - q));
+      dg |= (uint64_t)pack_even(~(hi | lo)) << (16 * (3 - q));
+    }
+    up = nl & ~dg;
+  };
+  row_masks(wblk[3 * 64 + lane]);
+  int cell = -1;   // this lane's row: the step of its DIAG cell in the current strip
+  // the current strip's DIAG cells to LDS, rows in descending order
+  auto emit = [&]() {
+    const uint64_t has = __ballot(cell >= 0);
+    if (has == 0ull) return;
+    const int nc = __popcll(has);
+    if (kb + nc > WALK_LDS) flush();
+    if (cell >= 0) lbuf[kb + __popcll(lane == 63 ? 0ull : has >> (lane + 1))] = make_int2(64 * s + lane, cell - lane);
+    kb += nc;
+    k += nc;
+    cell = -1;
+  };
   for (;;) {
     if (r < 0) {   // into the strip above
+      emit();
       --s;
       r += 64;
       t += 64;
     }
     if (s < 0 || t - r < 0) break;   // i == 0 or j == 0
     const int G = t >> 6;
-    if (s != cs || G != cG) {
-      // the three prefetches (one block old) must have landed before any of
-      // their registers can be reused; the compiler does not track them
-      asm volatile("s_waitcnt vmcnt(0)" : "+v"(pA), "+v"(pB), "+v"(pC));
-      if (s == cs && G == cG - 1) {
-        cur = pA;
-      } else if (s == cs - 1 && G == cG) {
-        cur = pB;
-      } else if (s == cs - 1 && G == cG + 1) {
-        cur = pC;
-      } else {
-        cur = load_block_async(blk_ptr(s, G));
-        asm volatile("s_waitcnt vmcnt(0)" : "+v"(cur));
-      }
+    if (s != cs) {
+      // into the strip above (s = cs - 1): its blocks, requested a strip
+      // ago, become the held set, and the set just left (read for the last
+      // time at an earlier block change) takes the strip above this one
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      hs ^= 1;
+      ob = ab;
       cs = s;
+      cG = G + 1;   // select below
+      pa_live = false;
+      ab = above_base(t);
+      for (int q = 0; q < 4; ++q) load_slot(4 * (hs ^ 1) + q, cs - 1, ab + q);
+    }
+    if (G != cG) {
+      // within a strip the walk only moves to the block on the left
+      const int x = G - ob;
+      int slot = 8;
+      if (x >= 0 && x < 4) {
+        slot = 4 * hs + x;
+      } else if (pa_live && G == cG - 1) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      } else {
+        load_slot(8, s, G);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      }
+      row_masks(wblk[slot * 64 + lane]);
+      pa_live = false;
       cG = G;
-      pA = load_block_async(blk_ptr(cs, cG - 1));
-      pB = load_block_async(blk_ptr(cs - 1, cG));
-      pC = load_block_async(blk_ptr(cs - 1, cG + 1));
+      if (G - 1 < ob && G >= 1) {   // past the held blocks: prefetch the next one to the left
+        __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): slot 8 has been read before it is refilled
+        load_slot(8, s, G - 1);
+        pa_live = true;
+      }
     }
     const int base = 64 * G;
-    // code of the current cell: row r's word of step t
-    const uint32_t c0 = code_at((uint32_t)__builtin_amdgcn_readlane((int)cur.x, r),
-                                (uint32_t)__builtin_amdgcn_readlane((int)cur.y, r),
-                                (uint32_t)__builtin_amdgcn_readlane((int)cur.z, r),
-                                (uint32_t)__builtin_amdgcn_readlane((int)cur.w, r), t - base);
-    if (c0 == DIR_LEFT) {
-      // lane q: step t - q of row r
-      const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)cur.x, r);
-      const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)cur.y, r);
-      const uint32_t w2 = (uint32_t)__builtin_amdgcn_readlane((int)cur.z, r);
-      const uint32_t w3 = (uint32_t)__builtin_amdgcn_readlane((int)cur.w, r);
-      const int tq = t - lane;
-      const bool ok = tq >= base && tq - r >= 0 && code_at(w0, w1, w2, w3, max(tq - base, 0)) == DIR_LEFT;
-      const uint64_t brk = __ballot(!ok);
-      const int L = brk ? __builtin_ctzll(brk) : 64;   // >= 1: lane 0 is the current cell
-      t -= L;
-    } else {
-      // DIAG (slope 2) or UP (slope 1): lane rho <= r, step t - slope (r - rho)
-      const int slope = c0 == DIR_DIAG ? 2 : 1;
-      const int tr = t - slope * (r - lane);
-      const bool ok = lane <= r && tr >= base && tr - lane >= 0 &&
-                      code_at(cur.x, cur.y, cur.z, cur.w, max(tr - base, 0)) == c0;
-      const uint64_t below = r >= 63 ? ~0ull : ((2ull << r) - 1ull);   // rows 0..r
-      const uint64_t brk = __ballot(!ok) & below;
-      const int rs = brk ? 63 - __builtin_clzll(brk) : -1;   // highest breaking row (< r)
-      const int L = r - rs;
-      if (c0 == DIR_DIAG) {
-        if (kb + L > WALK_LDS) flush();
-        // rows rs+1 .. r emit cells k .. k+L-1 (row r first)
-        if (lane > rs && lane <= r) lbuf[kb + (r - lane)] = make_int2(64 * s + lane, tr - lane);
-        kb += L;
-        k += L;
-      }
-      r -= L;
-      t -= slope * L;
+    const uint64_t nlr = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(nl >> 32), r) << 32) |
+                         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)nl, r);
+    const uint64_t dgr = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(dg >> 32), r) << 32) |
+                         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)dg, r);
+    const uint64_t x = nlr & (~0ull << (63 - (t - base)));
+    if (x == 0ull) {   // LEFT past the block's first step: on in block G - 1
+      t = base - 1;
+      continue;
     }
+    const int bb = __builtin_ctzll(x);
+    const int tp = base + 63 - bb;   // the step where the path leaves row r
+    if (tp < r) break;               // the LEFT run reaches column 0 first
+    const bool diag = (dgr >> bb) & 1ull;
+    // the run of DIAG (or UP) moves from tp: row rho < r is entered at step
+    // tp - slope (r - rho) and continues the run if its code there is the
+    // same; the first row (from r down) where it is not, or where the step
+    // leaves the block or column 1, is where the next iteration starts
+    const int slope = diag ? 2 : 1;
+    const int tq = tp - slope * (r - lane);
+    const int pq = tq - base;
+    const uint64_t same = diag ? dg : up;
+    const bool ok = lane < r && pq >= 0 && tq >= lane && ((same >> ((63 - pq) & 63)) & 1ull);
+    const uint64_t brk = __ballot(!ok) & ((1ull << r) - 1ull);
+    const int rs = brk ? 63 - __builtin_clzll(brk) : -1;   // highest breaking row below r
+    if (diag && lane > rs && lane <= r) cell = tq;
+    t = tp - slope * (r - rs);
+    r = rs;
   }
-  // drain the prefetches before the wave ends
-  asm volatile("s_waitcnt vmcnt(0)" : "+v"(pA), "+v"(pB), "+v"(pC));
+  emit();
+  // no LDS-direct load may still be writing LDS when the wave ends
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   flush();
   if (lane == 0) n_diag[b] = k;
 }
