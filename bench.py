@@ -221,13 +221,15 @@ def plain(nw, torch, ctx, batch, idx, dd):
     return ms
 
 
-def summarize(batch, res, prec_name):
+def summarize(batch, res, prec_name, counted):
+    """`counted`: the committed counter traffic was taken on this workload
+    (the full 4096-pair one); elsewhere traffic is null."""
     model, cells, n_kc = work_model(batch)
     rl = rooflines(model, res["kernel"], prec_name)
     for k, r in rl.items():
         name = KERNEL_NAMES[k] % prec_name if "%" in KERNEL_NAMES[k] else KERNEL_NAMES[k]
         r["kernel"] = name
-        r["traffic"] = profiled_traffic(name)
+        r["traffic"] = profiled_traffic(name) if counted else None
     dom = max(rl, key=lambda k: rl[k]["kernel_ms"])
     fill = res["kernel"].get("nw_fill")
     return dict(pairs_per_s=round(batch.B / (res["ms"] / 1000.0), 2), ms_per_step=round(res["ms"], 4),
@@ -393,7 +395,7 @@ def main():
         runs[prec_name] = batched(nw, torch, ctx, batch, prec_name, prec, args, db, dd)
         if prec_name != head:
             runs[prec_name].pop("miner")
-    head_sum = summarize(batch, runs[head], head)
+    head_sum = summarize(batch, runs[head], head, counted=cfg == 2 and args.pairs is None)
 
     bidir = None
     if not args.no_bidir:
@@ -462,7 +464,7 @@ def main():
             xa.steps, xa.warmup = args.extra_steps, 1
             r = batched(nw, torch, ctx, xb, "bf16", nw.NWM_BF16, xa, dd=xd)
             r.pop("miner")
-            s = summarize(xb, r, "bf16")
+            s = summarize(xb, r, "bf16", counted=False)
             s.update(pairs=xb.B, cells=xb.cells(), V=xb.V, workload=WORKLOADS[xc] % (xb.B, xb.V, "BF16"))
             if xc == 5 and not args.no_plain:
                 rng = np.random.default_rng(1512)
