@@ -55,7 +55,7 @@ constexpr int FILL_SLOTS = 4;                        // strips (waves) per task 
 constexpr int STRIP_LAG = 128;
 // Pairs whose DP dependency chain is at least this percent of the longest are
 // the "long" pairs: prepared, scored and aligned ahead of the others.
-constexpr int LONG_CHAIN_PERCENT = 15;
+constexpr int LONG_CHAIN_PERCENT = 10;
 // Of those, the pairs whose chain is at least this percent of the longest are
 // the "top" pairs: scored first, their DP started as soon as their own tiles
 // are scored.
