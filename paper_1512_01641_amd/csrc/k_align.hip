@@ -989,17 +989,29 @@ __global__ __launch_bounds__(64) void k_keep(PlanDev P, const float *__restrict_
   int2 *kp = kept + P.p_off[b];
   const float *Sb = S + P.s_off[b];
   int nk = 0;
-  for (int q0 = 0; q0 < k; q0 += 64) {
-    const int q = q0 + lane;
-    int2 c = make_int2(0, 0);
-    bool keep = false;
-    if (q < k) {
-      c = pa[q];
-      keep = Sb[(int64_t)c.x * m + c.y] >= thr;
+  // 256 path cells per round: the four path loads, then the four S loads
+  // that depend on them, are each in flight together
+  constexpr int U = 4;
+  for (int q0 = 0; q0 < k; q0 += 64 * U) {
+    int2 c[U];
+    float sv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + 64 * u + lane;
+      c[u] = q < k ? pa[q] : make_int2(0, 0);
     }
-    const uint64_t km = __ballot(keep);
-    if (keep) kp[nk + __popcll(km & ((1ull << lane) - 1ull))] = c;
-    nk += __popcll(km);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + 64 * u + lane;
+      sv[u] = q < k ? Sb[(int64_t)c[u].x * m + c[u].y] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool keep = q0 + 64 * u + lane < k && sv[u] >= thr;
+      const uint64_t km = __ballot(keep);
+      if (keep) kp[nk + __popcll(km & ((1ull << lane) - 1ull))] = c[u];
+      nk += __popcll(km);
+    }
   }
   if (lane == 0) n_kept[b] = nk;
 }
